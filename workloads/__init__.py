@@ -1,0 +1,329 @@
+"""Seeded synthetic inputs for the adjoint lattice Boltzmann hot path.
+
+This module is shared by the tests, the benchmark and the scripts that write
+stored expected values.  It holds none of the method's arithmetic: it only
+builds node-type masks (which nodes are walls, ports, heated walls, design
+nodes, with the port/heater inward normal), smoothed random design fields and
+the scalar parameter sets of the workloads.  The paper runs on geometric
+set-ups only (pipe bends, a microchannel heat sink); there is no dataset, so
+these seeded fields stand in for its cases.
+
+Mask byte layout (the input format of the C ABI and of the oracle):
+  bits 0-2  node kind: DESIGN 0, FLUID 1, INLET 2, OUTLET 3, WALL 4, HEATED 5
+  bits 3-5  inward normal for INLET/OUTLET/HEATED: +x 0, -x 1, +y 2, -y 3, +z 4, -z 5
+  bits 6-7  zero
+Arrays are indexed [z][y][x] (x fastest); 2D problems have nz == 1.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Optional
+
+import numpy as np
+from scipy import ndimage
+
+DESIGN, FLUID, INLET, OUTLET, WALL, HEATED = 0, 1, 2, 3, 4, 5
+NPX, NMX, NPY, NMY, NPZ, NMZ = 0, 1, 2, 3, 4, 5
+
+OBJ_PRESSURE_DROP, OBJ_DISSIPATION, OBJ_HEATSINK = 0, 1, 2
+OBJECTIVE_NAMES = {OBJ_PRESSURE_DROP: "pressure_drop", OBJ_DISSIPATION: "dissipation",
+                   OBJ_HEATSINK: "heatsink"}
+
+SEED_BASE = 20250102
+
+
+def code(kind: int, normal: int = 0) -> int:
+    """Pack a node kind and an inward-normal code into one mask byte."""
+    return (kind & 7) | ((normal & 7) << 3)
+
+
+@dataclasses.dataclass
+class Workload:
+    """One synthetic problem: grid, physical parameters, mask and design field."""
+    name: str
+    dim: int
+    nx: int
+    ny: int
+    nz: int
+    thermal: bool
+    tau: float
+    Re: float
+    L_ref: float
+    objective: int
+    mask: np.ndarray                      # uint8 [nz, ny, nx]
+    gamma: np.ndarray                     # float64 [nz, ny, nx]
+    rho0: float = 1.0
+    alpha_max: float = 0.05
+    q_brink: float = 0.1
+    Pr: float = 6.0
+    k_ratio: float = 100.0
+    q_ramp: float = 1.0
+    q_w: float = 0.01
+    T_in: float = 0.0
+    w_dp: float = 1.0
+    periodic: tuple = (False, False, False)
+    max_steps: int = 20000
+    tol: float = 1e-7
+    check_every: int = 1000
+    seed: int = 0
+
+    @property
+    def N(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    def replace(self, **kw) -> "Workload":
+        return dataclasses.replace(self, **kw)
+
+
+def smoothed_noise(shape, sigma: float, seed: int) -> np.ndarray:
+    """Uniform [0,1) noise from PCG64(seed), Gaussian-smoothed (truncated at
+    4 sigma, reflecting edges), then min-max rescaled to [0, 1]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    a = rng.random(shape)
+    if sigma > 0:
+        a = ndimage.gaussian_filter(a, sigma=sigma, mode="reflect", truncate=4.0)
+    lo, hi = float(a.min()), float(a.max())
+    if hi > lo:
+        a = (a - lo) / (hi - lo)
+    return np.clip(a, 0.0, 1.0)
+
+
+def walled_box(nx: int, ny: int, nz: int, dim: int = 3,
+               periodic=(False, False, False), interior: int = DESIGN) -> np.ndarray:
+    """Mask with WALL on the outer layer of every non-periodic axis and
+    `interior` elsewhere."""
+    m = np.full((nz, ny, nx), interior, dtype=np.uint8)
+    if not periodic[0]:
+        m[:, :, 0] = WALL
+        m[:, :, -1] = WALL
+    if not periodic[1]:
+        m[:, 0, :] = WALL
+        m[:, -1, :] = WALL
+    if dim == 3 and not periodic[2]:
+        m[0, :, :] = WALL
+        m[-1, :, :] = WALL
+    return m
+
+
+# --------------------------------------------------------------------------
+# The workloads of the benchmark and of the parity tests
+# --------------------------------------------------------------------------
+
+def pipe_bend_2d(n: int = 64, tau: float = 0.6, Re: float = 10.0, sigma: float = 3.0,
+                 seed: Optional[int] = None, inlet=(8, 23), outlet=(40, 55),
+                 steps: int = 5000) -> Workload:
+    """2D pipe bend, flow only, D2Q9 on n x n: parabolic velocity inlet on the
+    left wall (x=0, rows inlet[0]..inlet[1]), pressure outlet on the bottom
+    wall (y=0, columns outlet[0]..outlet[1]), bounce-back elsewhere.  The
+    objective is the static pressure drop inlet-to-outlet; fixed step counts."""
+    seed = SEED_BASE + 0 if seed is None else seed
+    m = walled_box(n, n, 1, dim=2)
+    m[0, inlet[0]:inlet[1] + 1, 0] = code(INLET, NPX)
+    m[0, 0, outlet[0]:outlet[1] + 1] = code(OUTLET, NPY)
+    gamma = smoothed_noise((1, n, n), sigma, seed)
+    L = inlet[1] - inlet[0] + 1
+    return Workload(name=f"pipe_bend_2d_{n}x{n}", dim=2, nx=n, ny=n, nz=1, thermal=False,
+                    tau=tau, Re=Re, L_ref=float(L), objective=OBJ_PRESSURE_DROP, mask=m,
+                    gamma=gamma, alpha_max=0.1, q_brink=0.1, w_dp=1.0, max_steps=steps,
+                    tol=0.0, check_every=1000, seed=seed)
+
+
+def pipe_bend_3d(n: int = 96, tau: float = 0.55, Re: float = 100.0, sigma: float = 4.0,
+                 seed: Optional[int] = None, port: int = 16, objective: int = OBJ_DISSIPATION
+                 ) -> Workload:
+    """3D pipe bend, flow only, D3Q19 on n^3: a port x port square velocity
+    inlet on face x=0 (y and z in [n/12, n/12+port) and [5n/12, 5n/12+port)),
+    a square pressure outlet on face y=0 (x in [3n/4, 3n/4+port), same z
+    range), bounce-back elsewhere.  Objective: viscous dissipation."""
+    seed = SEED_BASE + 1 if seed is None else seed
+    m = walled_box(n, n, n)
+    y0 = max(1, round(n * 8 / 96))
+    z0 = max(1, round(n * 40 / 96))
+    x0 = max(1, round(n * 72 / 96))
+    p = min(port, n - 2 - max(y0, z0, x0) + 1)
+    m[z0:z0 + p, y0:y0 + p, 0] = code(INLET, NPX)
+    m[z0:z0 + p, 0, x0:x0 + p] = code(OUTLET, NPY)
+    gamma = smoothed_noise((n, n, n), sigma, seed)
+    return Workload(name=f"pipe_bend_3d_{n}^3", dim=3, nx=n, ny=n, nz=n, thermal=False,
+                    tau=tau, Re=Re, L_ref=float(p), objective=objective, mask=m, gamma=gamma,
+                    alpha_max=0.05, q_brink=0.1, seed=seed)
+
+
+def heat_sink(nx: int = 160, ny: int = 80, nz: int = 40, Re: float = 200.0,
+              Pr: float = 6.0, u_peak: float = 0.05, sigma: float = 5.0,
+              seed: Optional[int] = None, tau: Optional[float] = None,
+              name: Optional[str] = None) -> Workload:
+    """3D microchannel heat sink, coupled D3Q19 flow + D3Q7 heat: velocity
+    inlet over the whole interior of face x=0, pressure outlet over the whole
+    interior of face x=nx-1, uniform heat flux through the floor z=0, walls
+    elsewhere.  Conductivity ratio 100 by RAMP(q=1).  Objective: mean
+    temperature of the layer on the heated floor + 0.1 x pressure drop.
+
+    The relaxation time is not given for this case; unless `tau` is passed
+    the peak inlet speed is fixed to `u_peak` and tau follows from
+    Re = u_peak L / nu with L = nz - 2 (the channel height between the
+    midway walls)."""
+    seed = SEED_BASE + 2 if seed is None else seed
+    m = walled_box(nx, ny, nz)
+    m[1:nz - 1, 1:ny - 1, 0] = code(INLET, NPX)
+    m[1:nz - 1, 1:ny - 1, nx - 1] = code(OUTLET, NMX)
+    m[0, 1:ny - 1, 1:nx - 1] = code(HEATED, NPZ)
+    L = float(nz - 2)
+    if tau is None:
+        tau = 0.5 + 3.0 * u_peak * L / Re
+    gamma = smoothed_noise((nz, ny, nx), sigma, seed)
+    return Workload(name=name or f"heat_sink_{nx}x{ny}x{nz}_Re{Re:g}", dim=3, nx=nx, ny=ny,
+                    nz=nz, thermal=True, tau=tau, Re=Re, L_ref=L, objective=OBJ_HEATSINK,
+                    mask=m, gamma=gamma, alpha_max=0.05, q_brink=0.1, Pr=Pr, k_ratio=100.0,
+                    q_ramp=1.0, q_w=0.01, T_in=0.0, w_dp=0.1, seed=seed)
+
+
+def differentiable_case(seed: Optional[int] = None) -> Workload:
+    """The autograd workload: coupled heat sink on 128 x 64 x 32 at Re 200."""
+    seed = SEED_BASE + 3 if seed is None else seed
+    return heat_sink(128, 64, 32, Re=200.0, seed=seed, name="heat_sink_128x64x32_Re200")
+
+
+SERVING_GRIDS = ((64, 32, 16), (128, 64, 32), (192, 96, 48))
+
+
+def serving_request(i: int, base_seed: int = SEED_BASE + 4) -> Workload:
+    """Request i of the serving stream: grid uniform over SERVING_GRIDS, Re
+    uniform in [50, 400], tau uniform in [0.52, 0.8], own smoothed design
+    field.  Re and tau are drawn independently, so the peak inlet speed
+    Re nu / L is capped at 0.1 and the effective Re is recorded instead."""
+    rng = np.random.Generator(np.random.PCG64(base_seed * 1000 + i))
+    nx, ny, nz = SERVING_GRIDS[int(rng.integers(0, len(SERVING_GRIDS)))]
+    Re = float(rng.uniform(50.0, 400.0))
+    tau = float(rng.uniform(0.52, 0.8))
+    L = float(nz - 2)
+    nu = (tau - 0.5) / 3.0
+    u = min(Re * nu / L, 0.1)
+    Re_eff = u * L / nu
+    w = heat_sink(nx, ny, nz, Re=Re_eff, tau=tau, sigma=5.0, seed=base_seed * 1000 + i,
+                  name=f"req{i}_{nx}x{ny}x{nz}")
+    return w
+
+
+def poisson_arrivals(n: int, rate: float, seed: int = SEED_BASE + 5) -> np.ndarray:
+    """Arrival times (seconds) of n requests with exponential gaps at `rate`/s."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return np.cumsum(rng.exponential(1.0 / rate, size=n))
+
+
+# --------------------------------------------------------------------------
+# Small geometries for pins and parity tests
+# --------------------------------------------------------------------------
+
+def channel_2d(nx: int, ny: int, tau: float, u_peak: float) -> Workload:
+    """Straight 2D channel (D2Q9): walls at y=0 and y=ny-1, parabolic velocity
+    inlet on x=0, pressure outlet on x=nx-1, fluid (non-design) inside."""
+    m = walled_box(nx, ny, 1, dim=2, interior=FLUID)
+    m[0, 1:ny - 1, 0] = code(INLET, NPX)
+    m[0, 1:ny - 1, nx - 1] = code(OUTLET, NMX)
+    L = float(ny - 2)
+    nu = (tau - 0.5) / 3.0
+    return Workload(name=f"channel_2d_{nx}x{ny}", dim=2, nx=nx, ny=ny, nz=1, thermal=False,
+                    tau=tau, Re=u_peak * L / nu, L_ref=L, objective=OBJ_PRESSURE_DROP,
+                    mask=m, gamma=np.ones((1, ny, nx)), alpha_max=0.0)
+
+
+def channel_3d_slit(nx: int, ny: int, nz: int, tau: float, u_peak: float) -> Workload:
+    """Plane channel in 3D (D3Q19): walls at z=0 and z=nz-1, periodic in y,
+    velocity inlet on x=0, pressure outlet on x=nx-1, fluid inside."""
+    per = (False, True, False)
+    m = walled_box(nx, ny, nz, periodic=per, interior=FLUID)
+    m[1:nz - 1, :, 0] = code(INLET, NPX)
+    m[1:nz - 1, :, nx - 1] = code(OUTLET, NMX)
+    L = float(nz - 2)
+    nu = (tau - 0.5) / 3.0
+    return Workload(name=f"slit_{nx}x{ny}x{nz}", dim=3, nx=nx, ny=ny, nz=nz, thermal=False,
+                    tau=tau, Re=u_peak * L / nu, L_ref=L, objective=OBJ_PRESSURE_DROP,
+                    mask=m, gamma=np.ones((nz, ny, nx)), alpha_max=0.0, periodic=per)
+
+
+def periodic_box(n: int, dim: int, gamma_value: float, thermal: bool = False) -> Workload:
+    """Fully periodic box of design nodes with a uniform design field."""
+    nz = n if dim == 3 else 1
+    per = (True, True, True)
+    m = np.full((nz, n, n), DESIGN, dtype=np.uint8)
+    return Workload(name=f"periodic_{dim}d_{n}", dim=dim, nx=n, ny=n, nz=nz,
+                    thermal=thermal, tau=0.8, Re=0.0, L_ref=1.0, objective=OBJ_DISSIPATION,
+                    mask=m, gamma=np.full((nz, n, n), gamma_value), periodic=per)
+
+
+def conduction_column(nx: int, ny: int, nz: int, tau: float, Pr: float, q_w: float,
+                      T_top: float) -> Workload:
+    """Pure conduction: closed box with a heated floor (z=0, heat flux q_w),
+    a zero-velocity inlet on the top face acting as a Dirichlet T_top
+    boundary, adiabatic walls elsewhere, fluid inside (no flow)."""
+    m = walled_box(nx, ny, nz, interior=FLUID)
+    m[0, 1:ny - 1, 1:nx - 1] = code(HEATED, NPZ)
+    m[nz - 1, 1:ny - 1, 1:nx - 1] = code(INLET, NMZ)
+    return Workload(name=f"conduction_{nx}x{ny}x{nz}", dim=3, nx=nx, ny=ny, nz=nz,
+                    thermal=True, tau=tau, Re=0.0, L_ref=1.0, objective=OBJ_HEATSINK, mask=m,
+                    gamma=np.ones((nz, ny, nx)), Pr=Pr, q_w=q_w, T_in=T_top, w_dp=0.0)
+
+
+def tiny_heat_sink(nx: int = 10, ny: int = 8, nz: int = 6, seed: int = 7, Re: float = 5.0,
+                   Pr: float = 1.0, tau: float = 0.8, alpha_max: float = 0.2,
+                   sigma: float = 1.0) -> Workload:
+    """A small coupled heat-sink problem with fast convergence, for gradient
+    checks (same boundary set-up as `heat_sink`)."""
+    w = heat_sink(nx, ny, nz, Re=Re, Pr=Pr, tau=tau, sigma=sigma, seed=seed,
+                  name=f"tiny_heat_sink_{nx}x{ny}x{nz}")
+    return w.replace(alpha_max=alpha_max)
+
+
+def tiny_pipe_bend_3d(n: int = 10, seed: int = 11, Re: float = 2.0, tau: float = 0.8,
+                      objective: int = OBJ_DISSIPATION, alpha_max: float = 0.2) -> Workload:
+    """A small 3D pipe bend (inlet on x=0, outlet on y=0) for gradient checks."""
+    m = walled_box(n, n, n)
+    lo, hi = 2, n - 4
+    m[lo:hi + 1, lo:hi + 1, 0] = code(INLET, NPX)
+    m[lo:hi + 1, 0, n - 1 - (hi - lo + 1) - 1:n - 2] = code(OUTLET, NPY)
+    gamma = smoothed_noise((n, n, n), 1.0, seed)
+    return Workload(name=f"tiny_pipe_bend_{n}", dim=3, nx=n, ny=n, nz=n, thermal=False,
+                    tau=tau, Re=Re, L_ref=float(hi - lo + 1), objective=objective, mask=m,
+                    gamma=gamma, alpha_max=alpha_max, q_brink=0.1, w_dp=1.0, seed=seed)
+
+
+def tiny_pipe_bend_2d(nx: int = 16, ny: int = 12, seed: int = 5, Re: float = 2.0,
+                      tau: float = 0.8, alpha_max: float = 0.2) -> Workload:
+    """A small 2D pipe bend (D2Q9) for gradient checks."""
+    m = walled_box(nx, ny, 1, dim=2)
+    m[0, 3:8, 0] = code(INLET, NPX)
+    m[0, 0, nx - 7:nx - 2] = code(OUTLET, NPY)
+    gamma = smoothed_noise((1, ny, nx), 1.0, seed)
+    return Workload(name=f"tiny_pipe_bend_2d_{nx}x{ny}", dim=2, nx=nx, ny=ny, nz=1,
+                    thermal=False, tau=tau, Re=Re, L_ref=5.0, objective=OBJ_PRESSURE_DROP,
+                    mask=m, gamma=gamma, alpha_max=alpha_max, q_brink=0.1, seed=seed)
+
+
+def config_workloads():
+    """The benchmark configurations at their full sizes."""
+    return {
+        "pipe_bend_2d": pipe_bend_2d(),
+        "pipe_bend_3d": pipe_bend_3d(),
+        "heat_sink_Re50": heat_sink(Re=50.0),
+        "heat_sink_Re200": heat_sink(Re=200.0),
+        "heat_sink_Re400": heat_sink(Re=400.0),
+        "differentiable": differentiable_case(),
+    }
+
+
+def nu_of(tau: float) -> float:
+    """Lattice viscosity for relaxation time tau (used only to pick inputs)."""
+    return (tau - 0.5) / 3.0
+
+
+def describe(w: Workload) -> dict:
+    """Short JSON-able description of a workload (no arrays)."""
+    return {"workload": w.name, "grid": [w.nx, w.ny, w.nz], "nodes": w.N, "tau": w.tau,
+            "Re": w.Re, "thermal": w.thermal, "objective": OBJECTIVE_NAMES[w.objective],
+            "seed": w.seed}
+
+
+__all__ = [n for n in dir() if not n.startswith("_") and n not in ("annotations", "math",
+                                                                   "dataclasses", "Optional")]

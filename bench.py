@@ -1,0 +1,171 @@
+"""Benchmark of the steady forward + adjoint + sensitivity hot path on one GPU.
+
+One step = one full sensitivity solve of the coupled heat-sink workload
+(D3Q19 flow + D3Q7 heat on 160 x 80 x 40, Re 200): forward sweep to the
+residual criterion (1e-7, checks every 1000 steps, at most 20000 steps),
+adjoint sweep the same way, then dJ/dgamma.  Inputs are resident in HBM before
+the timed region.  value = node updates of both sweeps per second (MLUPS, one
+update = both lattices at one node).
+
+The roofline entry is for the step kernel that takes most of the time: its
+algorithmic bytes per node-update times the node count, over its average
+launch duration, measured with HIP event pairs around every launch during the
+timed region.  The CPU baseline times the FP64 oracle on the host cores on a
+bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "fwd+adj MLUPS & % HBM peak (D3Q19+D3Q7 FP32); p50/p99 sensitivity latency"
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic bytes per node-update: every population read once and written
+# once (4 B each), plus the per-node inputs each kernel reads once.
+BYTES_PER_NODE = {
+    # forward: 19 + 7 populations in and out, gamma, flags
+    ("forward", True): (19 + 7) * 4 * 2 + 4 + 1,
+    ("forward", False): 19 * 4 * 2 + 4 + 1,
+    # adjoint: 19 + 7 populations in and out, u (3), T, gamma, flags
+    ("adjoint", True): (19 + 7) * 4 * 2 + 12 + 4 + 4 + 1,
+    ("adjoint", False): 19 * 4 * 2 + 12 + 4 + 1,
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="heat_sink_Re200",
+                    choices=["heat_sink_Re50", "heat_sink_Re200", "heat_sink_Re400",
+                             "heat_sink_320x160x80_Re200"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-fwd-steps", type=int, default=0,
+                    help="oracle sample size (0: pick ~15 s of work)")
+    return ap.parse_args()
+
+
+def make_workload(name):
+    import workloads as W
+    if name == "heat_sink_320x160x80_Re200":
+        return W.heat_sink(320, 160, 80, Re=200.0, name="heat_sink_320x160x80_Re200")
+    Re = float(name.split("Re")[1])
+    return W.heat_sink(Re=Re)
+
+
+def cpu_baseline(w, fwd_steps):
+    """The oracle (as it is) on the host cores: a bounded sample of forward and
+    adjoint steps of the same workload from rest."""
+    import numpy as np
+    import oracle
+    o = oracle.Oracle(w)
+    t0 = time.perf_counter()
+    fw = o.forward(max_steps=fwd_steps, tol=0.0, check_every=0)
+    t1 = time.perf_counter()
+    adj_steps = max(1, fwd_steps // 4)
+    o.adjoint(fw["f"], fw["g"], max_steps=adj_steps, tol=0.0, check_every=0)
+    t2 = time.perf_counter()
+    tf = (t1 - t0) / fwd_steps
+    ta = (t2 - t1) / adj_steps
+    # the GPU solve takes about as many adjoint as forward steps
+    mlups = 2 * w.N / (tf + ta) / 1e6
+    return {"value": round(mlups, 4), "unit": "MLUPS", "cores": oracle.threads_used(),
+            "kind": "oracle",
+            "sample": f"{fwd_steps} forward + {adj_steps} adjoint steps of {w.name} from rest "
+                      f"(FP64, {tf * 1e3:.0f} ms/forward step, {ta * 1e3:.0f} ms/adjoint step; "
+                      f"rate for equal forward and adjoint step counts)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (--gpus {args.gpus} requested); "
+              "a multi-GPU slab decomposition is not part of it.",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_2501_02161_amd import lbm
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    w = make_workload(args.workload)
+    prob = lbm.Problem(w, device="cuda:0")
+    gamma = prob.gamma_tensor(w.gamma)
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+
+    def one():
+        fi = prob.forward(gamma, stream)
+        ai = prob.adjoint(stream=stream)
+        J = prob.sensitivity(stream=stream)
+        return fi, ai, J
+
+    for _ in range(args.warmup):
+        one()
+    torch.cuda.synchronize()
+    lbm.lbm_set_kernel_timing(prob.h, True)
+    lbm.lbm_kernel_timing(prob.h, reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = [one() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    (ms_f, ms_a), (n_f, n_a) = lbm.lbm_kernel_timing(prob.h, reset=True)
+    lbm.lbm_set_kernel_timing(prob.h, False)
+    elapsed = t1 - t0
+    updates = sum(w.N * (fi["steps"] + ai["steps"]) for fi, ai, _ in infos)
+    mlups = updates / elapsed / 1e6
+    fi, ai, J = infos[-1]
+
+    kernels = {"forward": (ms_f, n_f), "adjoint": (ms_a, n_a)}
+    dom = max(kernels, key=lambda k: kernels[k][0])
+    ms_tot, n_launch = kernels[dom]
+    avg_s = ms_tot / 1e3 / max(n_launch, 1)
+    bpn = BYTES_PER_NODE[(dom, bool(w.thermal))]
+    achieved = bpn * w.N / avg_s / 1e9
+    per_kernel = {k: {"avg_us": round(v[0] * 1e3 / max(v[1], 1), 3), "launches": v[1],
+                      "bytes_per_node": BYTES_PER_NODE[(k, bool(w.thermal))],
+                      "GBps": round(BYTES_PER_NODE[(k, bool(w.thermal))] * w.N /
+                                    (v[0] / 1e3 / max(v[1], 1)) / 1e9, 1)}
+                  for k, v in kernels.items()}
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "nodes": w.N, "lattice": "D3Q19+D3Q7",
+                   "objective": "mean floor-layer T + 0.1 pressure drop", "tau": round(w.tau, 6),
+                   "tol": w.tol, "max_steps": w.max_steps, "fwd_steps": fi["steps"],
+                   "adj_steps": ai["steps"], "J": J},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None},
+        "kernels": per_kernel,
+        "hbm_frac_whole_job": round(
+            (BYTES_PER_NODE[("forward", bool(w.thermal))] * w.N * fi["steps"] +
+             BYTES_PER_NODE[("adjoint", bool(w.thermal))] * w.N * ai["steps"]) * args.steps /
+            elapsed / 1e9 / HBM_PEAK_GBS, 4),
+    }
+    if not args.no_cpu_baseline:
+        steps = args.cpu_fwd_steps or 48
+        out["cpu_baseline"] = cpu_baseline(w, steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,234 @@
+/*
+ * lbmadj.h -- C ABI of the MI355X (gfx950) library for the steady discrete
+ * adjoint lattice Boltzmann method of Luo, Chen, Yaji and Tao, "Improved
+ * adjoint lattice Boltzmann method for topology optimization of laminar
+ * convective heat transfer" (arXiv 2501.02161).
+ *
+ * One problem = one lattice: a D3Q19 BGK flow lattice with the incompressible
+ * equilibrium of Eq. (4), extended by the design field as in Eq. (12), and
+ * optionally a coupled D3Q7 BGK advection-diffusion lattice for temperature
+ * (Eq. 71 without volumetric source).  Three calls make the hot path:
+ *
+ *   lbm_forward_solve   the steady forward sweep: collision (Eq. 36),
+ *                       streaming (Eq. 37), boundary conditions (Eqs. 7-9)
+ *                       repeated until the residual criterion of Sec. 3.1;
+ *   lbm_adjoint_solve   the steady discrete adjoint sweep (Sec. 2.4, Eqs.
+ *                       53-56): adjoint boundary condition (Eqs. 54, 59, 60),
+ *                       reversed streaming (Eq. 61), adjoint collision minus
+ *                       the objective derivative (Eq. 65);
+ *   lbm_sensitivity     dJ/dgamma per node (Eq. 66, first equality, with the
+ *                       exact derivative of the collision).
+ *
+ * Units and conventions
+ *   Lattice units (dx = dt = 1).  Node n = x + nx*(y + ny*z); every field is
+ *   a contiguous FP32 array [z][y][x] (x fastest) of N = nx*ny*nz entries;
+ *   vector fields are [3][z][y][x] (component-major).
+ *   Design field gamma in [0,1] (1 fluid, 0 solid): Brinkman inverse
+ *   permeability a_B = alpha_max q (1-gamma)/(q+gamma); the equilibrium of
+ *   Eq. (12) uses chi u with chi = 1 - tau a_B (a velocity-shift forcing that
+ *   removes a_B rho0 u of momentum per step).  Thermal relaxation time
+ *   tau_g = 1/2 + 4 (nu/Pr) k(gamma), k = r + (1-r) gamma/(1 + q_r (1-gamma))
+ *   (RAMP, r = k_ratio).  Non-design nodes use chi = 1 and k = 1.
+ *   The peak inlet speed is U = Re nu / L_ref, nu = (tau - 1/2)/3 (Eq. 3); the
+ *   inlet profile is a product of parabolas over the inlet set's extent in
+ *   each tangential axis (uniform along an axis the set spans entirely).
+ *
+ * Memory and ownership
+ *   Device pointers are caller-owned (e.g. torch tensors) and must stay valid
+ *   for the call; the library never frees them.  Its only device memory is the
+ *   workspace the caller binds (lbm_workspace_bytes / lbm_bind_workspace),
+ *   which holds the A/B population buffers, node flags and reduction scratch.
+ *   Host pointers (desc, mask, info, J) are read/written during the call only.
+ *   All device work is enqueued on the HIP stream `stream` (NULL = default
+ *   stream); calls that return host values (info, J) synchronise that stream.
+ *   One problem handle must be used by one host thread at a time.
+ *
+ * Errors
+ *   0 LBM_OK; +1 LBM_NOT_CONVERGED (max_steps reached: the outputs are still
+ *   written).  Negative values are errors, with a message from
+ *   lbm_last_error() (thread-local): LBM_EINVAL (null pointer, bad size or
+ *   parameter, bad mask), LBM_ESTATE (no workspace bound, adjoint before a
+ *   forward solve, sensitivity before an adjoint solve), LBM_EDEVICE (a HIP
+ *   call failed), LBM_EDIVERGED (the residual monitor became non-finite).
+ *   No C++ exception crosses this interface.
+ */
+#ifndef LBMADJ_H
+#define LBMADJ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBM_OK 0
+#define LBM_NOT_CONVERGED 1
+#define LBM_EINVAL (-1)
+#define LBM_ESTATE (-2)
+#define LBM_ENOMEM (-3)
+#define LBM_EDEVICE (-4)
+#define LBM_EDIVERGED (-5)
+
+/* Mask byte, one per node (host array of N bytes, [z][y][x]).
+ * bits 0-2: node kind; bits 3-5: inward normal for INLET, OUTLET and HEATED
+ * nodes (the direction pointing into the domain); bits 6-7: zero.
+ *   DESIGN  interior node whose chi and k follow gamma
+ *   FLUID   interior node with chi = 1, k = 1 (not designable)
+ *   INLET   Zou-He velocity inlet (Eq. 7 generalised to any axis normal and
+ *           to D3Q19); thermal Dirichlet T = T_in
+ *   OUTLET  Zou-He pressure outlet rho = rho0 (Eq. 8 generalised); thermal
+ *           zero-gradient outflow
+ *   WALL    full-way bounce-back (Eq. 9): every pair is swapped, no
+ *           collision; adiabatic for the thermal lattice
+ *   HEATED  a WALL that adds the heat flux q_w per step to the thermal
+ *           population along its inward normal
+ * On every non-periodic axis the two outer layers must be WALL, HEATED,
+ * INLET or OUTLET nodes; a port's normal must be the inward normal of its
+ * face and ports may not sit on an edge of two non-periodic faces. */
+#define LBM_NODE_DESIGN 0
+#define LBM_NODE_FLUID 1
+#define LBM_NODE_INLET 2
+#define LBM_NODE_OUTLET 3
+#define LBM_NODE_WALL 4
+#define LBM_NODE_HEATED 5
+#define LBM_NORMAL_PX 0
+#define LBM_NORMAL_MX 1
+#define LBM_NORMAL_PY 2
+#define LBM_NORMAL_MY 3
+#define LBM_NORMAL_PZ 4
+#define LBM_NORMAL_MZ 5
+
+/* Objectives, evaluated on the post-boundary state (the moments of Eq. 6).
+ *   PRESSURE_DROP  J = w_dp (mean over inlet nodes of rho/3 - rho0/3): the
+ *                  paper's J = p_in of Eq. (34) minus the fixed outlet pressure.
+ *   DISSIPATION    J = sum over axis edges between non-wall nodes (no
+ *                  wrap-around) of rho0 nu |u(x+e) - u(x)|^2
+ *                  + sum over design nodes of a_B(gamma) rho0 |u|^2.
+ *   HEATSINK       J = mean T over the node layer next to the HEATED walls
+ *                  (x + normal of each HEATED node) + w_dp (mean inlet rho/3
+ *                  - rho0/3); needs the thermal lattice. */
+#define LBM_OBJ_PRESSURE_DROP 0
+#define LBM_OBJ_DISSIPATION 1
+#define LBM_OBJ_HEATSINK 2
+
+typedef struct lbm_desc {
+  int32_t nx, ny, nz;      /* grid, each >= 3 (nz >= 3 too: D3Q19 only)      */
+  int32_t thermal;         /* 0: flow only; 1: coupled D3Q7 temperature       */
+  int32_t periodic[3];     /* 1: periodic streaming along x / y / z           */
+  int32_t objective;       /* LBM_OBJ_*                                       */
+  double tau;              /* flow relaxation time, > 1/2                     */
+  double rho0;             /* reference density of the incompressible model  */
+  double Re;               /* Reynolds number U L_ref / nu (sets inlet speed) */
+  double L_ref;            /* length of Re, > 0 when there are inlets         */
+  double alpha_max, q_brink; /* Brinkman interpolation a_B(gamma)             */
+  double Pr;               /* Prandtl number: fluid diffusivity nu/Pr         */
+  double k_ratio, q_ramp;  /* solid/fluid conductivity ratio, RAMP parameter  */
+  double q_w;              /* heat flux per HEATED node and step              */
+  double T_in;             /* inlet temperature                               */
+  double w_dp;             /* weight of the pressure-drop term                */
+  int32_t max_steps;       /* step cap of each solve, >= 1                    */
+  int32_t check_every;     /* steps between residual checks (0: never)        */
+  double tol;              /* residual tolerance (0: run max_steps)           */
+} lbm_desc_t;
+
+/* Result of a solve.  Residuals follow Sec. 3.1: |I(t) - I(t - c)| / |I(t)|
+ * with c = check_every; forward I = (mean |u|, mean T) over non-wall nodes,
+ * adjoint I = (mean |sum_i e_i f*_S,i|, mean |sum_i g*_S,i|).  The solve has
+ * converged when both are <= tol at a check (never when tol == 0). */
+typedef struct lbm_info {
+  int32_t steps;           /* steps taken                                     */
+  int32_t status;          /* LBM_OK or LBM_NOT_CONVERGED                     */
+  double residual[2];      /* last residuals (flow, thermal)                  */
+  double monitor[2];       /* last monitored quantities I                     */
+  double J;                /* forward: objective; adjoint/sensitivity: copy   */
+} lbm_info_t;
+
+typedef struct lbm_problem lbm_problem_t;
+
+/* Validate desc and the host mask (N bytes) and create a handle.  Nothing is
+ * allocated on the device.  Returns LBM_EINVAL on a bad descriptor/mask. */
+int lbm_problem_create(const lbm_desc_t* desc, const uint8_t* mask, lbm_problem_t** out);
+
+/* Device bytes the workspace must have (including 256-byte alignment slack). */
+size_t lbm_workspace_bytes(const lbm_problem_t* p);
+
+/* Bind caller-owned device memory of at least lbm_workspace_bytes() bytes on
+ * the current device and upload the node flags and inlet profile
+ * (synchronous).  The workspace must outlive every later call. */
+int lbm_bind_workspace(lbm_problem_t* p, void* device_ptr, size_t bytes);
+
+/* Steady forward solve from rest (f = f_eq(rho0, 0), T = T_in).
+ * gamma: device [N] design field (read).  drho: device [N], written with the
+ * density deviation rho - rho0 (pressure deviation drho/3); u: device [3][N]
+ * velocity; T: device [N] temperature (may be NULL without the thermal
+ * lattice).  All fields are the moments of the final post-boundary state;
+ * wall nodes get 0.  info (host, may be NULL) receives steps, residuals and J.
+ * Returns LBM_OK, LBM_NOT_CONVERGED or an error. */
+int lbm_forward_solve(lbm_problem_t* p, const float* gamma, float* drho, float* u, float* T,
+                      lbm_info_t* info, void* stream);
+
+/* Run exactly nsteps more forward steps from the current forward state (no
+ * reset, no residual check) and write drho, u, T as lbm_forward_solve does.
+ * Needs a previous lbm_forward_solve. */
+int lbm_forward_continue(lbm_problem_t* p, const float* gamma, int32_t nsteps, float* drho,
+                         float* u, float* T, lbm_info_t* info, void* stream);
+
+/* Steady adjoint solve (Sec. 2.4) about the state (u, T) of the last forward
+ * solve, starting from f*_C = 0 (Eq. 53).  gamma, u (device [3][N]) and T
+ * (device [N], NULL without thermal) must be the ones that forward solve used
+ * and returned; drho may be NULL (the incompressible equilibrium's Jacobian
+ * does not depend on rho).  The thermal part also reads the non-equilibrium
+ * thermal populations the forward solve left in the workspace.  info may be
+ * NULL.  Returns LBM_OK, LBM_NOT_CONVERGED or an error (LBM_ESTATE without a
+ * forward solve). */
+int lbm_adjoint_solve(lbm_problem_t* p, const float* gamma, const float* drho, const float* u,
+                      const float* T, lbm_info_t* info, void* stream);
+
+/* Run exactly nsteps more adjoint steps from the current adjoint state. */
+int lbm_adjoint_continue(lbm_problem_t* p, const float* gamma, const float* drho,
+                         const float* u, const float* T, int32_t nsteps, lbm_info_t* info,
+                         void* stream);
+
+/* dJ/dgamma (device [N], written; 0 on non-design nodes) from the last
+ * adjoint state, Eq. (66): explicit dJ/dgamma - sum_i f*_S,i dC_i/dgamma
+ * - sum_i g*_S,i dC^g_i/dgamma.  J (host, may be NULL) receives the objective
+ * of the last forward solve.  Needs a previous lbm_adjoint_solve. */
+int lbm_sensitivity(lbm_problem_t* p, const float* gamma, const float* drho, const float* u,
+                    const float* T, float* dJdgamma, double* J, void* stream);
+
+/* Copy a workspace state to device memory dst: which 0 = forward flow
+ * populations (19 x N), 1 = forward thermal (7 x N), 2 = adjoint flow
+ * (19 x N), 3 = adjoint thermal (7 x N), 4 = thermal non-equilibrium
+ * populations of the last forward state (7 x N).  Populations are
+ * population-major [q][z][y][x] and stored shifted: f_i - w_i rho0 (forward
+ * flow), g_i - w_i T_in (forward thermal); the forward state is the
+ * post-collision one, the adjoint state the one after the adjoint boundary
+ * condition.  Direction order is given by lbm_lattice. */
+int lbm_copy_state(const lbm_problem_t* p, int32_t which, float* dst, void* stream);
+
+/* Per-launch timing of the step kernels, for roofline reporting.  When
+ * enabled, each forward and adjoint step kernel launch is bracketed by a pair
+ * of HIP events on the call's stream; the durations are summed at every
+ * residual check and at the end of each call.  lbm_kernel_timing returns the
+ * totals (ms[0], launches[0]: forward step kernel; ms[1], launches[1]:
+ * adjoint step kernel) and, if reset != 0, clears them.  Enabling creates
+ * events on the bound device (needs a bound workspace). */
+int lbm_set_kernel_timing(lbm_problem_t* p, int32_t enable);
+int lbm_kernel_timing(lbm_problem_t* p, double* ms, int64_t* launches, int32_t reset);
+
+/* Direction table of the library: which 0 = D3Q19 (19 entries), 1 = D3Q7
+ * (7 entries); e receives 3 ints per direction, w the weight. */
+int lbm_lattice(int32_t which, int32_t* e, double* w);
+
+/* Release the handle (not the caller's workspace). */
+void lbm_problem_destroy(lbm_problem_t* p);
+
+/* Message of the last error on this thread ("" when none). */
+const char* lbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBMADJ_H */

@@ -1,0 +1,51 @@
+"""Build the gfx950 shared library ``_build/liblbmadj.so`` with hipcc.
+
+Run ``python -m paper_2501_02161_amd.build`` (or ``__graft_entry__.build()``).
+hipcc cross-compiles for gfx950 without a GPU present.
+"""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+SOURCES = [os.path.join(HERE, "csrc", "lbm_kernels.hip"), os.path.join(HERE, "csrc", "lbm_host.hip")]
+HEADERS = [os.path.join(ROOT, "include", "lbmadj.h"), os.path.join(HERE, "csrc", "lbm_internal.h")]
+LIB = os.path.join(HERE, "_build", "liblbmadj.so")
+ARCH = os.environ.get("LBMADJ_ARCH", "gfx950")
+
+
+def hipcc() -> str:
+    for c in (os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "bin", "hipcc"), "hipcc"):
+        if os.path.sep not in c or os.path.exists(c):
+            return c
+    return "hipcc"
+
+
+def command(out: str) -> list:
+    return [hipcc(), "-std=c++17", "-O3", f"--offload-arch={ARCH}", "-fPIC", "-shared",
+            # packed-FP32 instructions stay off: the compiler may not emit v_pk_*_f32
+            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument",
+            "-I", os.path.join(ROOT, "include"), "-o", out] + SOURCES
+
+
+def build(verbose: bool = False) -> str:
+    """Compile the library (always) and return its path."""
+    os.makedirs(os.path.dirname(LIB), exist_ok=True)
+    tmp = LIB + f".tmp{os.getpid()}"
+    cmd = command(tmp)
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("hipcc failed building liblbmadj.so")
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))

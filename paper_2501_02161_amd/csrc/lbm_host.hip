@@ -1,0 +1,738 @@
+// Host side of the C ABI declared in include/lbmadj.h: descriptor and mask
+// validation, node set-up (flags, inlet profile, objective layer), the
+// workspace layout, and the forward / adjoint solve loops with the residual
+// criterion of Sec. 3.1 of arXiv 2501.02161.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lbm_internal.h"
+#include "lbmadj.h"
+
+using namespace lbmadj;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                        \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      return fail(LBM_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));          \
+  } while (0)
+
+const int NVEC[6][3] = {{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+}  // namespace
+
+struct lbm_problem {
+  lbm_desc_t d{};
+  int N = 0, Np = 0, nblk = 0;
+  std::vector<uint8_t> flags_host;
+  std::vector<float> uin_host;
+  int n_inlet = 0, n_layer = 0, n_nonwall = 0;
+  KParams kp{};
+  // workspace
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  int dev = -1;
+  float* f[2] = {nullptr, nullptr};
+  float* g[2] = {nullptr, nullptr};
+  float* a[2] = {nullptr, nullptr};
+  float* b[2] = {nullptr, nullptr};
+  float* gneq = nullptr;
+  float* G = nullptr;
+  float* uin = nullptr;
+  uint8_t* flags = nullptr;
+  double* partials = nullptr;
+  double* sums = nullptr;
+  double* pinned = nullptr;
+  int fcur = 0, acur = 0;
+  bool fwd_done = false, adj_done = false;
+  double J = 0.0;
+  // per-launch kernel timing
+  bool timing = false;
+  std::vector<hipEvent_t> ev_start, ev_stop;
+  std::vector<int> ev_kind;
+  int ev_used = 0;
+  double t_ms[2] = {0.0, 0.0};
+  long long t_n[2] = {0, 0};
+};
+
+namespace {
+
+bool thermal_of(const lbm_problem* p) { return p->d.thermal != 0; }
+
+// Layout of the workspace: offsets of every region (256-byte aligned).
+struct Layout {
+  size_t f[2], g[2], a[2], b[2], gneq, G, uin, flags, partials, sums, total;
+};
+
+Layout layout_of(const lbm_problem* p) {
+  Layout L{};
+  size_t off = 0;
+  const size_t pf = (size_t)19 * p->Np * sizeof(float), pg = (size_t)7 * p->Np * sizeof(float);
+  const bool th = thermal_of(p);
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  for (int k = 0; k < 2; ++k) L.f[k] = take(pf);
+  for (int k = 0; k < 2; ++k) L.g[k] = th ? take(pg) : 0;
+  for (int k = 0; k < 2; ++k) L.a[k] = take(pf);
+  for (int k = 0; k < 2; ++k) L.b[k] = th ? take(pg) : 0;
+  L.gneq = th ? take(pg) : 0;
+  L.G = (p->d.objective == LBM_OBJ_DISSIPATION) ? take((size_t)3 * p->Np * sizeof(float)) : 0;
+  L.uin = take((size_t)p->Np * sizeof(float));
+  L.flags = take((size_t)p->Np);
+  L.partials = take((size_t)p->nblk * 4 * sizeof(double));
+  L.sums = take(16 * sizeof(double));
+  L.total = off + 256;  // slack for aligning the caller's pointer
+  return L;
+}
+
+int validate_and_setup(lbm_problem* p, const lbm_desc_t& d, const uint8_t* mask) {
+  if (d.nx < 3 || d.ny < 3 || d.nz < 3) return fail(LBM_EINVAL, "nx, ny, nz must be >= 3");
+  const long long N = (long long)d.nx * d.ny * d.nz;
+  if (N > (1LL << 31) / 32) return fail(LBM_EINVAL, "grid too large for 32-bit indexing");
+  if (!(d.tau > 0.5)) return fail(LBM_EINVAL, "tau must be > 1/2");
+  if (!(d.rho0 > 0.0)) return fail(LBM_EINVAL, "rho0 must be > 0");
+  if (d.thermal != 0 && d.thermal != 1) return fail(LBM_EINVAL, "thermal must be 0 or 1");
+  for (int a = 0; a < 3; ++a)
+    if (d.periodic[a] != 0 && d.periodic[a] != 1) return fail(LBM_EINVAL, "periodic must be 0 or 1");
+  if (d.objective < 0 || d.objective > 2) return fail(LBM_EINVAL, "unknown objective");
+  if (d.max_steps < 1) return fail(LBM_EINVAL, "max_steps must be >= 1");
+  if (d.check_every < 0) return fail(LBM_EINVAL, "check_every must be >= 0");
+  if (!(d.tol >= 0.0)) return fail(LBM_EINVAL, "tol must be >= 0");
+  if (!(d.alpha_max >= 0.0) || !(d.q_brink > 0.0)) return fail(LBM_EINVAL, "need alpha_max >= 0, q > 0");
+  if (!(d.tau * d.alpha_max < 1.0)) return fail(LBM_EINVAL, "tau * alpha_max must be < 1 (chi > 0)");
+  if (d.thermal) {
+    if (!(d.Pr > 0.0) || !(d.k_ratio > 0.0) || !(d.q_ramp >= 0.0))
+      return fail(LBM_EINVAL, "need Pr > 0, k_ratio > 0, q_ramp >= 0");
+  }
+  if (d.objective == LBM_OBJ_HEATSINK && !d.thermal)
+    return fail(LBM_EINVAL, "the heat-sink objective needs the thermal lattice");
+  if (!mask) return fail(LBM_EINVAL, "mask is NULL");
+
+  p->d = d;
+  p->N = (int)N;
+  p->Np = (int)((N + 63) / 64 * 64);
+  p->nblk = (int)((N + kBlock - 1) / kBlock);
+  p->flags_host.assign(mask, mask + N);
+  p->uin_host.assign(N, 0.0f);
+  const int nx = d.nx, ny = d.ny, nz = d.nz;
+  const int lim[3] = {nx, ny, nz};
+  auto coords = [&](long long n, int* c) {
+    c[0] = (int)(n % nx);
+    c[1] = (int)((n / nx) % ny);
+    c[2] = (int)(n / ((long long)nx * ny));
+  };
+  for (long long n = 0; n < N; ++n) {
+    const unsigned m = mask[n];
+    const int kind = m & 7, nc = (m >> 3) & 7;
+    if ((m >> 6) != 0 || kind > K_HEATED) return fail(LBM_EINVAL, "bad mask byte at node " + std::to_string(n));
+    int c[3];
+    coords(n, c);
+    bool on_face[3];
+    for (int a = 0; a < 3; ++a) on_face[a] = !d.periodic[a] && (c[a] == 0 || c[a] == lim[a] - 1);
+    const bool boundary_kind = kind >= K_INLET;
+    if ((on_face[0] || on_face[1] || on_face[2]) && !boundary_kind)
+      return fail(LBM_EINVAL, "interior node on a non-periodic face at node " + std::to_string(n));
+    if (kind == K_INLET || kind == K_OUTLET || kind == K_HEATED) {
+      if (nc > 5) return fail(LBM_EINVAL, "bad normal code at node " + std::to_string(n));
+    } else {
+      p->flags_host[n] = (uint8_t)kind;  // normal bits are meaningless here
+    }
+    if (kind == K_INLET || kind == K_OUTLET) {
+      const int ax = nc / 2;
+      const int face = (nc % 2 == 0) ? 0 : lim[ax] - 1;
+      if (d.periodic[ax] || c[ax] != face)
+        return fail(LBM_EINVAL, "port normal is not the inward normal of its face at node " + std::to_string(n));
+      for (int b2 = 0; b2 < 3; ++b2)
+        if (b2 != ax && on_face[b2])
+          return fail(LBM_EINVAL, "port on an edge of two faces at node " + std::to_string(n));
+    }
+    if (kind == K_HEATED) {
+      for (int a = 0; a < 3; ++a) {
+        const int cc = c[a] + NVEC[nc][a];
+        if (cc < 0 || cc >= lim[a]) return fail(LBM_EINVAL, "heated wall normal points out of the box");
+      }
+    }
+  }
+  // counts, objective layer
+  p->n_inlet = p->n_layer = p->n_nonwall = 0;
+  for (long long n = 0; n < N; ++n) {
+    const int kind = p->flags_host[n] & 7;
+    if (kind == K_INLET) ++p->n_inlet;
+    if (kind < K_WALL) ++p->n_nonwall;
+    if (kind == K_HEATED) {
+      const int nc = (p->flags_host[n] >> 3) & 7;
+      int c[3];
+      coords(n, c);
+      const long long m = (c[0] + NVEC[nc][0]) + (long long)nx * ((c[1] + NVEC[nc][1]) + (long long)ny * (c[2] + NVEC[nc][2]));
+      if ((mask[m] & 7) < K_WALL) p->flags_host[m] |= (uint8_t)kLayerBit;
+    }
+  }
+  for (long long n = 0; n < N; ++n)
+    if (p->flags_host[n] & kLayerBit) ++p->n_layer;
+  if (p->n_nonwall == 0) return fail(LBM_EINVAL, "no non-wall nodes");
+  if ((d.objective == LBM_OBJ_PRESSURE_DROP || d.objective == LBM_OBJ_HEATSINK) && d.w_dp != 0.0 &&
+      p->n_inlet == 0)
+    return fail(LBM_EINVAL, "the pressure-drop term needs inlet nodes");
+  if (d.objective == LBM_OBJ_HEATSINK && p->n_layer == 0)
+    return fail(LBM_EINVAL, "the heat-sink objective needs HEATED walls next to non-wall nodes");
+  const double nu = (d.tau - 0.5) / 3.0;
+  if (p->n_inlet > 0 && !(d.L_ref > 0.0)) return fail(LBM_EINVAL, "L_ref must be > 0 with inlets");
+  const double U = p->n_inlet > 0 ? d.Re * nu / d.L_ref : 0.0;
+  // inlet profile: product of parabolas over the inlet set of each normal
+  for (int code = 0; code < 6; ++code) {
+    int lo[3] = {1 << 30, 1 << 30, 1 << 30}, hi[3] = {-1, -1, -1};
+    bool any = false;
+    for (long long n = 0; n < N; ++n) {
+      if ((p->flags_host[n] & 7) != K_INLET || ((p->flags_host[n] >> 3) & 7) != code) continue;
+      any = true;
+      int c[3];
+      coords(n, c);
+      for (int a = 0; a < 3; ++a) {
+        lo[a] = std::min(lo[a], c[a]);
+        hi[a] = std::max(hi[a], c[a]);
+      }
+    }
+    if (!any) continue;
+    for (long long n = 0; n < N; ++n) {
+      if ((p->flags_host[n] & 7) != K_INLET || ((p->flags_host[n] >> 3) & 7) != code) continue;
+      int c[3];
+      coords(n, c);
+      double prof = 1.0;
+      for (int a = 0; a < 3; ++a) {
+        if (NVEC[code][a] != 0) continue;
+        if (lo[a] == 0 && hi[a] == lim[a] - 1) continue;
+        const double s = (c[a] - lo[a] + 0.5) / double(hi[a] - lo[a] + 1);
+        prof *= 4.0 * s * (1.0 - s);
+      }
+      p->uin_host[n] = (float)(U * prof);
+    }
+  }
+  // kernel constants
+  KParams& k = p->kp;
+  k.nx = nx;
+  k.ny = ny;
+  k.nz = nz;
+  k.N = p->N;
+  k.Np = p->Np;
+  k.plane = nx * ny;
+  k.px = d.periodic[0];
+  k.py = d.periodic[1];
+  k.pz = d.periodic[2];
+  k.nblk = p->nblk;
+  k.xcd_per = p->nblk / 8;
+  k.xcd_rem = p->nblk % 8;
+  k.omega = (float)(1.0 / d.tau);
+  k.rho0 = (float)d.rho0;
+  k.tab = (float)(d.tau * d.alpha_max * d.q_brink);
+  k.amq = (float)(d.alpha_max * d.q_brink);
+  k.qb = (float)d.q_brink;
+  k.dfc = d.thermal ? (float)(4.0 * nu / d.Pr) : 0.0f;
+  k.kr = (float)d.k_ratio;
+  k.qr = (float)d.q_ramp;
+  k.q_w = (float)d.q_w;
+  k.T_ref = (float)d.T_in;
+  k.dT_in = 0.0f;
+  k.c_in = p->n_inlet > 0 ? (float)(d.w_dp / (3.0 * p->n_inlet)) : 0.0f;
+  k.c_layer = p->n_layer > 0 ? (float)(1.0 / p->n_layer) : 0.0f;
+  k.two_nu = (float)(2.0 * nu);
+  k.nu = (float)nu;
+  return LBM_OK;
+}
+
+constexpr int kEventPool = 1024;
+
+// Sum the durations of the recorded event pairs (their stream is synchronised
+// by the caller or here) and recycle the pool.
+int drain_events(lbm_problem* p) {
+  if (!p->timing || p->ev_used == 0) return LBM_OK;
+  HIPCHK(hipEventSynchronize(p->ev_stop[p->ev_used - 1]));
+  for (int i = 0; i < p->ev_used; ++i) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, p->ev_start[i], p->ev_stop[i]));
+    p->t_ms[p->ev_kind[i]] += ms;
+    p->t_n[p->ev_kind[i]] += 1;
+  }
+  p->ev_used = 0;
+  return LBM_OK;
+}
+
+int timed_begin(lbm_problem* p, int kind, hipStream_t s) {
+  if (!p->timing) return LBM_OK;
+  if (p->ev_used == kEventPool) {
+    int rc = drain_events(p);
+    if (rc) return rc;
+  }
+  p->ev_kind[p->ev_used] = kind;
+  HIPCHK(hipEventRecord(p->ev_start[p->ev_used], s));
+  return LBM_OK;
+}
+
+int timed_end(lbm_problem* p, hipStream_t s) {
+  if (!p->timing) return LBM_OK;
+  HIPCHK(hipEventRecord(p->ev_stop[p->ev_used], s));
+  ++p->ev_used;
+  return LBM_OK;
+}
+
+bool rel_converged(double now, double before, double tol) {
+  if (!(tol > 0.0)) return false;
+  return std::fabs(now - before) <= tol * std::fabs(now);
+}
+
+int read_sums(lbm_problem* p, int nvals, hipStream_t s) {
+  HIPCHK(launch_finalize(p->partials, p->nblk, nvals, p->sums, s));
+  HIPCHK(hipMemcpyAsync(p->pinned, p->sums, nvals * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return LBM_OK;
+}
+
+FwdArgs fwd_args(lbm_problem* p, const float* gamma, float* drho, float* u, float* T) {
+  FwdArgs A{};
+  A.fin = p->f[p->fcur];
+  A.fout = p->f[1 - p->fcur];
+  A.gin = p->g[p->fcur];
+  A.gout = p->g[1 - p->fcur];
+  A.flags = p->flags;
+  A.gamma = gamma;
+  A.uin = p->uin;
+  A.drho = drho;
+  A.u = u;
+  A.T = T;
+  A.gneq = p->gneq;
+  A.partials = p->partials;
+  A.P = p->kp;
+  return A;
+}
+
+int objective_value(lbm_problem* p, const float* gamma, const float* u, hipStream_t s, double* J) {
+  const lbm_desc_t& d = p->d;
+  if (d.objective == LBM_OBJ_DISSIPATION) {
+    HIPCHK(launch_dissipation_objective(u, gamma, p->flags, p->partials, p->kp, s));
+    int rc = read_sums(p, kRedDiss, s);
+    if (rc) return rc;
+    *J = p->pinned[0];
+    return LBM_OK;
+  }
+  // p->pinned holds the forward partial sums of the last diagnostic step
+  double v = 0.0;
+  if (p->n_inlet > 0) v += d.w_dp * (p->pinned[2] / p->n_inlet) / 3.0;
+  if (d.objective == LBM_OBJ_HEATSINK) v += p->pinned[3] / p->n_layer;
+  *J = v;
+  return LBM_OK;
+}
+
+// Forward iterations k = 1..nsteps from the current state.  With check > 0 the
+// residual criterion is evaluated every `check` steps; the last step always
+// writes the fields.
+int run_forward(lbm_problem* p, const float* gamma, float* drho, float* u, float* T, int nsteps,
+                int check, double tol, hipStream_t s, lbm_info_t* info) {
+  const bool th = thermal_of(p);
+  double prev[2] = {0, 0}, res[2] = {0, 0}, mon[2] = {0, 0};
+  bool have_prev = false;
+  int status = LBM_NOT_CONVERGED, k = 0;
+  for (k = 1; k <= nsteps; ++k) {
+    const bool at_check = check > 0 && k % check == 0;
+    const bool diag = at_check || k == nsteps;
+    int rc = timed_begin(p, 0, s);
+    if (rc) return rc;
+    HIPCHK(launch_forward(fwd_args(p, gamma, drho, u, T), th, diag, s));
+    rc = timed_end(p, s);
+    if (rc) return rc;
+    p->fcur = 1 - p->fcur;
+    if (!diag) continue;
+    rc = read_sums(p, kRedFwd, s);
+    if (rc) return rc;
+    rc = drain_events(p);
+    if (rc) return rc;
+    mon[0] = p->pinned[0] / p->n_nonwall;
+    mon[1] = p->pinned[1] / p->n_nonwall;
+    if (!std::isfinite(mon[0]) || !std::isfinite(mon[1])) {
+      p->fwd_done = false;
+      return fail(LBM_EDIVERGED, "forward solve diverged at step " + std::to_string(k));
+    }
+    if (at_check) {
+      if (have_prev) {
+        res[0] = std::fabs(mon[0] - prev[0]) / std::max(std::fabs(mon[0]), 1e-300);
+        res[1] = std::fabs(mon[1] - prev[1]) / std::max(std::fabs(mon[1]), 1e-300);
+        if (rel_converged(mon[0], prev[0], tol) && (!th || rel_converged(mon[1], prev[1], tol))) {
+          status = LBM_OK;
+          if (k != nsteps) {
+            // fields of this step are already written (diag)
+          }
+          break;
+        }
+      }
+      prev[0] = mon[0];
+      prev[1] = mon[1];
+      have_prev = true;
+    }
+  }
+  double J = 0.0;
+  int rc = objective_value(p, gamma, u, s, &J);
+  if (rc) return rc;
+  p->J = J;
+  p->fwd_done = true;
+  p->adj_done = false;
+  if (info) {
+    info->steps = std::min(k, nsteps);
+    info->status = status;
+    info->residual[0] = res[0];
+    info->residual[1] = res[1];
+    info->monitor[0] = mon[0];
+    info->monitor[1] = mon[1];
+    info->J = J;
+  }
+  return status;
+}
+
+AdjArgs adj_args(lbm_problem* p, const float* gamma, const float* u, const float* T) {
+  AdjArgs A{};
+  A.ain = p->a[p->acur];
+  A.aout = p->a[1 - p->acur];
+  A.bin = p->b[p->acur];
+  A.bout = p->b[1 - p->acur];
+  A.flags = p->flags;
+  A.gamma = gamma;
+  A.u = u;
+  A.T = T;
+  A.G = p->G;
+  A.partials = p->partials;
+  A.P = p->kp;
+  return A;
+}
+
+int run_adjoint(lbm_problem* p, const float* gamma, const float* u, const float* T, int nsteps,
+                int check, double tol, hipStream_t s, lbm_info_t* info) {
+  const bool th = thermal_of(p);
+  double prev[2] = {0, 0}, res[2] = {0, 0}, mon[2] = {0, 0};
+  bool have_prev = false;
+  int status = LBM_NOT_CONVERGED, k = 0;
+  for (k = 1; k <= nsteps; ++k) {
+    const bool at_check = check > 0 && k % check == 0;
+    const bool diag = at_check || k == nsteps;
+    int rc = timed_begin(p, 1, s);
+    if (rc) return rc;
+    HIPCHK(launch_adjoint(adj_args(p, gamma, u, T), th, p->d.objective, diag, s));
+    rc = timed_end(p, s);
+    if (rc) return rc;
+    p->acur = 1 - p->acur;
+    if (!diag) continue;
+    rc = read_sums(p, kRedAdj, s);
+    if (rc) return rc;
+    rc = drain_events(p);
+    if (rc) return rc;
+    mon[0] = p->pinned[0] / p->n_nonwall;
+    mon[1] = p->pinned[1] / p->n_nonwall;
+    if (!std::isfinite(mon[0]) || !std::isfinite(mon[1])) {
+      p->adj_done = false;
+      return fail(LBM_EDIVERGED, "adjoint solve diverged at step " + std::to_string(k));
+    }
+    if (at_check) {
+      if (have_prev) {
+        res[0] = std::fabs(mon[0] - prev[0]) / std::max(std::fabs(mon[0]), 1e-300);
+        res[1] = std::fabs(mon[1] - prev[1]) / std::max(std::fabs(mon[1]), 1e-300);
+        if (rel_converged(mon[0], prev[0], tol) && (!th || rel_converged(mon[1], prev[1], tol))) {
+          status = LBM_OK;
+          break;
+        }
+      }
+      prev[0] = mon[0];
+      prev[1] = mon[1];
+      have_prev = true;
+    }
+  }
+  p->adj_done = true;
+  if (info) {
+    info->steps = std::min(k, nsteps);
+    info->status = status;
+    info->residual[0] = res[0];
+    info->residual[1] = res[1];
+    info->monitor[0] = mon[0];
+    info->monitor[1] = mon[1];
+    info->J = p->J;
+  }
+  return status;
+}
+
+int check_bound(const lbm_problem* p) {
+  if (!p) return fail(LBM_EINVAL, "problem is NULL");
+  if (!p->ws) return fail(LBM_ESTATE, "no workspace bound");
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lbm_last_error(void) { return g_err.c_str(); }
+
+int lbm_problem_create(const lbm_desc_t* desc, const uint8_t* mask, lbm_problem_t** out) {
+  g_err.clear();
+  if (!desc || !out) return fail(LBM_EINVAL, "desc or out is NULL");
+  *out = nullptr;
+  lbm_problem* p = nullptr;
+  try {
+    p = new lbm_problem();
+  } catch (...) {
+    return fail(LBM_ENOMEM, "host allocation failed");
+  }
+  int rc;
+  try {
+    rc = validate_and_setup(p, *desc, mask);
+  } catch (...) {
+    rc = fail(LBM_ENOMEM, "host allocation failed");
+  }
+  if (rc != LBM_OK) {
+    delete p;
+    return rc;
+  }
+  *out = p;
+  return LBM_OK;
+}
+
+size_t lbm_workspace_bytes(const lbm_problem_t* p) {
+  if (!p) return 0;
+  return layout_of(p).total;
+}
+
+int lbm_bind_workspace(lbm_problem_t* p, void* device_ptr, size_t bytes) {
+  g_err.clear();
+  if (!p || !device_ptr) return fail(LBM_EINVAL, "problem or workspace is NULL");
+  const Layout L = layout_of(p);
+  if (bytes < L.total) return fail(LBM_EINVAL, "workspace too small");
+  HIPCHK(hipGetDevice(&p->dev));
+  char* base = (char*)(((uintptr_t)device_ptr + 255) & ~uintptr_t(255));
+  p->ws = base;
+  p->ws_bytes = bytes;
+  const bool th = thermal_of(p);
+  for (int k = 0; k < 2; ++k) {
+    p->f[k] = (float*)(base + L.f[k]);
+    p->a[k] = (float*)(base + L.a[k]);
+    p->g[k] = th ? (float*)(base + L.g[k]) : nullptr;
+    p->b[k] = th ? (float*)(base + L.b[k]) : nullptr;
+  }
+  p->gneq = th ? (float*)(base + L.gneq) : nullptr;
+  p->G = (p->d.objective == LBM_OBJ_DISSIPATION) ? (float*)(base + L.G) : nullptr;
+  p->uin = (float*)(base + L.uin);
+  p->flags = (uint8_t*)(base + L.flags);
+  p->partials = (double*)(base + L.partials);
+  p->sums = (double*)(base + L.sums);
+  if (!p->pinned) HIPCHK(hipHostMalloc((void**)&p->pinned, 16 * sizeof(double), hipHostMallocDefault));
+  std::vector<float> uin(p->Np, 0.0f);
+  std::copy(p->uin_host.begin(), p->uin_host.end(), uin.begin());
+  std::vector<uint8_t> fl(p->Np, (uint8_t)K_WALL);
+  std::copy(p->flags_host.begin(), p->flags_host.end(), fl.begin());
+  HIPCHK(hipMemcpy(p->uin, uin.data(), p->Np * sizeof(float), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(p->flags, fl.data(), p->Np, hipMemcpyHostToDevice));
+  p->fwd_done = p->adj_done = false;
+  return LBM_OK;
+}
+
+int lbm_forward_solve(lbm_problem_t* p, const float* gamma, float* drho, float* u, float* T,
+                      lbm_info_t* info, void* stream) {
+  g_err.clear();
+  int rc = check_bound(p);
+  if (rc) return rc;
+  if (!gamma || !drho || !u || (thermal_of(p) && !T)) return fail(LBM_EINVAL, "null field pointer");
+  DeviceGuard guard(p->dev);
+  hipStream_t s = (hipStream_t)stream;
+  p->fwd_done = p->adj_done = false;
+  p->fcur = 0;
+  HIPCHK(launch_fill(p->f[0], (size_t)19 * p->Np, s));
+  if (thermal_of(p)) HIPCHK(launch_fill(p->g[0], (size_t)7 * p->Np, s));
+  return run_forward(p, gamma, drho, u, T, p->d.max_steps, p->d.check_every, p->d.tol, s, info);
+}
+
+int lbm_forward_continue(lbm_problem_t* p, const float* gamma, int32_t nsteps, float* drho,
+                         float* u, float* T, lbm_info_t* info, void* stream) {
+  g_err.clear();
+  int rc = check_bound(p);
+  if (rc) return rc;
+  if (!p->fwd_done) return fail(LBM_ESTATE, "no forward state to continue");
+  if (nsteps < 1) return fail(LBM_EINVAL, "nsteps must be >= 1");
+  if (!gamma || !drho || !u || (thermal_of(p) && !T)) return fail(LBM_EINVAL, "null field pointer");
+  DeviceGuard guard(p->dev);
+  return run_forward(p, gamma, drho, u, T, nsteps, 0, 0.0, (hipStream_t)stream, info);
+}
+
+int lbm_adjoint_solve(lbm_problem_t* p, const float* gamma, const float* drho, const float* u,
+                      const float* T, lbm_info_t* info, void* stream) {
+  (void)drho;
+  g_err.clear();
+  int rc = check_bound(p);
+  if (rc) return rc;
+  if (!p->fwd_done) return fail(LBM_ESTATE, "adjoint solve needs a forward solve first");
+  if (!gamma || !u || (thermal_of(p) && !T)) return fail(LBM_EINVAL, "null field pointer");
+  DeviceGuard guard(p->dev);
+  hipStream_t s = (hipStream_t)stream;
+  p->adj_done = false;
+  p->acur = 0;
+  if (p->d.objective == LBM_OBJ_DISSIPATION)
+    HIPCHK(launch_dissipation_source(u, gamma, p->flags, p->G, p->kp, s));
+  HIPCHK(launch_fill(p->a[0], (size_t)19 * p->Np, s));
+  if (thermal_of(p)) HIPCHK(launch_fill(p->b[0], (size_t)7 * p->Np, s));
+  return run_adjoint(p, gamma, u, T, p->d.max_steps, p->d.check_every, p->d.tol, s, info);
+}
+
+int lbm_adjoint_continue(lbm_problem_t* p, const float* gamma, const float* drho, const float* u,
+                         const float* T, int32_t nsteps, lbm_info_t* info, void* stream) {
+  (void)drho;
+  g_err.clear();
+  int rc = check_bound(p);
+  if (rc) return rc;
+  if (!p->adj_done) return fail(LBM_ESTATE, "no adjoint state to continue");
+  if (nsteps < 1) return fail(LBM_EINVAL, "nsteps must be >= 1");
+  if (!gamma || !u || (thermal_of(p) && !T)) return fail(LBM_EINVAL, "null field pointer");
+  DeviceGuard guard(p->dev);
+  hipStream_t s = (hipStream_t)stream;
+  if (p->d.objective == LBM_OBJ_DISSIPATION)
+    HIPCHK(launch_dissipation_source(u, gamma, p->flags, p->G, p->kp, s));
+  return run_adjoint(p, gamma, u, T, nsteps, 0, 0.0, s, info);
+}
+
+int lbm_sensitivity(lbm_problem_t* p, const float* gamma, const float* drho, const float* u,
+                    const float* T, float* dJdgamma, double* J, void* stream) {
+  (void)drho;
+  g_err.clear();
+  int rc = check_bound(p);
+  if (rc) return rc;
+  if (!p->adj_done) return fail(LBM_ESTATE, "sensitivity needs an adjoint solve first");
+  if (!gamma || !u || !dJdgamma || (thermal_of(p) && !T)) return fail(LBM_EINVAL, "null field pointer");
+  DeviceGuard guard(p->dev);
+  hipStream_t s = (hipStream_t)stream;
+  SensArgs A{};
+  A.ain = p->a[p->acur];
+  A.bin = p->b[p->acur];
+  A.flags = p->flags;
+  A.gamma = gamma;
+  A.u = u;
+  A.T = T;
+  A.gneq = p->gneq;
+  A.dJ = dJdgamma;
+  A.partials = p->partials;
+  A.objective = p->d.objective;
+  A.P = p->kp;
+  HIPCHK(launch_sensitivity(A, thermal_of(p), s));
+  rc = read_sums(p, kRedSens, s);
+  if (rc) return rc;
+  if (J) *J = p->J;
+  return LBM_OK;
+}
+
+int lbm_copy_state(const lbm_problem_t* p, int32_t which, float* dst, void* stream) {
+  g_err.clear();
+  int rc = check_bound(p);
+  if (rc) return rc;
+  if (!dst) return fail(LBM_EINVAL, "dst is NULL");
+  const float* src = nullptr;
+  int q = 0;
+  switch (which) {
+    case 0: src = p->f[p->fcur]; q = 19; break;
+    case 1: src = p->g[p->fcur]; q = 7; break;
+    case 2: src = p->a[p->acur]; q = 19; break;
+    case 3: src = p->b[p->acur]; q = 7; break;
+    case 4: src = p->gneq; q = 7; break;
+    default: return fail(LBM_EINVAL, "which must be 0..4");
+  }
+  if (!src) return fail(LBM_EINVAL, "no such state for this problem");
+  DeviceGuard guard(p->dev);
+  hipStream_t s = (hipStream_t)stream;
+  for (int i = 0; i < q; ++i)
+    HIPCHK(hipMemcpyAsync(dst + (size_t)i * p->N, src + (size_t)i * p->Np, (size_t)p->N * sizeof(float),
+                          hipMemcpyDeviceToDevice, s));
+  return LBM_OK;
+}
+
+int lbm_set_kernel_timing(lbm_problem_t* p, int32_t enable) {
+  g_err.clear();
+  int rc = check_bound(p);
+  if (rc) return rc;
+  DeviceGuard guard(p->dev);
+  if (enable && p->ev_start.empty()) {
+    p->ev_start.resize(kEventPool);
+    p->ev_stop.resize(kEventPool);
+    p->ev_kind.resize(kEventPool);
+    for (int i = 0; i < kEventPool; ++i) {
+      HIPCHK(hipEventCreate(&p->ev_start[i]));
+      HIPCHK(hipEventCreate(&p->ev_stop[i]));
+    }
+  }
+  if (!enable) {
+    rc = drain_events(p);
+    if (rc) return rc;
+  }
+  p->timing = enable != 0;
+  return LBM_OK;
+}
+
+int lbm_kernel_timing(lbm_problem_t* p, double* ms, int64_t* launches, int32_t reset) {
+  g_err.clear();
+  if (!p || !ms || !launches) return fail(LBM_EINVAL, "null argument");
+  if (p->timing) {
+    DeviceGuard guard(p->dev);
+    int rc = drain_events(p);
+    if (rc) return rc;
+  }
+  for (int k = 0; k < 2; ++k) {
+    ms[k] = p->t_ms[k];
+    launches[k] = p->t_n[k];
+    if (reset) {
+      p->t_ms[k] = 0.0;
+      p->t_n[k] = 0;
+    }
+  }
+  return LBM_OK;
+}
+
+int lbm_lattice(int32_t which, int32_t* e, double* w) {
+  if (!e || !w || (which != 0 && which != 1)) return fail(LBM_EINVAL, "bad arguments");
+  lattice_table(which, e, w);
+  return LBM_OK;
+}
+
+void lbm_problem_destroy(lbm_problem_t* p) {
+  if (!p) return;
+  if (p->dev >= 0 && !p->ev_start.empty()) {
+    DeviceGuard guard(p->dev);
+    for (size_t i = 0; i < p->ev_start.size(); ++i) {
+      (void)hipEventDestroy(p->ev_start[i]);
+      (void)hipEventDestroy(p->ev_stop[i]);
+    }
+  }
+  if (p->pinned) (void)hipHostFree(p->pinned);
+  delete p;
+}
+
+}  // extern "C"

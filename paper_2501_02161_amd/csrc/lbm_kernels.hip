@@ -1,0 +1,783 @@
+// gfx950 kernels of the steady discrete adjoint lattice Boltzmann method
+// (arXiv 2501.02161): the fused forward step (streaming, boundary conditions,
+// collision of Eq. 35 for D3Q19 and the coupled D3Q7 lattice), the fused
+// adjoint step (Eqs. 54-56 in reverse: reversed pull of Eq. 61, adjoint
+// collision of Eq. 65, local adjoint boundary condition), the sensitivity of
+// Eq. (66) and FP64 wave-shuffle reductions.
+//
+// Data layout: populations are structure-of-arrays, plane q at q*Np, node
+// n = x + nx*(y + ny*z), so the 64 lanes of a wave touch 64 consecutive
+// floats of each population plane.  Every kernel is a pull: each stored value
+// is read by exactly one thread per step (there is no reuse to stage in LDS);
+// the only cross-lane sharing is the +-1 misalignment of the x-neighbour
+// loads, which the L2 absorbs because consecutive blocks are mapped to the
+// same XCD.  Forward populations are stored shifted, f_i - w_i rho0 and
+// g_i - w_i T_ref, to keep FP32 resolution on the small deviations.
+
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "lbm_internal.h"
+
+namespace lbmadj {
+namespace {
+
+// ----------------------------------------------------------------------------
+// Velocity sets.  D3Q19 weights of Eq. (5); order: rest, the six axis
+// directions (+x,-x,+y,-y,+z,-z), then the twelve edge diagonals in opposite
+// pairs.  D3Q7 for temperature: rest 1/4, axes 1/8 (cs2 = 1/4).  In both sets
+// the axis direction with normal code c (+x 0, -x 1, ... -z 5) is index c + 1.
+// ----------------------------------------------------------------------------
+struct Q19 {
+  static constexpr int Q = 19;
+  static constexpr int ex[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+  static constexpr int ey[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+  static constexpr int ez[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+  static constexpr int opp[19] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
+  static constexpr float w[19] = {1.f / 3.f,  1.f / 18.f, 1.f / 18.f, 1.f / 18.f, 1.f / 18.f,
+                                  1.f / 18.f, 1.f / 18.f, 1.f / 36.f, 1.f / 36.f, 1.f / 36.f,
+                                  1.f / 36.f, 1.f / 36.f, 1.f / 36.f, 1.f / 36.f, 1.f / 36.f,
+                                  1.f / 36.f, 1.f / 36.f, 1.f / 36.f, 1.f / 36.f};
+};
+struct Q7 {
+  static constexpr int Q = 7;
+  static constexpr int ex[7] = {0, 1, -1, 0, 0, 0, 0};
+  static constexpr int ey[7] = {0, 0, 0, 1, -1, 0, 0};
+  static constexpr int ez[7] = {0, 0, 0, 0, 0, 1, -1};
+  static constexpr int opp[7] = {0, 2, 1, 4, 3, 6, 5};
+  static constexpr float w[7] = {0.25f, 0.125f, 0.125f, 0.125f, 0.125f, 0.125f, 0.125f};
+};
+
+template <int V>
+using ic = std::integral_constant<int, V>;
+
+// Compile-time loop: f(ic<0>), ..., f(ic<N-1>), so that every population
+// index is a constant and the arrays stay in registers.
+template <int I, int N, class F>
+__device__ __forceinline__ void sfor_impl(F& f) {
+  if constexpr (I < N) {
+    f(ic<I>{});
+    sfor_impl<I + 1, N>(f);
+  }
+}
+template <int N, class F>
+__device__ __forceinline__ void sfor(F&& f) {
+  sfor_impl<0, N>(f);
+}
+
+// Block index -> logical tile: blocks are dealt round-robin to the 8 XCDs,
+// so give each XCD a contiguous run of tiles (its L2 then sees the x/y
+// neighbour lines of adjacent tiles).
+__device__ __forceinline__ int remap_block(int b, const KParams& P) {
+  const int xcd = b & 7, idx = b >> 3;
+  return xcd < P.xcd_rem ? xcd * (P.xcd_per + 1) + idx
+                         : P.xcd_rem * (P.xcd_per + 1) + (xcd - P.xcd_rem) * P.xcd_per + idx;
+}
+
+// Neighbour coordinates of one node for offsets -1, 0, +1 along each axis,
+// wrapped on periodic axes and flagged invalid beyond a non-periodic face
+// (reads there return 0: only wall populations that point out of the box and
+// port unknowns, which the boundary rule overwrites, come from outside).
+struct Nbr {
+  int X[3], Yo[3], Zo[3];
+  bool vx[3], vy[3], vz[3];
+};
+
+__device__ __forceinline__ Nbr make_nbr(int x, int y, int z, const KParams& P) {
+  Nbr b;
+  b.X[1] = x;
+  b.vx[1] = true;
+  b.X[0] = x - 1;
+  b.vx[0] = true;
+  b.X[2] = x + 1;
+  b.vx[2] = true;
+  if (x == 0) {
+    if (P.px) b.X[0] = P.nx - 1; else b.vx[0] = false;
+  }
+  if (x == P.nx - 1) {
+    if (P.px) b.X[2] = 0; else b.vx[2] = false;
+  }
+  int Y[3] = {y - 1, y, y + 1};
+  b.vy[0] = b.vy[1] = b.vy[2] = true;
+  if (y == 0) {
+    if (P.py) Y[0] = P.ny - 1; else b.vy[0] = false;
+  }
+  if (y == P.ny - 1) {
+    if (P.py) Y[2] = 0; else b.vy[2] = false;
+  }
+  int Z[3] = {z - 1, z, z + 1};
+  b.vz[0] = b.vz[1] = b.vz[2] = true;
+  if (z == 0) {
+    if (P.pz) Z[0] = P.nz - 1; else b.vz[0] = false;
+  }
+  if (z == P.nz - 1) {
+    if (P.pz) Z[2] = 0; else b.vz[2] = false;
+  }
+  for (int k = 0; k < 3; ++k) {
+    b.Yo[k] = Y[k] * P.nx;
+    b.Zo[k] = Z[k] * P.plane;
+  }
+  return b;
+}
+
+// Value of plane `base` at node + (DX, DY, DZ), 0 outside the box.
+template <int DX, int DY, int DZ>
+__device__ __forceinline__ float load_nbr(const float* __restrict__ base, const Nbr& b, int n) {
+  const bool v = b.vx[DX + 1] && b.vy[DY + 1] && b.vz[DZ + 1];
+  const int s = v ? b.X[DX + 1] + b.Yo[DY + 1] + b.Zo[DZ + 1] : n;
+  const float r = base[s];
+  return v ? r : 0.0f;
+}
+
+// ---------------------------------------------------------------------------
+// Design parametrisation (see the header): chi, a_B, thermal tau and their
+// derivatives with respect to gamma.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float chi_of(float g, const KParams& P) {
+  return 1.0f - P.tab * (1.0f - g) / (P.qb + g);
+}
+__device__ __forceinline__ float khat_of(float g, const KParams& P) {
+  return P.kr + (1.0f - P.kr) * g / (1.0f + P.qr * (1.0f - g));
+}
+
+// Inward normal (nx, ny, nz) of normal code c (+x 0, -x 1, +y 2, -y 3, +z 4, -z 5).
+struct Normal {
+  int x, y, z;
+};
+__device__ __forceinline__ Normal normal_of(int c) {
+  Normal v;
+  v.x = (c == 0) - (c == 1);
+  v.y = (c == 2) - (c == 3);
+  v.z = (c == 4) - (c == 5);
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// Zou-He rule at a port with inward normal n (Eqs. 7, 8 generalised), on
+// shifted populations h = f - w rho0.  For unknown i (e_i.n > 0):
+//   h_i = h_ibar + 6 w_i j_n - 1/2 e_i.N,  N = sum_{e_j.n = 0} e_j h_j
+// (N has no normal component, so e_i.N is the sum over the tangential axes);
+// j_n = rho0 u_n at a velocity inlet, and at a pressure outlet rho = rho0
+// gives j_n = -sum_{e.n=0} h - 2 sum_{e.n<0} h.  Written with selects on the
+// runtime normal so the populations stay in registers.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void zou_he(float (&h)[19], Normal nv, bool inlet, float jn_in) {
+  float sT = 0.f, sO = 0.f, Nx = 0.f, Ny = 0.f, Nz = 0.f;
+  sfor<19>([&](auto I) {
+    constexpr int i = I;
+    const int c = Q19::ex[i] * nv.x + Q19::ey[i] * nv.y + Q19::ez[i] * nv.z;
+    const float t = (c == 0) ? h[i] : 0.f;
+    sT += t;
+    sO += (c < 0) ? h[i] : 0.f;
+    if constexpr (Q19::ex[i] != 0) Nx += float(Q19::ex[i]) * t;
+    if constexpr (Q19::ey[i] != 0) Ny += float(Q19::ey[i]) * t;
+    if constexpr (Q19::ez[i] != 0) Nz += float(Q19::ez[i]) * t;
+  });
+  const float jn = inlet ? jn_in : -(sT + 2.0f * sO);
+  float o[19];
+  sfor<19>([&](auto I) {
+    constexpr int i = I;
+    const int c = Q19::ex[i] * nv.x + Q19::ey[i] * nv.y + Q19::ez[i] * nv.z;
+    float v = h[Q19::opp[i]] + (6.0f * Q19::w[i]) * jn;
+    if constexpr (Q19::ex[i] != 0) v -= 0.5f * float(Q19::ex[i]) * Nx;
+    if constexpr (Q19::ey[i] != 0) v -= 0.5f * float(Q19::ey[i]) * Ny;
+    if constexpr (Q19::ez[i] != 0) v -= 0.5f * float(Q19::ez[i]) * Nz;
+    o[i] = (c > 0) ? v : h[i];
+  });
+  sfor<19>([&](auto I) { h[I] = o[I]; });
+}
+
+// Transpose of the rule above (Eq. 54 at a port; Eqs. 59, 60 in 2D), in place
+// on c = f*_C -> f*:  f*_i = 0 for unknown i; for tangential j
+//   f*_j = c_j - 1/2 e_j.P - [outlet] S6,
+// for outgoing j:  f*_j = c_j + c_jbar - [outlet] 2 S6,
+// with P = sum_{unknown i} e_i c_i and S6 = sum_{unknown i} 6 w_i c_i.
+__device__ __forceinline__ void zou_he_transpose(float (&c)[19], Normal nv, bool outlet) {
+  float S6 = 0.f, Px = 0.f, Py = 0.f, Pz = 0.f;
+  sfor<19>([&](auto I) {
+    constexpr int i = I;
+    const int cl = Q19::ex[i] * nv.x + Q19::ey[i] * nv.y + Q19::ez[i] * nv.z;
+    const float t = (cl > 0) ? c[i] : 0.f;
+    S6 += (6.0f * Q19::w[i]) * t;
+    if constexpr (Q19::ex[i] != 0) Px += float(Q19::ex[i]) * t;
+    if constexpr (Q19::ey[i] != 0) Py += float(Q19::ey[i]) * t;
+    if constexpr (Q19::ez[i] != 0) Pz += float(Q19::ez[i]) * t;
+  });
+  const float s6 = outlet ? S6 : 0.0f;
+  float o[19];
+  sfor<19>([&](auto I) {
+    constexpr int j = I;
+    const int cl = Q19::ex[j] * nv.x + Q19::ey[j] * nv.y + Q19::ez[j] * nv.z;
+    float tv = c[j] - s6;
+    if constexpr (Q19::ex[j] != 0) tv -= 0.5f * float(Q19::ex[j]) * Px;
+    if constexpr (Q19::ey[j] != 0) tv -= 0.5f * float(Q19::ey[j]) * Py;
+    if constexpr (Q19::ez[j] != 0) tv -= 0.5f * float(Q19::ez[j]) * Pz;
+    const float ov = c[j] + c[Q19::opp[j]] - 2.0f * s6;
+    o[j] = (cl == 0) ? tv : ((cl < 0) ? ov : 0.0f);
+  });
+  sfor<19>([&](auto I) { c[I] = o[I]; });
+}
+
+// ---------------------------------------------------------------------------
+// FP64 block reduction: wave64 shuffle tree, then the 4 wave partials in a
+// fixed order (deterministic), written to out[0..NV).
+// ---------------------------------------------------------------------------
+template <int NV>
+__device__ __forceinline__ void block_reduce_store(double (&acc)[NV], double* __restrict__ out) {
+  __shared__ double red[kBlock / 64][NV];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    double s = acc[v];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if (lane == 0) red[wave][v] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < NV) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < kBlock / 64; ++k) s += red[k][threadIdx.x];
+    out[threadIdx.x] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Forward step: pull (Eq. 37), boundary (Eqs. 7-9), collision (Eq. 36 with the
+// equilibrium of Eq. 12), plus the coupled D3Q7 step advected by the same
+// node's velocity.  DIAG additionally writes the macroscopic fields, the
+// thermal non-equilibrium populations and the residual partial sums.
+// ---------------------------------------------------------------------------
+template <bool THERMAL, bool DIAG>
+__global__ __launch_bounds__(kBlock) void k_forward(FwdArgs A) {
+  const KParams& P = A.P;
+  const int blk = remap_block(blockIdx.x, P);
+  const int n = blk * kBlock + threadIdx.x;
+  double acc[kRedFwd] = {0.0, 0.0, 0.0, 0.0};
+  if (n < P.N) {
+    const int x = n % P.nx, t = n / P.nx, y = t % P.ny, z = t / P.ny;
+    const Nbr nb = make_nbr(x, y, z, P);
+    const unsigned fl = A.flags[n];
+    const int kind = fl & 7, nc = (fl >> 3) & 7;
+    float h[19];
+    sfor<19>([&](auto I) {
+      constexpr int i = I;
+      h[i] = load_nbr<-Q19::ex[i], -Q19::ey[i], -Q19::ez[i]>(A.fin + (size_t)i * P.Np, nb, n);
+    });
+    float k[7];
+    if constexpr (THERMAL) {
+      sfor<7>([&](auto I) {
+        constexpr int i = I;
+        k[i] = load_nbr<-Q7::ex[i], -Q7::ey[i], -Q7::ez[i]>(A.gin + (size_t)i * P.Np, nb, n);
+      });
+      // zero-gradient outflow: the population along the inward normal takes
+      // the node's own post-collision value
+      if (kind == K_OUTLET) {
+        const int d = nc + 1;
+        const float own = A.gin[(size_t)d * P.Np + n];
+        sfor<7>([&](auto I) { k[I] = (I == d) ? own : k[I]; });
+      }
+    }
+    if (kind >= K_WALL) {
+      // full-way bounce-back, no collision (the heated wall adds q_w)
+      sfor<19>([&](auto I) {
+        constexpr int i = I;
+        A.fout[(size_t)i * P.Np + n] = h[Q19::opp[i]];
+      });
+      if constexpr (THERMAL) {
+        float ko[7];
+        sfor<7>([&](auto I) {
+          constexpr int i = I;
+          ko[i] = k[Q7::opp[i]];
+        });
+        if (kind == K_HEATED) {
+          const int d = nc + 1;
+          sfor<7>([&](auto I) { ko[I] += (I == d) ? P.q_w : 0.0f; });
+        }
+        sfor<7>([&](auto I) {
+          constexpr int i = I;
+          A.gout[(size_t)i * P.Np + n] = ko[i];
+        });
+      }
+      if constexpr (DIAG) {
+        A.drho[n] = 0.f;
+        A.u[n] = 0.f;
+        A.u[P.N + n] = 0.f;
+        A.u[2 * P.N + n] = 0.f;
+        if constexpr (THERMAL) {
+          A.T[n] = 0.f;
+          sfor<7>([&](auto I) { A.gneq[(size_t)I * P.Np + n] = 0.f; });
+        }
+      }
+    } else {
+      if (kind == K_INLET || kind == K_OUTLET) {
+        const float jn = (kind == K_INLET) ? A.uin[n] * P.rho0 : 0.f;
+        zou_he(h, normal_of(nc), kind == K_INLET, jn);
+      }
+      if constexpr (THERMAL) {
+        if (kind == K_INLET) {
+          // Dirichlet T = T_in by the sum rule on the inward-normal population
+          const int d = nc + 1;
+          float s = 0.f;
+          sfor<7>([&](auto J) { s += (J == d) ? 0.0f : k[J]; });
+          sfor<7>([&](auto J) { k[J] = (J == d) ? P.dT_in - s : k[J]; });
+        }
+      }
+      // moments of the post-boundary state (Eq. 6)
+      float drho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
+      sfor<19>([&](auto I) {
+        constexpr int i = I;
+        drho += h[i];
+        if constexpr (Q19::ex[i] != 0) jx += float(Q19::ex[i]) * h[i];
+        if constexpr (Q19::ey[i] != 0) jy += float(Q19::ey[i]) * h[i];
+        if constexpr (Q19::ez[i] != 0) jz += float(Q19::ez[i]) * h[i];
+      });
+      const float inv_rho0 = 1.0f / P.rho0;
+      const float ux = jx * inv_rho0, uy = jy * inv_rho0, uz = jz * inv_rho0;
+      float gam = 1.0f;
+      if (kind == K_DESIGN) gam = A.gamma[n];
+      const float chi = (kind == K_DESIGN) ? chi_of(gam, P) : 1.0f;
+      const float vx = chi * ux, vy = chi * uy, vz = chi * uz;
+      const float vv = vx * vx + vy * vy + vz * vz;
+      sfor<19>([&](auto I) {
+        constexpr int i = I;
+        const float eu = float(Q19::ex[i]) * vx + float(Q19::ey[i]) * vy + float(Q19::ez[i]) * vz;
+        const float heq = Q19::w[i] * (drho + P.rho0 * (3.0f * eu + 4.5f * eu * eu - 1.5f * vv));
+        A.fout[(size_t)i * P.Np + n] = h[i] + P.omega * (heq - h[i]);
+      });
+      float Tabs = 0.f;
+      if constexpr (THERMAL) {
+        float dT = 0.f;
+        sfor<7>([&](auto I) { dT += k[I]; });
+        Tabs = P.T_ref + dT;
+        const float tg = 0.5f + P.dfc * ((kind == K_DESIGN) ? khat_of(gam, P) : 1.0f);
+        const float og = 1.0f / tg;
+        sfor<7>([&](auto I) {
+          constexpr int i = I;
+          const float eu = float(Q7::ex[i]) * ux + float(Q7::ey[i]) * uy + float(Q7::ez[i]) * uz;
+          const float keq = Q7::w[i] * (dT + 4.0f * Tabs * eu);
+          A.gout[(size_t)i * P.Np + n] = k[i] + og * (keq - k[i]);
+          if constexpr (DIAG) A.gneq[(size_t)i * P.Np + n] = k[i] - keq;
+        });
+      }
+      if constexpr (DIAG) {
+        A.drho[n] = drho;
+        A.u[n] = ux;
+        A.u[P.N + n] = uy;
+        A.u[2 * P.N + n] = uz;
+        if constexpr (THERMAL) A.T[n] = Tabs;
+        acc[0] = sqrt((double)ux * ux + (double)uy * uy + (double)uz * uz);
+        acc[1] = (double)Tabs;
+        if (kind == K_INLET) acc[2] = (double)drho;
+        if (fl & kLayerBit) acc[3] = (double)Tabs;
+      }
+    }
+  }
+  if constexpr (DIAG) block_reduce_store<kRedFwd>(acc, A.partials + (size_t)blk * kRedFwd);
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint step (the paper's order reversed onto a pull kernel): reversed pull
+// a_i(x) = f*_i(x + e_i) (Eq. 61), adjoint collision minus the objective
+// source (Eq. 65), then the node's own adjoint boundary condition (Eq. 54),
+// so the stored state is f* = B^T f*_C.  The collision transpose is applied
+// matrix-free through moments: for the equilibrium of Eq. (12),
+//   sum_m a_m d feq_m / d f_i = M0 + e_i.V,  V = chi (3 M1 + 9 K - 3 M0 chi u),
+//   M0 = sum w a, M1 = sum w a e, K = sum w a (e.chi u) e;
+// the coupling from the thermal lattice adds e_i.W, W = 4 T/(tau_g rho0) sum w b e,
+// and the thermal transpose is (1 - 1/tau_g) b_i + (1/tau_g) sum w b (1 + 4 e.u).
+// ---------------------------------------------------------------------------
+template <bool THERMAL, int OBJ, bool DIAG>
+__global__ __launch_bounds__(kBlock) void k_adjoint(AdjArgs A) {
+  const KParams& P = A.P;
+  const int blk = remap_block(blockIdx.x, P);
+  const int n = blk * kBlock + threadIdx.x;
+  double acc[kRedAdj] = {0.0, 0.0};
+  if (n < P.N) {
+    const int x = n % P.nx, t = n / P.nx, y = t % P.ny, z = t / P.ny;
+    const Nbr nb = make_nbr(x, y, z, P);
+    const unsigned fl = A.flags[n];
+    const int kind = fl & 7, nc = (fl >> 3) & 7;
+    float a[19];
+    sfor<19>([&](auto I) {
+      constexpr int i = I;
+      a[i] = load_nbr<Q19::ex[i], Q19::ey[i], Q19::ez[i]>(A.ain + (size_t)i * P.Np, nb, n);
+    });
+    float b[7];
+    if constexpr (THERMAL) {
+      sfor<7>([&](auto I) {
+        constexpr int i = I;
+        b[i] = load_nbr<Q7::ex[i], Q7::ey[i], Q7::ez[i]>(A.bin + (size_t)i * P.Np, nb, n);
+      });
+      // transpose of the outflow self-copy
+      if (kind == K_OUTLET) {
+        const int d = nc + 1;
+        const float own = A.bin[(size_t)d * P.Np + n];
+        sfor<7>([&](auto I) { b[I] += (I == d) ? own : 0.0f; });
+      }
+    }
+    if constexpr (DIAG) {
+      if (kind < K_WALL) {
+        float mx = 0.f, my = 0.f, mz = 0.f;
+        sfor<19>([&](auto I) {
+          constexpr int i = I;
+          if constexpr (Q19::ex[i] != 0) mx += float(Q19::ex[i]) * a[i];
+          if constexpr (Q19::ey[i] != 0) my += float(Q19::ey[i]) * a[i];
+          if constexpr (Q19::ez[i] != 0) mz += float(Q19::ez[i]) * a[i];
+        });
+        acc[0] = sqrt((double)mx * mx + (double)my * my + (double)mz * mz);
+        if constexpr (THERMAL) {
+          float sb = 0.f;
+          sfor<7>([&](auto I) { sb += b[I]; });
+          acc[1] = fabs((double)sb);
+        }
+      }
+    }
+    if (kind >= K_WALL) {
+      sfor<19>([&](auto I) {
+        constexpr int i = I;
+        A.aout[(size_t)i * P.Np + n] = a[Q19::opp[i]];
+      });
+      if constexpr (THERMAL) {
+        sfor<7>([&](auto I) {
+          constexpr int i = I;
+          A.bout[(size_t)i * P.Np + n] = b[Q7::opp[i]];
+        });
+      }
+    } else {
+      const float ux = A.u[n], uy = A.u[P.N + n], uz = A.u[2 * P.N + n];
+      float gam = 1.0f;
+      if (kind == K_DESIGN) gam = A.gamma[n];
+      const float chi = (kind == K_DESIGN) ? chi_of(gam, P) : 1.0f;
+      const float vx = chi * ux, vy = chi * uy, vz = chi * uz;
+      float M0 = 0.f, M1x = 0.f, M1y = 0.f, M1z = 0.f, Kx = 0.f, Ky = 0.f, Kz = 0.f;
+      sfor<19>([&](auto I) {
+        constexpr int i = I;
+        const float wa = Q19::w[i] * a[i];
+        M0 += wa;
+        const float ev = float(Q19::ex[i]) * vx + float(Q19::ey[i]) * vy + float(Q19::ez[i]) * vz;
+        const float wae = wa * ev;
+        if constexpr (Q19::ex[i] != 0) { M1x += float(Q19::ex[i]) * wa; Kx += float(Q19::ex[i]) * wae; }
+        if constexpr (Q19::ey[i] != 0) { M1y += float(Q19::ey[i]) * wa; Ky += float(Q19::ey[i]) * wae; }
+        if constexpr (Q19::ez[i] != 0) { M1z += float(Q19::ez[i]) * wa; Kz += float(Q19::ez[i]) * wae; }
+      });
+      const float Vx = chi * (3.0f * M1x + 9.0f * Kx - 3.0f * M0 * vx);
+      const float Vy = chi * (3.0f * M1y + 9.0f * Ky - 3.0f * M0 * vy);
+      const float Vz = chi * (3.0f * M1z + 9.0f * Kz - 3.0f * M0 * vz);
+      float Wx = 0.f, Wy = 0.f, Wz = 0.f;
+      float Bg = 0.f, og = 0.f;
+      if constexpr (THERMAL) {
+        const float Tn = A.T[n];
+        const float tg = 0.5f + P.dfc * ((kind == K_DESIGN) ? khat_of(gam, P) : 1.0f);
+        og = 1.0f / tg;
+        float Sb = 0.f, Mbx = 0.f, Mby = 0.f, Mbz = 0.f;
+        sfor<7>([&](auto I) {
+          constexpr int i = I;
+          const float wb = Q7::w[i] * b[i];
+          Sb += wb;
+          if constexpr (Q7::ex[i] != 0) Mbx += float(Q7::ex[i]) * wb;
+          if constexpr (Q7::ey[i] != 0) Mby += float(Q7::ey[i]) * wb;
+          if constexpr (Q7::ez[i] != 0) Mbz += float(Q7::ez[i]) * wb;
+        });
+        Bg = Sb + 4.0f * (ux * Mbx + uy * Mby + uz * Mbz);
+        const float cW = 4.0f * og * Tn / P.rho0;
+        Wx = cW * Mbx;
+        Wy = cW * Mby;
+        Wz = cW * Mbz;
+      }
+      // objective sources dJ/df_i = c + e_i.G and dJ/dg_i = d
+      float csrc = 0.f, dsrc = 0.f, Gx = 0.f, Gy = 0.f, Gz = 0.f;
+      if constexpr (OBJ == OBJ_PRESSURE_DROP || OBJ == OBJ_HEATSINK) {
+        if (kind == K_INLET) csrc = P.c_in;
+      }
+      if constexpr (OBJ == OBJ_HEATSINK) {
+        if (fl & kLayerBit) dsrc = P.c_layer;
+      }
+      if constexpr (OBJ == OBJ_DISSIPATION) {
+        Gx = A.G[n];
+        Gy = A.G[(size_t)P.Np + n];
+        Gz = A.G[2 * (size_t)P.Np + n];
+      }
+      const float Sx = P.omega * Vx + Wx - Gx, Sy = P.omega * Vy + Wy - Gy,
+                  Sz = P.omega * Vz + Wz - Gz;
+      const float base = P.omega * M0 - csrc;
+      const float keep = 1.0f - P.omega;
+      float c[19];
+      sfor<19>([&](auto I) {
+        constexpr int i = I;
+        float v = keep * a[i] + base;
+        if constexpr (Q19::ex[i] != 0) v += float(Q19::ex[i]) * Sx;
+        if constexpr (Q19::ey[i] != 0) v += float(Q19::ey[i]) * Sy;
+        if constexpr (Q19::ez[i] != 0) v += float(Q19::ez[i]) * Sz;
+        c[i] = v;
+      });
+      if (kind == K_INLET || kind == K_OUTLET)
+        zou_he_transpose(c, normal_of(nc), kind == K_OUTLET);
+      sfor<19>([&](auto I) { A.aout[(size_t)I * P.Np + n] = c[I]; });
+      if constexpr (THERMAL) {
+        float cg[7];
+        const float bb = og * Bg - dsrc;
+        sfor<7>([&](auto I) {
+          constexpr int i = I;
+          cg[i] = (1.0f - og) * b[i] + bb;
+        });
+        if (kind == K_INLET) {
+          // transpose of the Dirichlet sum rule
+          const int d = nc + 1;
+          float cd = 0.f;
+          sfor<7>([&](auto J) { cd += (J == d) ? cg[J] : 0.0f; });
+          sfor<7>([&](auto J) { cg[J] = (J == d) ? 0.0f : cg[J] - cd; });
+        }
+        sfor<7>([&](auto I) { A.bout[(size_t)I * P.Np + n] = cg[I]; });
+      }
+    }
+  }
+  if constexpr (DIAG) block_reduce_store<kRedAdj>(acc, A.partials + (size_t)blk * kRedAdj);
+}
+
+// ---------------------------------------------------------------------------
+// Sensitivity, Eq. (66) with the exact derivative of the collision:
+// dJ/dgamma = explicit - (1/tau) chi' rho0 sum_i w_i a_i [3 e.u + 9 chi (e.u)^2
+// - 3 chi |u|^2] - (tau_g'/tau_g^2) sum_i b_i (g_i - geq_i), a, b the reversed
+// pulls of the final adjoint state.  Non-design nodes get 0.
+// ---------------------------------------------------------------------------
+template <bool THERMAL>
+__global__ __launch_bounds__(kBlock) void k_sensitivity(SensArgs A) {
+  const KParams& P = A.P;
+  const int blk = remap_block(blockIdx.x, P);
+  const int n = blk * kBlock + threadIdx.x;
+  double acc[kRedSens] = {0.0, 0.0};
+  if (n < P.N) {
+    const unsigned fl = A.flags[n];
+    const int kind = fl & 7;
+    float out = 0.0f;
+    if (kind == K_DESIGN) {
+      const int x = n % P.nx, t = n / P.nx, y = t % P.ny, z = t / P.ny;
+      const Nbr nb = make_nbr(x, y, z, P);
+      const float ux = A.u[n], uy = A.u[P.N + n], uz = A.u[2 * P.N + n];
+      const float gam = A.gamma[n];
+      const float chi = chi_of(gam, P);
+      const float qg = P.qb + gam;
+      const float dchi = P.tab * (1.0f + P.qb) / (qg * qg);
+      const float uu = ux * ux + uy * uy + uz * uz;
+      float s = 0.f;
+      sfor<19>([&](auto I) {
+        constexpr int i = I;
+        const float a = load_nbr<Q19::ex[i], Q19::ey[i], Q19::ez[i]>(A.ain + (size_t)i * P.Np, nb, n);
+        const float eu = float(Q19::ex[i]) * ux + float(Q19::ey[i]) * uy + float(Q19::ez[i]) * uz;
+        s += Q19::w[i] * a * (3.0f * eu + 9.0f * chi * eu * eu - 3.0f * chi * uu);
+      });
+      out = -P.omega * P.rho0 * dchi * s;
+      if constexpr (THERMAL) {
+        const float den = 1.0f + P.qr * (1.0f - gam);
+        const float kh = P.kr + (1.0f - P.kr) * gam / den;
+        const float dkh = (1.0f - P.kr) * (1.0f + P.qr) / (den * den);
+        const float tg = 0.5f + P.dfc * kh;
+        const float dtg = P.dfc * dkh;
+        float sg = 0.f;
+        sfor<7>([&](auto I) {
+          constexpr int i = I;
+          const float b = load_nbr<Q7::ex[i], Q7::ey[i], Q7::ez[i]>(A.bin + (size_t)i * P.Np, nb, n);
+          sg += b * A.gneq[(size_t)i * P.Np + n];
+        });
+        out -= dtg / (tg * tg) * sg;
+      }
+      if (A.objective == OBJ_DISSIPATION) {
+        const float dab = -P.amq * (1.0f + P.qb) / (qg * qg);
+        out += dab * P.rho0 * uu;
+      }
+    }
+    A.dJ[n] = out;
+    acc[0] = (double)out;
+    acc[1] = (double)out * out;
+  }
+  block_reduce_store<kRedSens>(acc, A.partials + (size_t)blk * kRedSens);
+}
+
+// ---------------------------------------------------------------------------
+// Dissipation objective: source G = dJ/du / rho0 per node and the value of J.
+// Edges join axis neighbours inside the box (no wrap) that are both non-wall.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_dissipation_source(const float* __restrict__ u,
+                                                               const float* __restrict__ gamma,
+                                                               const uint8_t* __restrict__ flags,
+                                                               float* __restrict__ G, KParams P) {
+  const int n = blockIdx.x * kBlock + threadIdx.x;
+  if (n >= P.N) return;
+  const int kind = flags[n] & 7;
+  float gx = 0.f, gy = 0.f, gz = 0.f;
+  if (kind < K_WALL) {
+    const int x = n % P.nx, t = n / P.nx, y = t % P.ny, z = t / P.ny;
+    const float ux = u[n], uy = u[P.N + n], uz = u[2 * P.N + n];
+    const int c[3] = {x, y, z}, lim[3] = {P.nx, P.ny, P.nz}, off[3] = {1, P.nx, P.plane};
+    for (int a = 0; a < 3; ++a) {
+      for (int s = -1; s <= 1; s += 2) {
+        const int cc = c[a] + s;
+        if (cc < 0 || cc >= lim[a]) continue;
+        const int m = n + s * off[a];
+        if ((flags[m] & 7) >= K_WALL) continue;
+        gx += P.two_nu * (ux - u[m]);
+        gy += P.two_nu * (uy - u[P.N + m]);
+        gz += P.two_nu * (uz - u[2 * P.N + m]);
+      }
+    }
+    if (kind == K_DESIGN) {
+      const float g = gamma[n];
+      const float ab = P.amq * (1.0f - g) / (P.qb + g);
+      gx += 2.0f * ab * ux;
+      gy += 2.0f * ab * uy;
+      gz += 2.0f * ab * uz;
+    }
+  }
+  G[n] = gx;
+  G[(size_t)P.Np + n] = gy;
+  G[2 * (size_t)P.Np + n] = gz;
+}
+
+__global__ __launch_bounds__(kBlock) void k_dissipation_objective(const float* __restrict__ u,
+                                                                  const float* __restrict__ gamma,
+                                                                  const uint8_t* __restrict__ flags,
+                                                                  double* __restrict__ partials,
+                                                                  KParams P) {
+  const int n = blockIdx.x * kBlock + threadIdx.x;
+  double acc[kRedDiss] = {0.0};
+  if (n < P.N) {
+    const int kind = flags[n] & 7;
+    if (kind < K_WALL) {
+      const int x = n % P.nx, t = n / P.nx, y = t % P.ny, z = t / P.ny;
+      const double ux = u[n], uy = u[P.N + n], uz = u[2 * P.N + n];
+      const int c[3] = {x, y, z}, lim[3] = {P.nx, P.ny, P.nz}, off[3] = {1, P.nx, P.plane};
+      double s = 0.0;
+      for (int a = 0; a < 3; ++a) {
+        if (c[a] + 1 >= lim[a]) continue;
+        const int m = n + off[a];
+        if ((flags[m] & 7) >= K_WALL) continue;
+        const double dx = u[m] - ux, dy = u[P.N + m] - uy, dz = u[2 * P.N + m] - uz;
+        s += (double)P.rho0 * (double)P.nu * (dx * dx + dy * dy + dz * dz);
+      }
+      if (kind == K_DESIGN) {
+        const double g = gamma[n];
+        const double ab = (double)P.amq * (1.0 - g) / ((double)P.qb + g);
+        s += ab * (double)P.rho0 * (ux * ux + uy * uy + uz * uz);
+      }
+      acc[0] = s;
+    }
+  }
+  block_reduce_store<kRedDiss>(acc, partials + (size_t)blockIdx.x * kRedDiss);
+}
+
+// Deterministic final sum of block partials (one block, fixed order).
+__global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict__ partials, int nblk,
+                                                     int nvals, double* __restrict__ out) {
+  __shared__ double sh[kBlock];
+  for (int v = 0; v < nvals; ++v) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nblk; i += kBlock) s += partials[(size_t)i * nvals + v];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int st = kBlock / 2; st > 0; st >>= 1) {
+      if (threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[v] = sh[0];
+    __syncthreads();
+  }
+}
+
+__global__ void k_fill(float* __restrict__ p, size_t count) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = 0.0f;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_fill(float* p, size_t count, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  const unsigned blocks = (unsigned)((count + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_fill, dim3(blocks), dim3(kBlock), 0, s, p, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_forward(const FwdArgs& a, bool thermal, bool diag, hipStream_t s) {
+  const dim3 grid(a.P.nblk), block(kBlock);
+  if (thermal) {
+    if (diag) hipLaunchKernelGGL((k_forward<true, true>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_forward<true, false>), grid, block, 0, s, a);
+  } else {
+    if (diag) hipLaunchKernelGGL((k_forward<false, true>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_forward<false, false>), grid, block, 0, s, a);
+  }
+  return hipGetLastError();
+}
+
+template <bool TH, int OBJ>
+static void adj_dispatch(const AdjArgs& a, bool diag, hipStream_t s) {
+  const dim3 grid(a.P.nblk), block(kBlock);
+  if (diag) hipLaunchKernelGGL((k_adjoint<TH, OBJ, true>), grid, block, 0, s, a);
+  else hipLaunchKernelGGL((k_adjoint<TH, OBJ, false>), grid, block, 0, s, a);
+}
+
+hipError_t launch_adjoint(const AdjArgs& a, bool thermal, int objective, bool diag, hipStream_t s) {
+  if (thermal) {
+    switch (objective) {
+      case OBJ_PRESSURE_DROP: adj_dispatch<true, OBJ_PRESSURE_DROP>(a, diag, s); break;
+      case OBJ_DISSIPATION: adj_dispatch<true, OBJ_DISSIPATION>(a, diag, s); break;
+      default: adj_dispatch<true, OBJ_HEATSINK>(a, diag, s); break;
+    }
+  } else {
+    switch (objective) {
+      case OBJ_PRESSURE_DROP: adj_dispatch<false, OBJ_PRESSURE_DROP>(a, diag, s); break;
+      default: adj_dispatch<false, OBJ_DISSIPATION>(a, diag, s); break;
+    }
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_sensitivity(const SensArgs& a, bool thermal, hipStream_t s) {
+  const dim3 grid(a.P.nblk), block(kBlock);
+  if (thermal) hipLaunchKernelGGL(k_sensitivity<true>, grid, block, 0, s, a);
+  else hipLaunchKernelGGL(k_sensitivity<false>, grid, block, 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_dissipation_source(const float* u, const float* gamma, const uint8_t* flags,
+                                     float* G, const KParams& P, hipStream_t s) {
+  hipLaunchKernelGGL(k_dissipation_source, dim3(P.nblk), dim3(kBlock), 0, s, u, gamma, flags, G, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_dissipation_objective(const float* u, const float* gamma, const uint8_t* flags,
+                                        double* partials, const KParams& P, hipStream_t s) {
+  hipLaunchKernelGGL(k_dissipation_objective, dim3(P.nblk), dim3(kBlock), 0, s, u, gamma, flags,
+                     partials, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const double* partials, int nblk, int nvals, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, partials, nblk, nvals, out);
+  return hipGetLastError();
+}
+
+void lattice_table(int which, int32_t* e, double* w) {
+  if (which == 0) {
+    for (int i = 0; i < 19; ++i) {
+      e[3 * i] = Q19::ex[i];
+      e[3 * i + 1] = Q19::ey[i];
+      e[3 * i + 2] = Q19::ez[i];
+      w[i] = (i == 0) ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);
+    }
+  } else {
+    for (int i = 0; i < 7; ++i) {
+      e[3 * i] = Q7::ex[i];
+      e[3 * i + 1] = Q7::ey[i];
+      e[3 * i + 2] = Q7::ez[i];
+      w[i] = (i == 0) ? 0.25 : 0.125;
+    }
+  }
+}
+
+}  // namespace lbmadj

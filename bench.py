@@ -9,8 +9,10 @@ update = both lattices at one node).
 
 The roofline entry is for the step kernel that takes most of the time: its
 algorithmic bytes per node-update times the node count, over its average
-launch duration, measured with HIP event pairs around every launch during the
-timed region.  The CPU baseline times the FP64 oracle on the host cores on a
+launch duration.  That duration is measured during the timed region with a
+pair of HIP events on the solve's stream around every forward and adjoint
+sweep: the step kernels of a sweep run back to back (rocprofv3 shows no gap
+between them), so sweep time over launches is the average launch duration.  The CPU baseline times the FP64 oracle on the host cores on a
 bounded sample of the same workload.
 """
 import argparse
@@ -47,8 +49,83 @@ def parse():
                              "heat_sink_320x160x80_Re200"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-fwd-steps", type=int, default=0,
-                    help="oracle sample size (0: pick ~15 s of work)")
+                    help="oracle sample size in forward steps (0: 48)")
+    ap.add_argument("--profile", action="store_true",
+                    help="profiling run for rocprofv3: a plain device copy of known size, then "
+                         "one forward + adjoint + sensitivity solve of --fixed-steps steps each")
+    ap.add_argument("--fixed-steps", type=int, default=200)
+    ap.add_argument("--copy-bw", action="store_true",
+                    help="measure device-to-device copy bandwidth (1 GiB, out of cache) and exit")
+    ap.add_argument("--no-kernel-timing", action="store_true",
+                    help="do not bracket the sweeps with HIP events")
     return ap.parse_args()
+
+
+def profile_run(args):
+    """Short fixed workload for kernel traces and HBM counters: two copies of a
+    256 MiB buffer (torch's copy kernel, whose FETCH_SIZE / WRITE_SIZE per
+    dispatch calibrate the counters), then one solve of exactly
+    --fixed-steps forward and adjoint steps."""
+    import torch
+    from paper_2501_02161_amd import lbm
+    torch.cuda.set_device(0)
+    src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    w = make_workload(args.workload).replace(max_steps=args.fixed_steps, tol=0.0,
+                                             check_every=1000)
+    prob = lbm.Problem(w, device="cuda:0")
+    res = prob.solve(w.gamma)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile": w.name, "nodes": w.N, "copy_bytes": src.numel() * 4,
+                      "fwd_steps": res["forward"]["steps"], "adj_steps": res["adjoint"]["steps"],
+                      "J": res["J"]}), flush=True)
+
+
+def copy_bandwidth():
+    """Best read+write bandwidth of torch's device copy on 1 GiB buffers."""
+    import torch
+    torch.cuda.set_device(0)
+    n = 256 * 1024 * 1024
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    best = 0.0
+    for _ in range(3):
+        b.copy_(a)
+    for _ in range(10):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        best = max(best, 2 * n * 4 / (e0.elapsed_time(e1) / 1e3) / 1e9)
+    print(json.dumps({"copy_GBps_read_plus_write": round(best, 1), "bytes": 2 * n * 4}), flush=True)
+
+
+COUNTERS = os.path.join(ROOT, "profiles", "hbm_counters_heat_sink_160x80x40_Re200.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2501_02161_amd", "csrc", "lbm_kernels.hip")
+
+
+def counter_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE scaled by the copy-kernel calibration),
+    or None if there is none for this workload or the kernels changed since."""
+    import hashlib
+    try:
+        with open(COUNTERS) as fh:
+            c = json.load(fh)
+        with open(KERNEL_SRC, "rb") as fh:
+            sha = hashlib.sha256(fh.read()).hexdigest()
+    except OSError:
+        return None
+    if c.get("workload") != workload or c.get("kernel_source_sha256") != sha:
+        return None
+    k = c["kernels"].get(kernel)
+    if not k:
+        return None
+    return int((k["fetch_kib"] * c["fetch_scale"] + k["write_kib"] * c["write_scale"]) * 1024)
 
 
 def make_workload(name):
@@ -89,6 +166,12 @@ def main():
               "a multi-GPU slab decomposition is not part of it.",
               file=sys.stderr)
         sys.exit(2)
+    if args.profile:
+        profile_run(args)
+        return
+    if args.copy_bw:
+        copy_bandwidth()
+        return
     import numpy as np
     import torch
     from paper_2501_02161_amd import lbm
@@ -110,7 +193,7 @@ def main():
     for _ in range(args.warmup):
         one()
     torch.cuda.synchronize()
-    lbm.lbm_set_kernel_timing(prob.h, True)
+    lbm.lbm_set_kernel_timing(prob.h, not args.no_kernel_timing)
     lbm.lbm_kernel_timing(prob.h, reset=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -127,14 +210,14 @@ def main():
     kernels = {"forward": (ms_f, n_f), "adjoint": (ms_a, n_a)}
     dom = max(kernels, key=lambda k: kernels[k][0])
     ms_tot, n_launch = kernels[dom]
-    avg_s = ms_tot / 1e3 / max(n_launch, 1)
     bpn = BYTES_PER_NODE[(dom, bool(w.thermal))]
-    achieved = bpn * w.N / avg_s / 1e9
-    per_kernel = {k: {"avg_us": round(v[0] * 1e3 / max(v[1], 1), 3), "launches": v[1],
-                      "bytes_per_node": BYTES_PER_NODE[(k, bool(w.thermal))],
-                      "GBps": round(BYTES_PER_NODE[(k, bool(w.thermal))] * w.N /
-                                    (v[0] / 1e3 / max(v[1], 1)) / 1e9, 1)}
-                  for k, v in kernels.items()}
+    achieved = bpn * w.N / (ms_tot / 1e3 / n_launch) / 1e9 if n_launch else None
+    per_kernel = {}
+    for k, (ms, n) in kernels.items():
+        b = BYTES_PER_NODE[(k, bool(w.thermal))]
+        per_kernel[k] = {"avg_us": round(ms * 1e3 / n, 3) if n else None, "launches": n,
+                         "bytes_per_node": b,
+                         "GBps": round(b * w.N / (ms / 1e3 / n) / 1e9, 1) if n else None}
     out = {
         "metric": METRIC,
         "value": round(mlups, 2),
@@ -152,9 +235,12 @@ def main():
                    "objective": "mean floor-layer T + 0.1 pressure drop", "tau": round(w.tau, 6),
                    "tol": w.tol, "max_steps": w.max_steps, "fwd_steps": fi["steps"],
                    "adj_steps": ai["steps"], "J": J},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None},
+        "roofline": {"bound": "hbm", "kernel": dom,
+                     "achieved": round(achieved, 1) if achieved else None,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
+                     "traffic": counter_traffic(w.name, dom),
+                     "algorithmic_bytes_per_launch": bpn * w.N},
         "kernels": per_kernel,
         "hbm_frac_whole_job": round(
             (BYTES_PER_NODE[("forward", bool(w.thermal))] * w.N * fi["steps"] +

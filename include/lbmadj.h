@@ -207,13 +207,15 @@ int lbm_sensitivity(lbm_problem_t* p, const float* gamma, const float* drho, con
  * condition.  Direction order is given by lbm_lattice. */
 int lbm_copy_state(const lbm_problem_t* p, int32_t which, float* dst, void* stream);
 
-/* Per-launch timing of the step kernels, for roofline reporting.  When
- * enabled, each forward and adjoint step kernel launch is bracketed by a pair
- * of HIP events on the call's stream; the durations are summed at every
- * residual check and at the end of each call.  lbm_kernel_timing returns the
- * totals (ms[0], launches[0]: forward step kernel; ms[1], launches[1]:
- * adjoint step kernel) and, if reset != 0, clears them.  Enabling creates
- * events on the bound device (needs a bound workspace). */
+/* Timing of the step kernels, for roofline reporting.  When enabled, each
+ * forward and each adjoint sweep (a solve or a continuation) is bracketed by
+ * a pair of HIP events on the call's stream; the step kernels of a sweep run
+ * back to back, so sweep time over its step-kernel launches is their average
+ * launch duration (the few residual reductions and host checks inside a
+ * sweep are included, well under 1 % of it).  lbm_kernel_timing returns the
+ * totals (ms[0], launches[0]: forward sweeps; ms[1], launches[1]: adjoint
+ * sweeps) and, if reset != 0, clears them.  Enabling creates two events on
+ * the bound device (needs a bound workspace). */
 int lbm_set_kernel_timing(lbm_problem_t* p, int32_t enable);
 int lbm_kernel_timing(lbm_problem_t* p, double* ms, int64_t* launches, int32_t reset);
 

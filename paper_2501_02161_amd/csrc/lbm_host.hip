@@ -75,11 +75,9 @@ struct lbm_problem {
   int fcur = 0, acur = 0;
   bool fwd_done = false, adj_done = false;
   double J = 0.0;
-  // per-launch kernel timing
+  // sweep timing: one event pair around each forward / adjoint sweep
   bool timing = false;
-  std::vector<hipEvent_t> ev_start, ev_stop;
-  std::vector<int> ev_kind;
-  int ev_used = 0;
+  hipEvent_t sweep_ev[2] = {nullptr, nullptr};
   double t_ms[2] = {0.0, 0.0};
   long long t_n[2] = {0, 0};
 };
@@ -271,38 +269,22 @@ int validate_and_setup(lbm_problem* p, const lbm_desc_t& d, const uint8_t* mask)
   return LBM_OK;
 }
 
-constexpr int kEventPool = 1024;
-
-// Sum the durations of the recorded event pairs (their stream is synchronised
-// by the caller or here) and recycle the pool.
-int drain_events(lbm_problem* p) {
-  if (!p->timing || p->ev_used == 0) return LBM_OK;
-  HIPCHK(hipEventSynchronize(p->ev_stop[p->ev_used - 1]));
-  for (int i = 0; i < p->ev_used; ++i) {
-    float ms = 0.f;
-    HIPCHK(hipEventElapsedTime(&ms, p->ev_start[i], p->ev_stop[i]));
-    p->t_ms[p->ev_kind[i]] += ms;
-    p->t_n[p->ev_kind[i]] += 1;
-  }
-  p->ev_used = 0;
+// Sweep timing: events before the first and after the last step kernel of a
+// sweep; the caller has synchronised the stream when sweep_end runs.
+int sweep_begin(lbm_problem* p, hipStream_t s) {
+  if (!p->timing) return LBM_OK;
+  HIPCHK(hipEventRecord(p->sweep_ev[0], s));
   return LBM_OK;
 }
 
-int timed_begin(lbm_problem* p, int kind, hipStream_t s) {
+int sweep_end(lbm_problem* p, int kind, int launches, hipStream_t s) {
   if (!p->timing) return LBM_OK;
-  if (p->ev_used == kEventPool) {
-    int rc = drain_events(p);
-    if (rc) return rc;
-  }
-  p->ev_kind[p->ev_used] = kind;
-  HIPCHK(hipEventRecord(p->ev_start[p->ev_used], s));
-  return LBM_OK;
-}
-
-int timed_end(lbm_problem* p, hipStream_t s) {
-  if (!p->timing) return LBM_OK;
-  HIPCHK(hipEventRecord(p->ev_stop[p->ev_used], s));
-  ++p->ev_used;
+  HIPCHK(hipEventRecord(p->sweep_ev[1], s));
+  HIPCHK(hipEventSynchronize(p->sweep_ev[1]));
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, p->sweep_ev[0], p->sweep_ev[1]));
+  p->t_ms[kind] += ms;
+  p->t_n[kind] += launches;
   return LBM_OK;
 }
 
@@ -362,19 +344,15 @@ int run_forward(lbm_problem* p, const float* gamma, float* drho, float* u, float
   double prev[2] = {0, 0}, res[2] = {0, 0}, mon[2] = {0, 0};
   bool have_prev = false;
   int status = LBM_NOT_CONVERGED, k = 0;
+  int rc0 = sweep_begin(p, s);
+  if (rc0) return rc0;
   for (k = 1; k <= nsteps; ++k) {
     const bool at_check = check > 0 && k % check == 0;
     const bool diag = at_check || k == nsteps;
-    int rc = timed_begin(p, 0, s);
-    if (rc) return rc;
     HIPCHK(launch_forward(fwd_args(p, gamma, drho, u, T), th, diag, s));
-    rc = timed_end(p, s);
-    if (rc) return rc;
     p->fcur = 1 - p->fcur;
     if (!diag) continue;
-    rc = read_sums(p, kRedFwd, s);
-    if (rc) return rc;
-    rc = drain_events(p);
+    int rc = read_sums(p, kRedFwd, s);
     if (rc) return rc;
     mon[0] = p->pinned[0] / p->n_nonwall;
     mon[1] = p->pinned[1] / p->n_nonwall;
@@ -399,8 +377,10 @@ int run_forward(lbm_problem* p, const float* gamma, float* drho, float* u, float
       have_prev = true;
     }
   }
+  int rc = sweep_end(p, 0, std::min(k, nsteps), s);
+  if (rc) return rc;
   double J = 0.0;
-  int rc = objective_value(p, gamma, u, s, &J);
+  rc = objective_value(p, gamma, u, s, &J);
   if (rc) return rc;
   p->J = J;
   p->fwd_done = true;
@@ -439,19 +419,15 @@ int run_adjoint(lbm_problem* p, const float* gamma, const float* u, const float*
   double prev[2] = {0, 0}, res[2] = {0, 0}, mon[2] = {0, 0};
   bool have_prev = false;
   int status = LBM_NOT_CONVERGED, k = 0;
+  int rc0 = sweep_begin(p, s);
+  if (rc0) return rc0;
   for (k = 1; k <= nsteps; ++k) {
     const bool at_check = check > 0 && k % check == 0;
     const bool diag = at_check || k == nsteps;
-    int rc = timed_begin(p, 1, s);
-    if (rc) return rc;
     HIPCHK(launch_adjoint(adj_args(p, gamma, u, T), th, p->d.objective, diag, s));
-    rc = timed_end(p, s);
-    if (rc) return rc;
     p->acur = 1 - p->acur;
     if (!diag) continue;
-    rc = read_sums(p, kRedAdj, s);
-    if (rc) return rc;
-    rc = drain_events(p);
+    int rc = read_sums(p, kRedAdj, s);
     if (rc) return rc;
     mon[0] = p->pinned[0] / p->n_nonwall;
     mon[1] = p->pinned[1] / p->n_nonwall;
@@ -473,6 +449,8 @@ int run_adjoint(lbm_problem* p, const float* gamma, const float* u, const float*
       have_prev = true;
     }
   }
+  int rc = sweep_end(p, 1, std::min(k, nsteps), s);
+  if (rc) return rc;
   p->adj_done = true;
   if (info) {
     info->steps = std::min(k, nsteps);
@@ -680,18 +658,9 @@ int lbm_set_kernel_timing(lbm_problem_t* p, int32_t enable) {
   int rc = check_bound(p);
   if (rc) return rc;
   DeviceGuard guard(p->dev);
-  if (enable && p->ev_start.empty()) {
-    p->ev_start.resize(kEventPool);
-    p->ev_stop.resize(kEventPool);
-    p->ev_kind.resize(kEventPool);
-    for (int i = 0; i < kEventPool; ++i) {
-      HIPCHK(hipEventCreate(&p->ev_start[i]));
-      HIPCHK(hipEventCreate(&p->ev_stop[i]));
-    }
-  }
-  if (!enable) {
-    rc = drain_events(p);
-    if (rc) return rc;
+  if (enable && !p->sweep_ev[0]) {
+    HIPCHK(hipEventCreate(&p->sweep_ev[0]));
+    HIPCHK(hipEventCreate(&p->sweep_ev[1]));
   }
   p->timing = enable != 0;
   return LBM_OK;
@@ -700,11 +669,6 @@ int lbm_set_kernel_timing(lbm_problem_t* p, int32_t enable) {
 int lbm_kernel_timing(lbm_problem_t* p, double* ms, int64_t* launches, int32_t reset) {
   g_err.clear();
   if (!p || !ms || !launches) return fail(LBM_EINVAL, "null argument");
-  if (p->timing) {
-    DeviceGuard guard(p->dev);
-    int rc = drain_events(p);
-    if (rc) return rc;
-  }
   for (int k = 0; k < 2; ++k) {
     ms[k] = p->t_ms[k];
     launches[k] = p->t_n[k];
@@ -724,12 +688,10 @@ int lbm_lattice(int32_t which, int32_t* e, double* w) {
 
 void lbm_problem_destroy(lbm_problem_t* p) {
   if (!p) return;
-  if (p->dev >= 0 && !p->ev_start.empty()) {
+  if (p->dev >= 0 && p->sweep_ev[0]) {
     DeviceGuard guard(p->dev);
-    for (size_t i = 0; i < p->ev_start.size(); ++i) {
-      (void)hipEventDestroy(p->ev_start[i]);
-      (void)hipEventDestroy(p->ev_stop[i]);
-    }
+    (void)hipEventDestroy(p->sweep_ev[0]);
+    (void)hipEventDestroy(p->sweep_ev[1]);
   }
   if (p->pinned) (void)hipHostFree(p->pinned);
   delete p;

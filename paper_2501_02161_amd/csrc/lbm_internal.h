@@ -89,8 +89,12 @@ struct SensArgs {
 
 // Launchers (return the hipError_t of the launch).
 hipError_t launch_fill(float* p, size_t count, hipStream_t s);
-hipError_t launch_forward(const FwdArgs& a, bool thermal, bool diag, hipStream_t s);
-hipError_t launch_adjoint(const AdjArgs& a, bool thermal, int objective, bool diag, hipStream_t s);
+// Step kernels; with non-null events the launch records them at the start and
+// end of the kernel itself (hipExtLaunchKernelGGL), for per-launch timing.
+hipError_t launch_forward(const FwdArgs& a, bool thermal, bool diag, hipStream_t s,
+                          hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+hipError_t launch_adjoint(const AdjArgs& a, bool thermal, int objective, bool diag, hipStream_t s,
+                          hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 hipError_t launch_sensitivity(const SensArgs& a, bool thermal, hipStream_t s);
 hipError_t launch_dissipation_source(const float* u, const float* gamma, const uint8_t* flags,
                                      float* G, const KParams& P, hipStream_t s);

@@ -14,6 +14,7 @@
 // same XCD.  Forward populations are stored shifted, f_i - w_i rho0 and
 // g_i - w_i T_ref, to keep FP32 resolution on the small deviations.
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -30,7 +31,6 @@ namespace {
 // the axis direction with normal code c (+x 0, -x 1, ... -z 5) is index c + 1.
 // ----------------------------------------------------------------------------
 struct Q19 {
-  static constexpr int Q = 19;
   static constexpr int ex[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
   static constexpr int ey[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
   static constexpr int ez[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
@@ -41,7 +41,6 @@ struct Q19 {
                                   1.f / 36.f, 1.f / 36.f, 1.f / 36.f, 1.f / 36.f};
 };
 struct Q7 {
-  static constexpr int Q = 7;
   static constexpr int ex[7] = {0, 1, -1, 0, 0, 0, 0};
   static constexpr int ey[7] = {0, 0, 0, 1, -1, 0, 0};
   static constexpr int ez[7] = {0, 0, 0, 0, 0, 1, -1};
@@ -702,36 +701,46 @@ hipError_t launch_fill(float* p, size_t count, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_forward(const FwdArgs& a, bool thermal, bool diag, hipStream_t s) {
-  const dim3 grid(a.P.nblk), block(kBlock);
+// Launch `kern` plainly, or with start/stop events stamped by the dispatch.
+template <class K, class A>
+static void launch_step(K kern, int nblk, const A& a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+  if (ev0 && ev1)
+    hipExtLaunchKernelGGL(kern, dim3(nblk), dim3(kBlock), 0, s, ev0, ev1, 0, a);
+  else
+    hipLaunchKernelGGL(kern, dim3(nblk), dim3(kBlock), 0, s, a);
+}
+
+hipError_t launch_forward(const FwdArgs& a, bool thermal, bool diag, hipStream_t s, hipEvent_t ev0,
+                          hipEvent_t ev1) {
+  const int nb = a.P.nblk;
   if (thermal) {
-    if (diag) hipLaunchKernelGGL((k_forward<true, true>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((k_forward<true, false>), grid, block, 0, s, a);
+    if (diag) launch_step(k_forward<true, true>, nb, a, s, ev0, ev1);
+    else launch_step(k_forward<true, false>, nb, a, s, ev0, ev1);
   } else {
-    if (diag) hipLaunchKernelGGL((k_forward<false, true>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((k_forward<false, false>), grid, block, 0, s, a);
+    if (diag) launch_step(k_forward<false, true>, nb, a, s, ev0, ev1);
+    else launch_step(k_forward<false, false>, nb, a, s, ev0, ev1);
   }
   return hipGetLastError();
 }
 
 template <bool TH, int OBJ>
-static void adj_dispatch(const AdjArgs& a, bool diag, hipStream_t s) {
-  const dim3 grid(a.P.nblk), block(kBlock);
-  if (diag) hipLaunchKernelGGL((k_adjoint<TH, OBJ, true>), grid, block, 0, s, a);
-  else hipLaunchKernelGGL((k_adjoint<TH, OBJ, false>), grid, block, 0, s, a);
+static void adj_dispatch(const AdjArgs& a, bool diag, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+  if (diag) launch_step(k_adjoint<TH, OBJ, true>, a.P.nblk, a, s, ev0, ev1);
+  else launch_step(k_adjoint<TH, OBJ, false>, a.P.nblk, a, s, ev0, ev1);
 }
 
-hipError_t launch_adjoint(const AdjArgs& a, bool thermal, int objective, bool diag, hipStream_t s) {
+hipError_t launch_adjoint(const AdjArgs& a, bool thermal, int objective, bool diag, hipStream_t s,
+                          hipEvent_t ev0, hipEvent_t ev1) {
   if (thermal) {
     switch (objective) {
-      case OBJ_PRESSURE_DROP: adj_dispatch<true, OBJ_PRESSURE_DROP>(a, diag, s); break;
-      case OBJ_DISSIPATION: adj_dispatch<true, OBJ_DISSIPATION>(a, diag, s); break;
-      default: adj_dispatch<true, OBJ_HEATSINK>(a, diag, s); break;
+      case OBJ_PRESSURE_DROP: adj_dispatch<true, OBJ_PRESSURE_DROP>(a, diag, s, ev0, ev1); break;
+      case OBJ_DISSIPATION: adj_dispatch<true, OBJ_DISSIPATION>(a, diag, s, ev0, ev1); break;
+      default: adj_dispatch<true, OBJ_HEATSINK>(a, diag, s, ev0, ev1); break;
     }
   } else {
     switch (objective) {
-      case OBJ_PRESSURE_DROP: adj_dispatch<false, OBJ_PRESSURE_DROP>(a, diag, s); break;
-      default: adj_dispatch<false, OBJ_DISSIPATION>(a, diag, s); break;
+      case OBJ_PRESSURE_DROP: adj_dispatch<false, OBJ_PRESSURE_DROP>(a, diag, s, ev0, ev1); break;
+      default: adj_dispatch<false, OBJ_DISSIPATION>(a, diag, s, ev0, ev1); break;
     }
   }
   return hipGetLastError();

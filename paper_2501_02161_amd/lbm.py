@@ -184,6 +184,7 @@ def lbm_copy_state(p, which: int, dst, stream=None) -> None:
 
 
 def lbm_set_kernel_timing(p, enable: bool) -> None:
+    """Bracket every forward / adjoint sweep with HIP events (see the header)."""
     _check(load_library().lbm_set_kernel_timing(p, int(bool(enable))))
 
 

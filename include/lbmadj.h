@@ -178,12 +178,26 @@ int lbm_forward_continue(lbm_problem_t* p, const float* gamma, int32_t nsteps, f
  * solve, starting from f*_C = 0 (Eq. 53).  gamma, u (device [3][N]) and T
  * (device [N], NULL without thermal) must be the ones that forward solve used
  * and returned; drho may be NULL (the incompressible equilibrium's Jacobian
- * does not depend on rho).  The thermal part also reads the non-equilibrium
- * thermal populations the forward solve left in the workspace.  info may be
- * NULL.  Returns LBM_OK, LBM_NOT_CONVERGED or an error (LBM_ESTATE without a
- * forward solve). */
+ * does not depend on rho).  With the thermal lattice, the sensitivity also
+ * needs the converged thermal non-equilibrium populations, which the last
+ * lbm_forward_solve or lbm_thermal_resolve left in the workspace; without
+ * one of them the call returns LBM_ESTATE.  A flow-only adjoint needs
+ * nothing but (gamma, u).  info may be NULL.  Returns LBM_OK,
+ * LBM_NOT_CONVERGED or an error. */
 int lbm_adjoint_solve(lbm_problem_t* p, const float* gamma, const float* drho, const float* u,
                       const float* T, lbm_info_t* info, void* stream);
+
+/* Recover the converged thermal non-equilibrium populations from saved fields
+ * only (for callers that keep gamma, u, T and not the populations, such as a
+ * differentiable wrapper): the D3Q7 lattice is solved alone with u frozen,
+ * from g = g_eq(T, u), to the residual criterion on mean T (desc tol,
+ * check_every, max_steps).  At a converged forward state this is the same
+ * linear fixed point.  Afterwards lbm_adjoint_solve may run; the forward flow
+ * state is no longer available (lbm_forward_continue returns LBM_ESTATE) and
+ * the J reported by later calls is NaN.  LBM_EINVAL without the thermal
+ * lattice. */
+int lbm_thermal_resolve(lbm_problem_t* p, const float* gamma, const float* u, const float* T,
+                        lbm_info_t* info, void* stream);
 
 /* Run exactly nsteps more adjoint steps from the current adjoint state. */
 int lbm_adjoint_continue(lbm_problem_t* p, const float* gamma, const float* drho,
@@ -222,6 +236,78 @@ int lbm_kernel_timing(lbm_problem_t* p, double* ms, int64_t* launches, int32_t r
 /* Direction table of the library: which 0 = D3Q19 (19 entries), 1 = D3Q7
  * (7 entries); e receives 3 ints per direction, w the weight. */
 int lbm_lattice(int32_t which, int32_t* e, double* w);
+
+/* ---------------------------------------------------------------------------
+ * Continuous batching of many sensitivity solves (serving).
+ *
+ * A batch engine holds requests of one kind (thermal flag and objective) on
+ * one GPU.  lbm_batch_submit queues a request (descriptor, host mask, host
+ * design field; all copied).  Each lbm_batch_step call first admits queued
+ * requests in arrival order while a slot is free and the request's workspace
+ * and fields fit in the arena the caller bound (the HBM budget); then one
+ * ragged-batch kernel launch per lattice step advances every resident
+ * request by one step of its forward or adjoint sweep, `quantum` times;
+ * then every request's residual is checked and requests move from the
+ * forward sweep to the adjoint sweep to dJ/dgamma exactly as
+ * lbm_forward_solve / lbm_adjoint_solve / lbm_sensitivity would, so each
+ * result is bit for bit the result of the same request solved alone.  A
+ * request's max_steps and check_every must be multiples of the quantum.
+ * lbm_batch_poll reports a ticket's state; once DONE or FAILED it returns
+ * the result (copying dJ/dgamma to dJ_host, N floats, if non-NULL) and
+ * releases the request's memory.  A request whose sweep diverges is FAILED
+ * with status LBM_EDIVERGED and does not affect the others.  The arena is
+ * caller-owned device memory; it must outlive the engine.  One host thread
+ * at a time per engine.
+ * ------------------------------------------------------------------------- */
+#define LBM_BATCH_QUEUED 0
+#define LBM_BATCH_RUNNING 1
+#define LBM_BATCH_DONE 2
+#define LBM_BATCH_FAILED 3
+
+typedef struct lbm_batch lbm_batch_t;
+
+typedef struct lbm_batch_result {
+  int64_t ticket;
+  int32_t state;           /* LBM_BATCH_*                                      */
+  int32_t status;          /* LBM_OK, LBM_NOT_CONVERGED or LBM_EDIVERGED        */
+  int32_t nodes;           /* N of the request                                  */
+  int32_t fwd_steps;       /* steps taken (so far) by the forward sweep         */
+  int32_t adj_steps;       /* steps taken (so far) by the adjoint sweep         */
+  int32_t reserved;
+  double J;                /* objective (DONE only)                             */
+} lbm_batch_result_t;
+
+typedef struct lbm_batch_stats {
+  uint64_t arena_bytes;    /* usable arena (budget)                             */
+  uint64_t bytes_in_use;   /* held by resident requests                         */
+  int32_t running, finished, queued, reserved;
+  int64_t launches;        /* ragged-batch kernel launches so far               */
+  int64_t node_updates;    /* node-steps advanced so far                        */
+} lbm_batch_stats_t;
+
+/* Engine for requests with this thermal flag and objective; at most
+ * max_slots resident requests; quantum = steps between admission and
+ * residual checks.  LBM_EINVAL on bad parameters. */
+int lbm_batch_create(int32_t thermal, int32_t objective, int32_t max_slots, int32_t quantum,
+                     lbm_batch_t** out);
+/* Bytes of the arena taken by the engine's own tables for an arena of
+ * arena_bytes (the rest is the budget for requests). */
+size_t lbm_batch_table_bytes(const lbm_batch_t* b, size_t arena_bytes);
+/* Bind caller-owned device memory as the arena (current device). */
+int lbm_batch_bind_arena(lbm_batch_t* b, void* device_ptr, size_t bytes);
+/* Queue a request; validates it (LBM_EINVAL, or LBM_ENOMEM if it can never
+ * fit the arena) and returns its ticket. */
+int lbm_batch_submit(lbm_batch_t* b, const lbm_desc_t* desc, const uint8_t* mask,
+                     const float* gamma_host, int64_t* ticket);
+/* Admit, advance every resident request by one quantum of steps, check
+ * residuals and move phases; synchronises `stream`.  active/queued (may be
+ * NULL) receive the resident running requests and the queue length. */
+int lbm_batch_step(lbm_batch_t* b, void* stream, int32_t* active, int32_t* queued);
+/* State of a ticket; DONE/FAILED results are returned once and released. */
+int lbm_batch_poll(lbm_batch_t* b, int64_t ticket, lbm_batch_result_t* res, float* dJ_host,
+                   void* stream);
+int lbm_batch_stats(const lbm_batch_t* b, lbm_batch_stats_t* out);
+void lbm_batch_destroy(lbm_batch_t* b);
 
 /* Release the handle (not the caller's workspace). */
 void lbm_problem_destroy(lbm_problem_t* p);

@@ -362,6 +362,11 @@ class Oracle:
                 "fsC": ad["fsC"], "gsC": ad["gsC"]}
 
 
+def set_threads(n: int) -> None:
+    """OpenMP threads for oracle calls made from the calling host thread."""
+    _load().orc_set_threads(int(n))
+
+
 def threads_used() -> int:
     """Threads the oracle's OpenMP loops use in this process."""
     n = os.environ.get("OMP_NUM_THREADS")

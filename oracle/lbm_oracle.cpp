@@ -34,6 +34,10 @@
 #include <string>
 #include <vector>
 
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
 namespace {
 
 using cplx = std::complex<double>;
@@ -994,6 +998,16 @@ thread_local std::string g_err;
 extern "C" {
 
 const char* orc_last_error() { return g_err.c_str(); }
+
+// Threads of the OpenMP loops started from the calling thread (the harness
+// runs independent small solves in parallel host threads with 1 each).
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
 
 void* orc_create(const OrcConfig* c, const uint8_t* mask) {
   Problem* P = new Problem();

@@ -11,7 +11,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = [os.path.join(HERE, "csrc", "lbm_kernels.hip"), os.path.join(HERE, "csrc", "lbm_host.hip")]
+SOURCES = [os.path.join(HERE, "csrc", n) for n in ("lbm_kernels.hip", "lbm_host.hip", "lbm_batch.hip")]
 HEADERS = [os.path.join(ROOT, "include", "lbmadj.h"), os.path.join(HERE, "csrc", "lbm_internal.h")]
 LIB = os.path.join(HERE, "_build", "liblbmadj.so")
 ARCH = os.environ.get("LBMADJ_ARCH", "gfx950")

@@ -17,79 +17,18 @@
 
 using namespace lbmadj;
 
-namespace {
+namespace lbmadj {
 
-thread_local std::string g_err;
-
-int fail(int code, const std::string& msg) {
-  g_err = msg;
-  return code;
+std::string& last_error() {
+  thread_local std::string err;
+  return err;
 }
 
-#define HIPCHK(expr)                                                                        \
-  do {                                                                                      \
-    hipError_t e_ = (expr);                                                                 \
-    if (e_ != hipSuccess)                                                                   \
-      return fail(LBM_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));          \
-  } while (0)
+}  // namespace lbmadj
 
-const int NVEC[6][3] = {{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
-
-size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
-
-struct DeviceGuard {
-  int prev = -1;
-  explicit DeviceGuard(int dev) {
-    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-    if (prev != dev) (void)hipSetDevice(dev);
-  }
-  ~DeviceGuard() {
-    if (prev >= 0) (void)hipSetDevice(prev);
-  }
-};
-
-}  // namespace
-
-struct lbm_problem {
-  lbm_desc_t d{};
-  int N = 0, Np = 0, nblk = 0;
-  std::vector<uint8_t> flags_host;
-  std::vector<float> uin_host;
-  int n_inlet = 0, n_layer = 0, n_nonwall = 0;
-  KParams kp{};
-  // workspace
-  char* ws = nullptr;
-  size_t ws_bytes = 0;
-  int dev = -1;
-  float* f[2] = {nullptr, nullptr};
-  float* g[2] = {nullptr, nullptr};
-  float* a[2] = {nullptr, nullptr};
-  float* b[2] = {nullptr, nullptr};
-  float* gneq = nullptr;
-  float* G = nullptr;
-  float* uin = nullptr;
-  uint8_t* flags = nullptr;
-  double* partials = nullptr;
-  double* sums = nullptr;
-  double* pinned = nullptr;
-  int fcur = 0, acur = 0;
-  bool fwd_done = false, adj_done = false;
-  double J = 0.0;
-  // sweep timing: one event pair around each forward / adjoint sweep
-  bool timing = false;
-  hipEvent_t sweep_ev[2] = {nullptr, nullptr};
-  double t_ms[2] = {0.0, 0.0};
-  long long t_n[2] = {0, 0};
-};
-
-namespace {
+namespace lbmadj {
 
 bool thermal_of(const lbm_problem* p) { return p->d.thermal != 0; }
-
-// Layout of the workspace: offsets of every region (256-byte aligned).
-struct Layout {
-  size_t f[2], g[2], a[2], b[2], gneq, G, uin, flags, partials, sums, total;
-};
 
 Layout layout_of(const lbm_problem* p) {
   Layout L{};
@@ -178,7 +117,7 @@ int validate_and_setup(lbm_problem* p, const lbm_desc_t& d, const uint8_t* mask)
     }
     if (kind == K_HEATED) {
       for (int a = 0; a < 3; ++a) {
-        const int cc = c[a] + NVEC[nc][a];
+        const int cc = c[a] + NVEC_HOST[nc][a];
         if (cc < 0 || cc >= lim[a]) return fail(LBM_EINVAL, "heated wall normal points out of the box");
       }
     }
@@ -193,7 +132,7 @@ int validate_and_setup(lbm_problem* p, const lbm_desc_t& d, const uint8_t* mask)
       const int nc = (p->flags_host[n] >> 3) & 7;
       int c[3];
       coords(n, c);
-      const long long m = (c[0] + NVEC[nc][0]) + (long long)nx * ((c[1] + NVEC[nc][1]) + (long long)ny * (c[2] + NVEC[nc][2]));
+      const long long m = (c[0] + NVEC_HOST[nc][0]) + (long long)nx * ((c[1] + NVEC_HOST[nc][1]) + (long long)ny * (c[2] + NVEC_HOST[nc][2]));
       if ((mask[m] & 7) < K_WALL) p->flags_host[m] |= (uint8_t)kLayerBit;
     }
   }
@@ -229,7 +168,7 @@ int validate_and_setup(lbm_problem* p, const lbm_desc_t& d, const uint8_t* mask)
       coords(n, c);
       double prof = 1.0;
       for (int a = 0; a < 3; ++a) {
-        if (NVEC[code][a] != 0) continue;
+        if (NVEC_HOST[code][a] != 0) continue;
         if (lo[a] == 0 && hi[a] == lim[a] - 1) continue;
         const double s = (c[a] - lo[a] + 0.5) / double(hi[a] - lo[a] + 1);
         prof *= 4.0 * s * (1.0 - s);
@@ -358,6 +297,7 @@ int run_forward(lbm_problem* p, const float* gamma, float* drho, float* u, float
     mon[1] = p->pinned[1] / p->n_nonwall;
     if (!std::isfinite(mon[0]) || !std::isfinite(mon[1])) {
       p->fwd_done = false;
+      p->have_gneq = false;
       return fail(LBM_EDIVERGED, "forward solve diverged at step " + std::to_string(k));
     }
     if (at_check) {
@@ -384,6 +324,7 @@ int run_forward(lbm_problem* p, const float* gamma, float* drho, float* u, float
   if (rc) return rc;
   p->J = J;
   p->fwd_done = true;
+  p->have_gneq = true;
   p->adj_done = false;
   if (info) {
     info->steps = std::min(k, nsteps);
@@ -464,20 +405,81 @@ int run_adjoint(lbm_problem* p, const float* gamma, const float* u, const float*
   return status;
 }
 
+// Thermal lattice alone with the velocity frozen, from g_eq(T, u), until the
+// mean-T residual criterion or nsteps.
+int run_thermal(lbm_problem* p, const float* gamma, const float* u, const float* T, int nsteps,
+                int check, double tol, hipStream_t s, lbm_info_t* info) {
+  ThermArgs A{};
+  A.flags = p->flags;
+  A.gamma = gamma;
+  A.u = u;
+  A.T = T;
+  A.gneq = p->gneq;
+  A.partials = p->partials;
+  A.P = p->kp;
+  A.gout = p->g[0];
+  HIPCHK(launch_thermal_init(A, s));
+  p->fcur = 0;
+  double prev = 0, res = 0, mon = 0;
+  bool have_prev = false;
+  int status = LBM_NOT_CONVERGED, k = 0;
+  for (k = 1; k <= nsteps; ++k) {
+    const bool at_check = check > 0 && k % check == 0;
+    const bool diag = at_check || k == nsteps;
+    A.gin = p->g[p->fcur];
+    A.gout = p->g[1 - p->fcur];
+    HIPCHK(launch_thermal(A, diag, s));
+    p->fcur = 1 - p->fcur;
+    if (!diag) continue;
+    int rc = read_sums(p, kRedFwd, s);
+    if (rc) return rc;
+    mon = p->pinned[1] / p->n_nonwall;
+    if (!std::isfinite(mon)) {
+      p->have_gneq = false;
+      return fail(LBM_EDIVERGED, "thermal re-solve diverged at step " + std::to_string(k));
+    }
+    if (at_check) {
+      if (have_prev) {
+        res = std::fabs(mon - prev) / std::max(std::fabs(mon), 1e-300);
+        if (rel_converged(mon, prev, tol)) {
+          status = LBM_OK;
+          break;
+        }
+      }
+      prev = mon;
+      have_prev = true;
+    }
+  }
+  p->have_gneq = true;
+  p->fwd_done = false;  // the flow populations are not a forward state any more
+  p->adj_done = false;
+  p->J = std::nan("");
+  if (info) {
+    info->steps = std::min(k, nsteps);
+    info->status = status;
+    info->residual[0] = 0.0;
+    info->residual[1] = res;
+    info->monitor[0] = 0.0;
+    info->monitor[1] = mon;
+    info->J = p->J;
+  }
+  return status;
+}
+
 int check_bound(const lbm_problem* p) {
   if (!p) return fail(LBM_EINVAL, "problem is NULL");
   if (!p->ws) return fail(LBM_ESTATE, "no workspace bound");
   return LBM_OK;
 }
 
-}  // namespace
+}  // namespace lbmadj
 
 extern "C" {
 
-const char* lbm_last_error(void) { return g_err.c_str(); }
+const char* lbm_last_error(void) { return last_error().c_str(); }
 
 int lbm_problem_create(const lbm_desc_t* desc, const uint8_t* mask, lbm_problem_t** out) {
-  g_err.clear();
+  last_error().clear();
   if (!desc || !out) return fail(LBM_EINVAL, "desc or out is NULL");
   *out = nullptr;
   lbm_problem* p = nullptr;
@@ -506,7 +508,7 @@ size_t lbm_workspace_bytes(const lbm_problem_t* p) {
 }
 
 int lbm_bind_workspace(lbm_problem_t* p, void* device_ptr, size_t bytes) {
-  g_err.clear();
+  last_error().clear();
   if (!p || !device_ptr) return fail(LBM_EINVAL, "problem or workspace is NULL");
   const Layout L = layout_of(p);
   if (bytes < L.total) return fail(LBM_EINVAL, "workspace too small");
@@ -540,13 +542,13 @@ int lbm_bind_workspace(lbm_problem_t* p, void* device_ptr, size_t bytes) {
 
 int lbm_forward_solve(lbm_problem_t* p, const float* gamma, float* drho, float* u, float* T,
                       lbm_info_t* info, void* stream) {
-  g_err.clear();
+  last_error().clear();
   int rc = check_bound(p);
   if (rc) return rc;
   if (!gamma || !drho || !u || (thermal_of(p) && !T)) return fail(LBM_EINVAL, "null field pointer");
   DeviceGuard guard(p->dev);
   hipStream_t s = (hipStream_t)stream;
-  p->fwd_done = p->adj_done = false;
+  p->fwd_done = p->adj_done = p->have_gneq = false;
   p->fcur = 0;
   HIPCHK(launch_fill(p->f[0], (size_t)19 * p->Np, s));
   if (thermal_of(p)) HIPCHK(launch_fill(p->g[0], (size_t)7 * p->Np, s));
@@ -555,7 +557,7 @@ int lbm_forward_solve(lbm_problem_t* p, const float* gamma, float* drho, float* 
 
 int lbm_forward_continue(lbm_problem_t* p, const float* gamma, int32_t nsteps, float* drho,
                          float* u, float* T, lbm_info_t* info, void* stream) {
-  g_err.clear();
+  last_error().clear();
   int rc = check_bound(p);
   if (rc) return rc;
   if (!p->fwd_done) return fail(LBM_ESTATE, "no forward state to continue");
@@ -568,10 +570,11 @@ int lbm_forward_continue(lbm_problem_t* p, const float* gamma, int32_t nsteps, f
 int lbm_adjoint_solve(lbm_problem_t* p, const float* gamma, const float* drho, const float* u,
                       const float* T, lbm_info_t* info, void* stream) {
   (void)drho;
-  g_err.clear();
+  last_error().clear();
   int rc = check_bound(p);
   if (rc) return rc;
-  if (!p->fwd_done) return fail(LBM_ESTATE, "adjoint solve needs a forward solve first");
+  if (thermal_of(p) && !p->have_gneq)
+    return fail(LBM_ESTATE, "adjoint solve needs lbm_forward_solve or lbm_thermal_resolve first");
   if (!gamma || !u || (thermal_of(p) && !T)) return fail(LBM_EINVAL, "null field pointer");
   DeviceGuard guard(p->dev);
   hipStream_t s = (hipStream_t)stream;
@@ -584,10 +587,22 @@ int lbm_adjoint_solve(lbm_problem_t* p, const float* gamma, const float* drho, c
   return run_adjoint(p, gamma, u, T, p->d.max_steps, p->d.check_every, p->d.tol, s, info);
 }
 
+int lbm_thermal_resolve(lbm_problem_t* p, const float* gamma, const float* u, const float* T,
+                        lbm_info_t* info, void* stream) {
+  last_error().clear();
+  int rc = check_bound(p);
+  if (rc) return rc;
+  if (!thermal_of(p)) return fail(LBM_EINVAL, "the problem has no thermal lattice");
+  if (!gamma || !u || !T) return fail(LBM_EINVAL, "null field pointer");
+  DeviceGuard guard(p->dev);
+  return run_thermal(p, gamma, u, T, p->d.max_steps, p->d.check_every, p->d.tol, (hipStream_t)stream,
+                     info);
+}
+
 int lbm_adjoint_continue(lbm_problem_t* p, const float* gamma, const float* drho, const float* u,
                          const float* T, int32_t nsteps, lbm_info_t* info, void* stream) {
   (void)drho;
-  g_err.clear();
+  last_error().clear();
   int rc = check_bound(p);
   if (rc) return rc;
   if (!p->adj_done) return fail(LBM_ESTATE, "no adjoint state to continue");
@@ -603,7 +618,7 @@ int lbm_adjoint_continue(lbm_problem_t* p, const float* gamma, const float* drho
 int lbm_sensitivity(lbm_problem_t* p, const float* gamma, const float* drho, const float* u,
                     const float* T, float* dJdgamma, double* J, void* stream) {
   (void)drho;
-  g_err.clear();
+  last_error().clear();
   int rc = check_bound(p);
   if (rc) return rc;
   if (!p->adj_done) return fail(LBM_ESTATE, "sensitivity needs an adjoint solve first");
@@ -630,7 +645,7 @@ int lbm_sensitivity(lbm_problem_t* p, const float* gamma, const float* drho, con
 }
 
 int lbm_copy_state(const lbm_problem_t* p, int32_t which, float* dst, void* stream) {
-  g_err.clear();
+  last_error().clear();
   int rc = check_bound(p);
   if (rc) return rc;
   if (!dst) return fail(LBM_EINVAL, "dst is NULL");
@@ -654,7 +669,7 @@ int lbm_copy_state(const lbm_problem_t* p, int32_t which, float* dst, void* stre
 }
 
 int lbm_set_kernel_timing(lbm_problem_t* p, int32_t enable) {
-  g_err.clear();
+  last_error().clear();
   int rc = check_bound(p);
   if (rc) return rc;
   DeviceGuard guard(p->dev);
@@ -667,7 +682,7 @@ int lbm_set_kernel_timing(lbm_problem_t* p, int32_t enable) {
 }
 
 int lbm_kernel_timing(lbm_problem_t* p, double* ms, int64_t* launches, int32_t reset) {
-  g_err.clear();
+  last_error().clear();
   if (!p || !ms || !launches) return fail(LBM_EINVAL, "null argument");
   for (int k = 0; k < 2; ++k) {
     ms[k] = p->t_ms[k];

@@ -6,6 +6,10 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <string>
+#include <vector>
+
+#include "lbmadj.h"
 
 namespace lbmadj {
 
@@ -87,6 +91,36 @@ struct SensArgs {
   KParams P;
 };
 
+// Thermal lattice alone, advected by a frozen velocity field.
+struct ThermArgs {
+  const float* gin;
+  float* gout;
+  const uint8_t* flags;
+  const float* gamma;
+  const float* u;       // [3][N] frozen velocity
+  const float* T;       // [N] initial temperature (init kernel only)
+  float* gneq;          // 7 x Np (diagnostic step)
+  double* partials;
+  KParams P;
+};
+
+// Ragged batch: one slot per resident problem, one tile per 256-node block of
+// a slot.  A batch launch advances every slot in the forward or adjoint phase
+// by one step; the slot's step in its phase is (launch - start), the A/B
+// buffers alternate with its parity (even steps read buffer 0).
+struct SlotDev {
+  int phase;        // 0 idle, 1 forward, 2 adjoint
+  int start;        // launch index of the phase's first step
+  int max_steps;
+  int check;        // residual check period (0: only the last step)
+  FwdArgs fa;       // fin/gin = buffer 0, fout/gout = buffer 1
+  AdjArgs aa;       // ain/bin = buffer 0, aout/bout = buffer 1
+};
+struct Tile {
+  int slot;
+  int blk;
+};
+
 // Launchers (return the hipError_t of the launch).
 hipError_t launch_fill(float* p, size_t count, hipStream_t s);
 // Step kernels; with non-null events the launch records them at the start and
@@ -96,14 +130,101 @@ hipError_t launch_forward(const FwdArgs& a, bool thermal, bool diag, hipStream_t
 hipError_t launch_adjoint(const AdjArgs& a, bool thermal, int objective, bool diag, hipStream_t s,
                           hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 hipError_t launch_sensitivity(const SensArgs& a, bool thermal, hipStream_t s);
+hipError_t launch_thermal(const ThermArgs& a, bool diag, hipStream_t s);
+hipError_t launch_thermal_init(const ThermArgs& a, hipStream_t s);
 hipError_t launch_dissipation_source(const float* u, const float* gamma, const uint8_t* flags,
                                      float* G, const KParams& P, hipStream_t s);
 hipError_t launch_dissipation_objective(const float* u, const float* gamma, const uint8_t* flags,
                                         double* partials, const KParams& P, hipStream_t s);
 hipError_t launch_finalize(const double* partials, int nblk, int nvals, double* out,
                            hipStream_t s);
+hipError_t launch_batch(const Tile* tiles, int ntiles, const SlotDev* slots, int launch,
+                        bool thermal, int objective, hipStream_t s);
+// Per-slot residual sums of the slots' last diagnostic step: out[slot * 4 + v].
+hipError_t launch_finalize_slots(const SlotDev* slots, int nslots, double* out, hipStream_t s);
 
 // Host-side copies of the direction tables (for lbm_lattice).
 void lattice_table(int which, int32_t* e, double* w);
+
+// ---------------------------------------------------------------------------
+// Host-side helpers shared by the single-problem ABI and the batch engine.
+// ---------------------------------------------------------------------------
+std::string& last_error();
+inline int fail(int code, const std::string& msg) {
+  last_error() = msg;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                        \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      return ::lbmadj::fail(LBM_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr int NVEC_HOST[6][3] = {{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
+
+inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+}  // namespace lbmadj
+
+// One lattice problem: validated description, host-side node data and the
+// pointers into its bound workspace.
+struct lbm_problem {
+  lbm_desc_t d{};
+  int N = 0, Np = 0, nblk = 0;
+  std::vector<uint8_t> flags_host;
+  std::vector<float> uin_host;
+  int n_inlet = 0, n_layer = 0, n_nonwall = 0;
+  lbmadj::KParams kp{};
+  // workspace
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  int dev = -1;
+  float* f[2] = {nullptr, nullptr};
+  float* g[2] = {nullptr, nullptr};
+  float* a[2] = {nullptr, nullptr};
+  float* b[2] = {nullptr, nullptr};
+  float* gneq = nullptr;
+  float* G = nullptr;
+  float* uin = nullptr;
+  uint8_t* flags = nullptr;
+  double* partials = nullptr;
+  double* sums = nullptr;
+  double* pinned = nullptr;
+  int fcur = 0, acur = 0;
+  bool fwd_done = false, adj_done = false;
+  bool have_gneq = false;  // thermal non-equilibrium of a converged state in the workspace
+  double J = 0.0;
+  // sweep timing: one event pair around each forward / adjoint sweep
+  bool timing = false;
+  hipEvent_t sweep_ev[2] = {nullptr, nullptr};
+  double t_ms[2] = {0.0, 0.0};
+  long long t_n[2] = {0, 0};
+};
+
+namespace lbmadj {
+
+// Workspace regions of a problem (byte offsets, 256-byte aligned).
+struct Layout {
+  size_t f[2], g[2], a[2], b[2], gneq, G, uin, flags, partials, sums, total;
+};
+Layout layout_of(const lbm_problem* p);
+bool thermal_of(const lbm_problem* p);
+int validate_and_setup(lbm_problem* p, const lbm_desc_t& d, const uint8_t* mask);
+FwdArgs fwd_args(lbm_problem* p, const float* gamma, float* drho, float* u, float* T);
+AdjArgs adj_args(lbm_problem* p, const float* gamma, const float* u, const float* T);
+bool rel_converged(double now, double before, double tol);
 
 }  // namespace lbmadj

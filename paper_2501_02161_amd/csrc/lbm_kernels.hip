@@ -249,9 +249,8 @@ __device__ __forceinline__ void block_reduce_store(double (&acc)[NV], double* __
 // thermal non-equilibrium populations and the residual partial sums.
 // ---------------------------------------------------------------------------
 template <bool THERMAL, bool DIAG>
-__global__ __launch_bounds__(kBlock) void k_forward(FwdArgs A) {
+__device__ __forceinline__ void forward_tile(const FwdArgs& A, int blk) {
   const KParams& P = A.P;
-  const int blk = remap_block(blockIdx.x, P);
   const int n = blk * kBlock + threadIdx.x;
   double acc[kRedFwd] = {0.0, 0.0, 0.0, 0.0};
   if (n < P.N) {
@@ -376,6 +375,11 @@ __global__ __launch_bounds__(kBlock) void k_forward(FwdArgs A) {
   if constexpr (DIAG) block_reduce_store<kRedFwd>(acc, A.partials + (size_t)blk * kRedFwd);
 }
 
+template <bool THERMAL, bool DIAG>
+__global__ __launch_bounds__(kBlock) void k_forward(FwdArgs A) {
+  forward_tile<THERMAL, DIAG>(A, remap_block(blockIdx.x, A.P));
+}
+
 // ---------------------------------------------------------------------------
 // Adjoint step (the paper's order reversed onto a pull kernel): reversed pull
 // a_i(x) = f*_i(x + e_i) (Eq. 61), adjoint collision minus the objective
@@ -388,9 +392,8 @@ __global__ __launch_bounds__(kBlock) void k_forward(FwdArgs A) {
 // and the thermal transpose is (1 - 1/tau_g) b_i + (1/tau_g) sum w b (1 + 4 e.u).
 // ---------------------------------------------------------------------------
 template <bool THERMAL, int OBJ, bool DIAG>
-__global__ __launch_bounds__(kBlock) void k_adjoint(AdjArgs A) {
+__device__ __forceinline__ void adjoint_tile(const AdjArgs& A, int blk) {
   const KParams& P = A.P;
-  const int blk = remap_block(blockIdx.x, P);
   const int n = blk * kBlock + threadIdx.x;
   double acc[kRedAdj] = {0.0, 0.0};
   if (n < P.N) {
@@ -535,6 +538,11 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(AdjArgs A) {
   if constexpr (DIAG) block_reduce_store<kRedAdj>(acc, A.partials + (size_t)blk * kRedAdj);
 }
 
+template <bool THERMAL, int OBJ, bool DIAG>
+__global__ __launch_bounds__(kBlock) void k_adjoint(AdjArgs A) {
+  adjoint_tile<THERMAL, OBJ, DIAG>(A, remap_block(blockIdx.x, A.P));
+}
+
 // ---------------------------------------------------------------------------
 // Sensitivity, Eq. (66) with the exact derivative of the collision:
 // dJ/dgamma = explicit - (1/tau) chi' rho0 sum_i w_i a_i [3 e.u + 9 chi (e.u)^2
@@ -667,8 +675,8 @@ __global__ __launch_bounds__(kBlock) void k_dissipation_objective(const float* _
 }
 
 // Deterministic final sum of block partials (one block, fixed order).
-__global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict__ partials, int nblk,
-                                                     int nvals, double* __restrict__ out) {
+__device__ __forceinline__ void finalize_block(const double* __restrict__ partials, int nblk, int nvals,
+                                               double* __restrict__ out) {
   __shared__ double sh[kBlock];
   for (int v = 0; v < nvals; ++v) {
     double s = 0.0;
@@ -682,6 +690,138 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict__ 
     if (threadIdx.x == 0) out[v] = sh[0];
     __syncthreads();
   }
+}
+
+__global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict__ partials, int nblk,
+                                                     int nvals, double* __restrict__ out) {
+  finalize_block(partials, nblk, nvals, out);
+}
+
+// One block per slot; the forward phase reduces 4 sums, the adjoint phase 2.
+__global__ __launch_bounds__(kBlock) void k_finalize_slots(const SlotDev* __restrict__ slots,
+                                                           double* __restrict__ out) {
+  const SlotDev& S = slots[blockIdx.x];
+  if (S.phase == 0) return;
+  const int nvals = S.phase == 1 ? kRedFwd : kRedAdj;
+  finalize_block(S.fa.partials, S.fa.P.nblk, nvals, out + (size_t)blockIdx.x * 4);
+}
+
+// Ragged-batch step: block -> tile (XCD-contiguous runs of tiles) -> slot ->
+// the slot's forward or adjoint step on that tile, with the same tile code as
+// the single-problem kernels, so a slot computes bit for bit what it would
+// alone.
+template <bool THERMAL, int OBJ>
+__global__ __launch_bounds__(kBlock) void k_batch(const Tile* __restrict__ tiles,
+                                                  const SlotDev* __restrict__ slots, int launch,
+                                                  int xper, int xrem) {
+  const int b = blockIdx.x, xcd = b & 7, idx = b >> 3;
+  const int t = xcd < xrem ? xcd * (xper + 1) + idx : xrem * (xper + 1) + (xcd - xrem) * xper + idx;
+  const Tile tl = tiles[t];
+  const SlotDev& S = slots[tl.slot];
+  const int phase = S.phase;
+  const int k = launch - S.start;
+  if (phase == 0 || k < 0 || k >= S.max_steps) return;  // uniform over the block
+  const bool diag = (S.check > 0 && (k + 1) % S.check == 0) || (k + 1 == S.max_steps);
+  const bool odd = (k & 1) != 0;
+  if (phase == 1) {
+    FwdArgs A = S.fa;
+    if (odd) {
+      A.fin = S.fa.fout;
+      A.fout = const_cast<float*>(S.fa.fin);
+      A.gin = S.fa.gout;
+      A.gout = const_cast<float*>(S.fa.gin);
+    }
+    if (diag) forward_tile<THERMAL, true>(A, tl.blk);
+    else forward_tile<THERMAL, false>(A, tl.blk);
+  } else {
+    AdjArgs A = S.aa;
+    if (odd) {
+      A.ain = S.aa.aout;
+      A.aout = const_cast<float*>(S.aa.ain);
+      A.bin = S.aa.bout;
+      A.bout = const_cast<float*>(S.aa.bin);
+    }
+    if (diag) adjoint_tile<THERMAL, OBJ, true>(A, tl.blk);
+    else adjoint_tile<THERMAL, OBJ, false>(A, tl.blk);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Thermal lattice alone with the velocity frozen (a saved field): the D3Q7 part
+// of the forward step, used to recover the converged thermal non-equilibrium
+// populations from (u, T) only.  Same pull, boundary rules and collision as
+// the coupled kernel; DIAG writes g - g_eq and the mean-T partial sums.
+// ---------------------------------------------------------------------------
+template <bool DIAG>
+__global__ __launch_bounds__(kBlock) void k_thermal(ThermArgs A) {
+  const KParams& P = A.P;
+  const int blk = remap_block(blockIdx.x, P);
+  const int n = blk * kBlock + threadIdx.x;
+  double acc[kRedFwd] = {0.0, 0.0, 0.0, 0.0};
+  if (n < P.N) {
+    const int x = n % P.nx, t = n / P.nx, y = t % P.ny, z = t / P.ny;
+    const Nbr nb = make_nbr(x, y, z, P);
+    const unsigned fl = A.flags[n];
+    const int kind = fl & 7, nc = (fl >> 3) & 7;
+    float k[7];
+    sfor<7>([&](auto I) {
+      constexpr int i = I;
+      k[i] = load_nbr<-Q7::ex[i], -Q7::ey[i], -Q7::ez[i]>(A.gin + (size_t)i * P.Np, nb, n);
+    });
+    const int d = nc + 1;
+    if (kind == K_OUTLET) {
+      const float own = A.gin[(size_t)d * P.Np + n];
+      sfor<7>([&](auto I) { k[I] = (I == d) ? own : k[I]; });
+    }
+    if (kind >= K_WALL) {
+      float ko[7];
+      sfor<7>([&](auto I) { ko[I] = k[Q7::opp[I]]; });
+      if (kind == K_HEATED) sfor<7>([&](auto I) { ko[I] += (I == d) ? P.q_w : 0.0f; });
+      sfor<7>([&](auto I) { A.gout[(size_t)I * P.Np + n] = ko[I]; });
+      if constexpr (DIAG) sfor<7>([&](auto I) { A.gneq[(size_t)I * P.Np + n] = 0.f; });
+    } else {
+      if (kind == K_INLET) {
+        float s = 0.f;
+        sfor<7>([&](auto J) { s += (J == d) ? 0.0f : k[J]; });
+        sfor<7>([&](auto J) { k[J] = (J == d) ? P.dT_in - s : k[J]; });
+      }
+      const float ux = A.u[n], uy = A.u[P.N + n], uz = A.u[2 * P.N + n];
+      float dT = 0.f;
+      sfor<7>([&](auto I) { dT += k[I]; });
+      const float Tabs = P.T_ref + dT;
+      const float tg = 0.5f + P.dfc * ((kind == K_DESIGN) ? khat_of(A.gamma[n], P) : 1.0f);
+      const float og = 1.0f / tg;
+      sfor<7>([&](auto I) {
+        constexpr int i = I;
+        const float eu = float(Q7::ex[i]) * ux + float(Q7::ey[i]) * uy + float(Q7::ez[i]) * uz;
+        const float keq = Q7::w[i] * (dT + 4.0f * Tabs * eu);
+        A.gout[(size_t)i * P.Np + n] = k[i] + og * (keq - k[i]);
+        if constexpr (DIAG) A.gneq[(size_t)i * P.Np + n] = k[i] - keq;
+      });
+      if constexpr (DIAG) {
+        acc[1] = (double)Tabs;
+        if (fl & kLayerBit) acc[3] = (double)Tabs;
+      }
+    }
+  }
+  if constexpr (DIAG) block_reduce_store<kRedFwd>(acc, A.partials + (size_t)blk * kRedFwd);
+}
+
+// Initial thermal state g = g_eq(T, u) (stored shifted by w T_ref) at
+// non-wall nodes, 0 (that is w T_ref) at walls.
+__global__ __launch_bounds__(kBlock) void k_thermal_init(ThermArgs A) {
+  const KParams& P = A.P;
+  const int n = blockIdx.x * kBlock + threadIdx.x;
+  if (n >= P.N) return;
+  const int kind = A.flags[n] & 7;
+  const float ux = A.u[n], uy = A.u[P.N + n], uz = A.u[2 * P.N + n];
+  const float Tabs = A.T[n];
+  sfor<7>([&](auto I) {
+    constexpr int i = I;
+    const float eu = float(Q7::ex[i]) * ux + float(Q7::ey[i]) * uy + float(Q7::ez[i]) * uz;
+    const float keq = Q7::w[i] * ((Tabs - P.T_ref) + 4.0f * Tabs * eu);
+    A.gout[(size_t)i * P.Np + n] = (kind >= K_WALL) ? 0.0f : keq;
+  });
 }
 
 __global__ void k_fill(float* __restrict__ p, size_t count) {
@@ -753,6 +893,17 @@ hipError_t launch_sensitivity(const SensArgs& a, bool thermal, hipStream_t s) {
   return hipGetLastError();
 }
 
+hipError_t launch_thermal(const ThermArgs& a, bool diag, hipStream_t s) {
+  if (diag) hipLaunchKernelGGL(k_thermal<true>, dim3(a.P.nblk), dim3(kBlock), 0, s, a);
+  else hipLaunchKernelGGL(k_thermal<false>, dim3(a.P.nblk), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_thermal_init(const ThermArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_thermal_init, dim3(a.P.nblk), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_dissipation_source(const float* u, const float* gamma, const uint8_t* flags,
                                      float* G, const KParams& P, hipStream_t s) {
   hipLaunchKernelGGL(k_dissipation_source, dim3(P.nblk), dim3(kBlock), 0, s, u, gamma, flags, G, P);
@@ -768,6 +919,42 @@ hipError_t launch_dissipation_objective(const float* u, const float* gamma, cons
 
 hipError_t launch_finalize(const double* partials, int nblk, int nvals, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, partials, nblk, nvals, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch(const Tile* tiles, int ntiles, const SlotDev* slots, int launch,
+                        bool thermal, int objective, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  const int xper = ntiles / 8, xrem = ntiles % 8;
+  const dim3 grid(ntiles), block(kBlock);
+  if (thermal) {
+    switch (objective) {
+      case OBJ_PRESSURE_DROP:
+        hipLaunchKernelGGL((k_batch<true, OBJ_PRESSURE_DROP>), grid, block, 0, s, tiles, slots, launch, xper, xrem);
+        break;
+      case OBJ_DISSIPATION:
+        hipLaunchKernelGGL((k_batch<true, OBJ_DISSIPATION>), grid, block, 0, s, tiles, slots, launch, xper, xrem);
+        break;
+      default:
+        hipLaunchKernelGGL((k_batch<true, OBJ_HEATSINK>), grid, block, 0, s, tiles, slots, launch, xper, xrem);
+        break;
+    }
+  } else {
+    switch (objective) {
+      case OBJ_PRESSURE_DROP:
+        hipLaunchKernelGGL((k_batch<false, OBJ_PRESSURE_DROP>), grid, block, 0, s, tiles, slots, launch, xper, xrem);
+        break;
+      default:
+        hipLaunchKernelGGL((k_batch<false, OBJ_DISSIPATION>), grid, block, 0, s, tiles, slots, launch, xper, xrem);
+        break;
+    }
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize_slots(const SlotDev* slots, int nslots, double* out, hipStream_t s) {
+  if (nslots <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_finalize_slots, dim3(nslots), dim3(kBlock), 0, s, slots, out);
   return hipGetLastError();
 }
 

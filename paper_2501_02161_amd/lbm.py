@@ -53,10 +53,28 @@ class lbm_info_t(ctypes.Structure):
                 "monitor": [float(self.monitor[0]), float(self.monitor[1])], "J": float(self.J)}
 
 
+class lbm_batch_result_t(ctypes.Structure):
+    _fields_ = [("ticket", ctypes.c_int64), ("state", c_int32), ("status", c_int32),
+                ("nodes", c_int32), ("fwd_steps", c_int32), ("adj_steps", c_int32),
+                ("reserved", c_int32), ("J", c_double)]
+
+
+class lbm_batch_stats_t(ctypes.Structure):
+    _fields_ = [("arena_bytes", ctypes.c_uint64), ("bytes_in_use", ctypes.c_uint64),
+                ("running", c_int32), ("finished", c_int32), ("queued", c_int32),
+                ("reserved", c_int32), ("launches", ctypes.c_int64),
+                ("node_updates", ctypes.c_int64)]
+
+
+LBM_BATCH_QUEUED, LBM_BATCH_RUNNING, LBM_BATCH_DONE, LBM_BATCH_FAILED = 0, 1, 2, 3
+
 EXPORTS = ("lbm_problem_create", "lbm_workspace_bytes", "lbm_bind_workspace", "lbm_forward_solve",
-           "lbm_forward_continue", "lbm_adjoint_solve", "lbm_adjoint_continue", "lbm_sensitivity",
+           "lbm_forward_continue", "lbm_adjoint_solve", "lbm_adjoint_continue",
+           "lbm_thermal_resolve", "lbm_sensitivity",
            "lbm_copy_state", "lbm_set_kernel_timing", "lbm_kernel_timing", "lbm_lattice",
-           "lbm_problem_destroy", "lbm_last_error")
+           "lbm_problem_destroy", "lbm_last_error", "lbm_batch_create", "lbm_batch_table_bytes",
+           "lbm_batch_bind_arena", "lbm_batch_submit", "lbm_batch_step", "lbm_batch_poll",
+           "lbm_batch_stats", "lbm_batch_destroy")
 
 _lib = None
 
@@ -85,6 +103,8 @@ def load_library(path: str = LIB_PATH):
     lib.lbm_adjoint_solve.restype = c_int
     lib.lbm_adjoint_continue.argtypes = [P, P, P, P, P, c_int32, POINTER(lbm_info_t), P]
     lib.lbm_adjoint_continue.restype = c_int
+    lib.lbm_thermal_resolve.argtypes = [P, P, P, P, POINTER(lbm_info_t), P]
+    lib.lbm_thermal_resolve.restype = c_int
     lib.lbm_sensitivity.argtypes = [P, P, P, P, P, P, POINTER(c_double), P]
     lib.lbm_sensitivity.restype = c_int
     lib.lbm_copy_state.argtypes = [P, c_int32, P, P]
@@ -99,6 +119,22 @@ def load_library(path: str = LIB_PATH):
     lib.lbm_problem_destroy.restype = None
     lib.lbm_last_error.argtypes = []
     lib.lbm_last_error.restype = c_char_p
+    lib.lbm_batch_create.argtypes = [c_int32, c_int32, c_int32, c_int32, POINTER(c_void_p)]
+    lib.lbm_batch_create.restype = c_int
+    lib.lbm_batch_table_bytes.argtypes = [P, c_size_t]
+    lib.lbm_batch_table_bytes.restype = c_size_t
+    lib.lbm_batch_bind_arena.argtypes = [P, P, c_size_t]
+    lib.lbm_batch_bind_arena.restype = c_int
+    lib.lbm_batch_submit.argtypes = [P, POINTER(lbm_desc_t), P, P, POINTER(ctypes.c_int64)]
+    lib.lbm_batch_submit.restype = c_int
+    lib.lbm_batch_step.argtypes = [P, P, POINTER(c_int32), POINTER(c_int32)]
+    lib.lbm_batch_step.restype = c_int
+    lib.lbm_batch_poll.argtypes = [P, ctypes.c_int64, POINTER(lbm_batch_result_t), P, P]
+    lib.lbm_batch_poll.restype = c_int
+    lib.lbm_batch_stats.argtypes = [P, POINTER(lbm_batch_stats_t)]
+    lib.lbm_batch_stats.restype = c_int
+    lib.lbm_batch_destroy.argtypes = [P]
+    lib.lbm_batch_destroy.restype = None
     _lib = lib
     return lib
 
@@ -172,6 +208,13 @@ def lbm_adjoint_continue(p, gamma, drho, u, T, nsteps, stream=None) -> lbm_info_
     return info
 
 
+def lbm_thermal_resolve(p, gamma, u, T, stream=None) -> lbm_info_t:
+    info = lbm_info_t()
+    _check(load_library().lbm_thermal_resolve(p, _ptr(gamma), _ptr(u), _ptr(T), byref(info),
+                                              _stream(stream)))
+    return info
+
+
 def lbm_sensitivity(p, gamma, drho, u, T, dJ, stream=None) -> float:
     J = c_double()
     _check(load_library().lbm_sensitivity(p, _ptr(gamma), _ptr(drho), _ptr(u), _ptr(T), _ptr(dJ),
@@ -214,6 +257,54 @@ def lbm_problem_destroy(p) -> None:
 
 def lbm_last_error() -> str:
     return load_library().lbm_last_error().decode()
+
+
+def lbm_batch_create(thermal: bool, objective: int, max_slots: int, quantum: int) -> c_void_p:
+    h = c_void_p()
+    _check(load_library().lbm_batch_create(int(bool(thermal)), int(objective), int(max_slots),
+                                           int(quantum), byref(h)))
+    return h
+
+
+def lbm_batch_table_bytes(b, arena_bytes: int) -> int:
+    return int(load_library().lbm_batch_table_bytes(b, int(arena_bytes)))
+
+
+def lbm_batch_bind_arena(b, arena: torch.Tensor) -> None:
+    _check(load_library().lbm_batch_bind_arena(b, c_void_p(arena.data_ptr()), arena.numel()))
+
+
+def lbm_batch_submit(b, desc: lbm_desc_t, mask, gamma) -> int:
+    import numpy as np
+    m = np.ascontiguousarray(mask, dtype=np.uint8).reshape(-1)
+    g = np.ascontiguousarray(gamma, dtype=np.float32).reshape(-1)
+    t = ctypes.c_int64()
+    _check(load_library().lbm_batch_submit(b, byref(desc), c_void_p(m.ctypes.data),
+                                           c_void_p(g.ctypes.data), byref(t)))
+    return int(t.value)
+
+
+def lbm_batch_step(b, stream=None):
+    a, q = c_int32(), c_int32()
+    _check(load_library().lbm_batch_step(b, _stream(stream), byref(a), byref(q)))
+    return int(a.value), int(q.value)
+
+
+def lbm_batch_poll(b, ticket: int, dJ_host=None, stream=None) -> lbm_batch_result_t:
+    r = lbm_batch_result_t()
+    ptr = None if dJ_host is None else c_void_p(dJ_host.ctypes.data)
+    _check(load_library().lbm_batch_poll(b, int(ticket), byref(r), ptr, _stream(stream)))
+    return r
+
+
+def lbm_batch_stats(b) -> dict:
+    st = lbm_batch_stats_t()
+    _check(load_library().lbm_batch_stats(b, byref(st)))
+    return {k: int(getattr(st, k)) for k, _ in lbm_batch_stats_t._fields_ if k != "reserved"}
+
+
+def lbm_batch_destroy(b) -> None:
+    load_library().lbm_batch_destroy(b)
 
 
 # ------------------------------------------------------------- convenience

@@ -1,0 +1,111 @@
+"""The differentiable form: J(gamma) as a torch.autograd.Function whose
+backward is the discrete adjoint, storing only (gamma, density deviation, u, T).
+
+* reduced grid with the differentiable workload's parameters (tau 0.5675,
+  Pr 6, conductivity ratio 100, heat-sink objective): the autograd gradient
+  against the FP64 oracle's converged adjoint gradient (1e-4 norm-wise) and
+  against central finite differences of the FP64 oracle (h = 1e-4) at 32
+  seeded design cells;
+* full 128 x 64 x 32 grid: autograd (thermal state re-solved from u, T)
+  against the direct C-ABI path (thermal state of the forward solve).
+"""
+import concurrent.futures as cf
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+from _parity import rel
+from paper_2501_02161_amd import autograd, lbm
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    torch.cuda.set_device(0)
+    yield
+
+
+TAU = 0.5675   # the differentiable workload: U 0.15, L 30, Re 200
+
+
+def reduced_case():
+    L = 6
+    Re = 0.15 * L / ((TAU - 0.5) / 3.0)
+    return W.heat_sink(20, 12, 8, Re=Re, tau=TAU, sigma=1.5, seed=W.SEED_BASE + 3,
+                       name="differentiable_reduced_20x12x8")
+
+
+def _autograd(w):
+    prob = lbm.Problem(w, device="cuda:0")
+    gamma = torch.tensor(w.gamma, dtype=torch.float32, device="cuda:0", requires_grad=True)
+    J = autograd.objective(gamma, prob)
+    saved = [t.numel() for t in J.grad_fn.saved_tensors]
+    J.backward()
+    torch.cuda.synchronize()
+    return prob, J, gamma.grad.detach().reshape(-1).cpu().numpy().astype(np.float64), saved
+
+
+def test_autograd_vs_oracle_gradient_and_fd():
+    w = reduced_case().replace(max_steps=40000, tol=2e-7, check_every=500)
+    print(f"[autograd] reduced grid {w.nx}x{w.ny}x{w.nz} tau {w.tau}", flush=True)
+    prob, J, grad, saved = _autograd(w)
+    # only gamma, the density deviation, u and T are kept for the backward
+    assert sorted(saved) == sorted([w.N, w.N, 3 * w.N, w.N])
+    o = oracle.Oracle(w)
+    fw = o.forward(max_steps=400000, tol=1e-13, check_every=500)
+    ad = o.adjoint(fw["f"], fw["g"], max_steps=400000, tol=1e-13, check_every=500)
+    assert fw["status"] == 0 and ad["status"] == 0
+    dJ = o.sensitivity(fw["f"], fw["g"], ad["fsC"], ad["gsC"])
+    J_ref = o.objective(fw["f"], fw["g"])
+    design = (w.mask.reshape(-1) & 7) == W.DESIGN
+    e_full = rel(grad[design], dJ[design])
+    assert abs(float(J) - J_ref) <= 1e-5 * abs(J_ref)
+    assert e_full < 1e-4, e_full
+    # central differences of the FP64 oracle, warm-started at the converged
+    # state and run a fixed number of steps (the residue of the base state
+    # cancels in the difference)
+    rng = np.random.default_rng(W.SEED_BASE + 32)
+    cells = rng.choice(np.nonzero(design)[0], size=32, replace=False)
+    h = 1e-4
+    steps = 2 * fw["steps"]
+
+    def fd(k):
+        oracle.set_threads(1)
+        out = []
+        for s in (+1.0, -1.0):
+            gm = o.gamma.copy()
+            gm[k] += s * h
+            r = o.forward(gamma=gm, max_steps=steps, tol=0.0, check_every=0,
+                          state=(fw["f"], fw["g"]))
+            out.append(o.objective(r["f"], r["g"], gamma=gm))
+        return (out[0] - out[1]) / (2 * h)
+
+    with cf.ThreadPoolExecutor(max_workers=16) as ex:
+        ref = np.array(list(ex.map(fd, cells)))
+    e_fd = rel(grad[cells], ref)
+    e_fd_oracle = rel(dJ[cells], ref)
+    print(f"[autograd] J {float(J):.9g} vs {J_ref:.9g}; grad vs oracle adjoint {e_full:.2e}; "
+          f"grad vs FD at 32 cells {e_fd:.2e}; oracle adjoint vs FD {e_fd_oracle:.2e}", flush=True)
+    assert e_fd_oracle < 1e-6
+    assert e_fd < 1e-4
+
+
+def test_autograd_full_size_matches_direct_path():
+    w = W.differentiable_case()
+    print(f"[autograd] full {w.nx}x{w.ny}x{w.nz} tau {w.tau}", flush=True)
+    prob, J, grad, _ = _autograd(w)
+    direct = lbm.Problem(w, device="cuda:0")
+    res = direct.solve(w.gamma)
+    torch.cuda.synchronize()
+    dJ = direct.dJ.reshape(-1).cpu().numpy().astype(np.float64)
+    design = (w.mask.reshape(-1) & 7) == W.DESIGN
+    e = rel(grad[design], dJ[design])
+    print(f"[autograd] full J {float(J):.9g} vs {res['J']:.9g}; grad vs direct path {e:.2e}; "
+          f"forward steps {res['forward']['steps']}", flush=True)
+    assert float(J) == res["J"]
+    assert e < 1e-4

@@ -153,7 +153,7 @@ def pipe_bend_3d(n: int = 96, tau: float = 0.55, Re: float = 100.0, sigma: float
 def heat_sink(nx: int = 160, ny: int = 80, nz: int = 40, Re: float = 200.0,
               Pr: float = 6.0, u_peak: float = 0.1, sigma: float = 5.0,
               seed: Optional[int] = None, tau: Optional[float] = None,
-              name: Optional[str] = None) -> Workload:
+              name: Optional[str] = None, buffer: int = 0) -> Workload:
     """3D microchannel heat sink, coupled D3Q19 flow + D3Q7 heat: velocity
     inlet over the whole interior of face x=0, pressure outlet over the whole
     interior of face x=nx-1, uniform heat flux through the floor z=0, walls
@@ -165,12 +165,18 @@ def heat_sink(nx: int = 160, ny: int = 80, nz: int = 40, Re: float = 200.0,
     Re = u_peak L / nu with L = nz - 2 (the channel height between the
     midway walls).  u_peak = 0.1 gives tau = 0.728, 0.557, 0.5285 at
     Re 50, 200, 400; with u_peak = 0.05 (tau 0.5285 at Re 200) the BGK flow
-    lattice blows up near the inlet corners on the full grid."""
+    lattice blows up near the inlet corners on the full grid.
+
+    `buffer` > 0 makes the last `buffer` interior layers before the outlet
+    plain fluid (not design): a jet leaving a design pore straight through
+    the pressure outlet can lock into a period-2 oscillation there."""
     seed = SEED_BASE + 2 if seed is None else seed
     m = walled_box(nx, ny, nz)
     m[1:nz - 1, 1:ny - 1, 0] = code(INLET, NPX)
     m[1:nz - 1, 1:ny - 1, nx - 1] = code(OUTLET, NMX)
     m[0, 1:ny - 1, 1:nx - 1] = code(HEATED, NPZ)
+    if buffer > 0:
+        m[1:nz - 1, 1:ny - 1, nx - 1 - buffer:nx - 1] = FLUID
     L = float(nz - 2)
     if tau is None:
         tau = 0.5 + 3.0 * u_peak * L / Re
@@ -182,9 +188,16 @@ def heat_sink(nx: int = 160, ny: int = 80, nz: int = 40, Re: float = 200.0,
 
 
 def differentiable_case(seed: Optional[int] = None) -> Workload:
-    """The autograd workload: coupled heat sink on 128 x 64 x 32 at Re 200."""
+    """The autograd workload: coupled heat sink on 128 x 64 x 32 at Re 200.
+    Peak inlet speed 0.15 (tau 0.5675): with 0.1 (tau 0.545) the BGK flow
+    lattice blows up after ~1500 steps on this grid.  Six fluid layers
+    before the outlet: without them a jet through a design pore at the
+    outlet (|u| 0.16) oscillates with period 2, which a residual taken over
+    an even number of steps cannot see, and the adjoint of that non-steady
+    state diverges."""
     seed = SEED_BASE + 3 if seed is None else seed
-    return heat_sink(128, 64, 32, Re=200.0, seed=seed, name="heat_sink_128x64x32_Re200")
+    return heat_sink(128, 64, 32, Re=200.0, u_peak=0.15, seed=seed, buffer=6,
+                     name="heat_sink_128x64x32_Re200")
 
 
 SERVING_GRIDS = ((64, 32, 16), (128, 64, 32), (192, 96, 48))

@@ -12,8 +12,15 @@ algorithmic bytes per node-update times the node count, over its average
 launch duration.  That duration is measured during the timed region with a
 pair of HIP events on the solve's stream around every forward and adjoint
 sweep: the step kernels of a sweep run back to back (rocprofv3 shows no gap
-between them), so sweep time over launches is the average launch duration.  The CPU baseline times the FP64 oracle on the host cores on a
-bounded sample of the same workload.
+between them), so sweep time over launches is the average launch duration.
+The CPU baseline times the FP64 oracle on the host cores on a bounded sample
+of the same workload.
+
+The serving object replays the first --serving-requests requests of the
+serving stream (heat-sink solves on 64x32x16, 128x64x32 or 192x96x48 grids,
+Re in [50, 400], tau in [0.52, 0.8], seeded designs, Poisson arrivals) through
+the continuous-batching engine under a 200 GB HBM budget, then as plain
+back-to-back solves, and reports p50/p99 latency and aggregate MLUPS of both.
 """
 import argparse
 import json
@@ -58,6 +65,13 @@ def parse():
                     help="measure device-to-device copy bandwidth (1 GiB, out of cache) and exit")
     ap.add_argument("--no-kernel-timing", action="store_true",
                     help="do not bracket the sweeps with HIP events")
+    ap.add_argument("--serving-requests", type=int, default=64,
+                    help="requests of the serving stream replayed batched and back to back "
+                         "(0: skip the serving leg; the full stream is 256)")
+    ap.add_argument("--serving-rate", type=float, default=0.0,
+                    help="Poisson arrival rate in requests/s (0: the stream's default)")
+    ap.add_argument("--serving-only", action="store_true",
+                    help="run only the serving leg and print its JSON object")
     return ap.parse_args()
 
 
@@ -159,6 +173,48 @@ def cpu_baseline(w, fwd_steps):
                       f"rate for equal forward and adjoint step counts)"}
 
 
+def serving_leg(n, rate):
+    """Replay the first n requests of the serving stream (seeded Poisson
+    arrivals) once through the continuous-batching engine and once as plain
+    back-to-back solves; report latency percentiles and aggregate MLUPS of
+    both and whether every request got the same result both ways."""
+    import torch
+    import workloads as W
+    from paper_2501_02161_amd import serving
+
+    def log(msg):
+        print(f"[serving] {msg}", file=sys.stderr, flush=True)
+
+    rate = rate or W.SERVING_RATE
+    reqs = [W.serving_request(i) for i in range(n)]
+    arrivals = W.poisson_arrivals(n, rate)
+    warm = W.heat_sink(24, 14, 10, Re=20.0, tau=0.6, sigma=1.5,
+                       name="warmup").replace(max_steps=500, check_every=250, tol=0.0)
+    eng = serving.BatchEngine(True, W.OBJ_HEATSINK, budget_bytes=W.SERVING_BUDGET_BYTES,
+                              quantum=250)
+    serving.serve(eng, [warm], [0.0])
+    log(f"batched replay of {n} requests at {rate} /s")
+    res_b, mk_b = serving.serve(eng, reqs, arrivals, log=log)
+    st = eng.stats()
+    eng.close()
+    del eng
+    torch.cuda.empty_cache()
+    serving.serve_back_to_back([warm], [0.0])
+    log(f"back-to-back replay of {n} requests")
+    res_s, mk_s = serving.serve_back_to_back(reqs, arrivals, log=log)
+    sizes = {}
+    for w in reqs:
+        key = f"{w.nx}x{w.ny}x{w.nz}"
+        sizes[key] = sizes.get(key, 0) + 1
+    return {"requests": n, "arrivals": f"Poisson {rate} /s, seeded", "grids": sizes,
+            "budget_GB": W.SERVING_BUDGET_BYTES / 1e9, "quantum_steps": 250,
+            "tol": reqs[0].tol, "max_steps": reqs[0].max_steps,
+            "batched": serving.summarize(res_b, mk_b),
+            "back_to_back": serving.summarize(res_s, mk_s),
+            "identical_results": serving.same_results(res_b, res_s),
+            "batch_launches": st["launches"]}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -171,6 +227,10 @@ def main():
         return
     if args.copy_bw:
         copy_bandwidth()
+        return
+    if args.serving_only:
+        print(json.dumps({"serving": serving_leg(args.serving_requests or 256,
+                                                 args.serving_rate)}), flush=True)
         return
     import numpy as np
     import torch
@@ -247,6 +307,9 @@ def main():
              BYTES_PER_NODE[("adjoint", bool(w.thermal))] * w.N * ai["steps"]) * args.steps /
             elapsed / 1e9 / HBM_PEAK_GBS, 4),
     }
+    prob.close()
+    if args.serving_requests > 0:
+        out["serving"] = serving_leg(args.serving_requests, args.serving_rate)
     if not args.no_cpu_baseline:
         steps = args.cpu_fwd_steps or 48
         out["cpu_baseline"] = cpu_baseline(w, steps)

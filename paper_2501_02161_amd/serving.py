@@ -62,10 +62,11 @@ class BatchEngine:
             pass
 
 
-def serve(engine: BatchEngine, requests, arrivals, time_scale: float = 1.0):
+def serve(engine: BatchEngine, requests, arrivals, time_scale: float = 1.0, log=None):
     """Replay `requests` arriving at `arrivals` (seconds from start) against
     the engine in wall-clock time.  Returns per-request dicts with arrival,
-    completion and latency (seconds), plus the makespan."""
+    completion and latency (seconds), plus the makespan.  `log`, if given, is
+    called with a progress line every 16 completed requests."""
     order = np.argsort(arrivals)
     pending = [(float(arrivals[i]) * time_scale, int(i)) for i in order]
     tickets = {}
@@ -86,6 +87,8 @@ def serve(engine: BatchEngine, requests, arrivals, time_scale: float = 1.0):
             r.update(arrival=a, completion=done, latency=done - a, index=i)
             results[i] = r
             del tickets[t]
+            if log and len(results) % 16 == 0:
+                log(f"batched: {len(results)}/{len(requests)} done at {done:.1f} s")
         if active == 0 and queued == 0 and not tickets and pending:
             wait = pending[0][0] - (time.perf_counter() - t0)
             if wait > 0:
@@ -94,7 +97,7 @@ def serve(engine: BatchEngine, requests, arrivals, time_scale: float = 1.0):
     return [results[i] for i in range(len(requests))], makespan
 
 
-def serve_back_to_back(requests, arrivals, device="cuda:0", time_scale: float = 1.0):
+def serve_back_to_back(requests, arrivals, device="cuda:0", time_scale: float = 1.0, log=None):
     """The same trace served by one plain solve at a time, in arrival order."""
     order = np.argsort(arrivals)
     results = {}
@@ -106,21 +109,55 @@ def serve_back_to_back(requests, arrivals, device="cuda:0", time_scale: float = 
             time.sleep(a - now)
         w = requests[i]
         prob = lbm.Problem(w, device=device)
-        res = prob.solve(w.gamma)
-        dJ = prob.dJ.reshape(-1).cpu().numpy()
+        try:
+            res = prob.solve(w.gamma)
+            dJ = prob.dJ.reshape(-1).cpu().numpy()
+            ok = res["forward"]["status"] == lbm.LBM_OK and res["adjoint"]["status"] == lbm.LBM_OK
+            r = {"state": lbm.LBM_BATCH_DONE,
+                 "status": lbm.LBM_OK if ok else lbm.LBM_NOT_CONVERGED, "J": res["J"],
+                 "fwd_steps": res["forward"]["steps"], "adj_steps": res["adjoint"]["steps"],
+                 "dJ": dJ}
+        except lbm.LBMError as e:
+            torch.cuda.synchronize(device)
+            r = {"state": lbm.LBM_BATCH_FAILED, "status": e.code, "J": float("nan"),
+                 "fwd_steps": 0, "adj_steps": 0, "dJ": np.zeros(0, np.float32)}
         done = time.perf_counter() - t0
-        results[int(i)] = {"index": int(i), "arrival": a, "completion": done, "latency": done - a,
-                           "J": res["J"], "fwd_steps": res["forward"]["steps"],
-                           "adj_steps": res["adjoint"]["steps"], "dJ": dJ}
+        r.update(index=int(i), arrival=a, completion=done, latency=done - a)
+        results[int(i)] = r
         prob.close()
+        if log and len(results) % 16 == 0:
+            log(f"back-to-back: {len(results)}/{len(requests)} done at {done:.1f} s")
     makespan = max(r["completion"] for r in results.values())
     return [results[i] for i in range(len(requests))], makespan
 
 
 def summarize(results, makespan) -> dict:
+    """Latency percentiles over every request (a failed request's latency is
+    the time until its failure was reported); MLUPS counts the node updates
+    of the completed requests only, over the makespan."""
     lat = np.array([r["latency"] for r in results])
-    updates = sum((r["fwd_steps"] + r["adj_steps"]) * r["dJ"].size for r in results)
-    return {"requests": len(results), "p50_s": round(float(np.percentile(lat, 50)), 4),
+    done = [r for r in results if r["state"] == lbm.LBM_BATCH_DONE]
+    updates = sum((r["fwd_steps"] + r["adj_steps"]) * r["dJ"].size for r in done)
+    return {"requests": len(results), "completed": len(done),
+            "failed": len(results) - len(done),
+            "p50_s": round(float(np.percentile(lat, 50)), 4),
             "p99_s": round(float(np.percentile(lat, 99)), 4),
             "mean_s": round(float(lat.mean()), 4), "makespan_s": round(makespan, 3),
             "MLUPS": round(updates / makespan / 1e6, 1)}
+
+
+def same_results(a, b) -> bool:
+    """True if two runs of one trace gave the same outcome for every request:
+    the same state, and for completed requests the same step counts, the same
+    J and the same dJ/dgamma bit for bit."""
+    for ra, rb in zip(a, b):
+        if ra["state"] != rb["state"]:
+            return False
+        if ra["state"] != lbm.LBM_BATCH_DONE:
+            continue
+        if (ra["fwd_steps"], ra["adj_steps"], ra["J"]) != (rb["fwd_steps"], rb["adj_steps"],
+                                                           rb["J"]):
+            return False
+        if not np.array_equal(ra["dJ"], rb["dJ"]):
+            return False
+    return True

@@ -201,6 +201,11 @@ def differentiable_case(seed: Optional[int] = None) -> Workload:
 
 
 SERVING_GRIDS = ((64, 32, 16), (128, 64, 32), (192, 96, 48))
+# Poisson arrival rate of the serving stream (requests/s): 0.8 of what plain
+# back-to-back solves sustain on one MI355X (mean service 0.53 s per request
+# over the first 256 requests of the stream).
+SERVING_RATE = 1.5
+SERVING_BUDGET_BYTES = 200 * 10**9
 
 
 def serving_request(i: int, base_seed: int = SEED_BASE + 4) -> Workload:

@@ -70,6 +70,12 @@ def parse():
                          "(0: skip the serving leg; the full stream is 256)")
     ap.add_argument("--serving-rate", type=float, default=0.0,
                     help="Poisson arrival rate in requests/s (0: the stream's default)")
+    ap.add_argument("--serving-policy", default="overlap", choices=["overlap", "srw", "all"],
+                    help="batch scheduling: two concurrent lanes, small requests beside the "
+                         "oldest one (overlap); shortest remaining work first (srw); every "
+                         "resident request every quantum (all)")
+    ap.add_argument("--serving-fill", type=int, default=512,
+                    help="tiles of 256 nodes per launch the srw policy fills up to")
     ap.add_argument("--serving-only", action="store_true",
                     help="run only the serving leg and print its JSON object")
     return ap.parse_args()
@@ -173,14 +179,14 @@ def cpu_baseline(w, fwd_steps):
                       f"rate for equal forward and adjoint step counts)"}
 
 
-def serving_leg(n, rate):
+def serving_leg(n, rate, policy="srw", fill=512):
     """Replay the first n requests of the serving stream (seeded Poisson
     arrivals) once through the continuous-batching engine and once as plain
     back-to-back solves; report latency percentiles and aggregate MLUPS of
     both and whether every request got the same result both ways."""
     import torch
     import workloads as W
-    from paper_2501_02161_amd import serving
+    from paper_2501_02161_amd import lbm, serving
 
     def log(msg):
         print(f"[serving] {msg}", file=sys.stderr, flush=True)
@@ -190,8 +196,10 @@ def serving_leg(n, rate):
     arrivals = W.poisson_arrivals(n, rate)
     warm = W.heat_sink(24, 14, 10, Re=20.0, tau=0.6, sigma=1.5,
                        name="warmup").replace(max_steps=500, check_every=250, tol=0.0)
+    pol = {"srw": lbm.LBM_BATCH_POLICY_SRW, "all": lbm.LBM_BATCH_POLICY_ALL,
+           "overlap": lbm.LBM_BATCH_POLICY_OVERLAP}[policy]
     eng = serving.BatchEngine(True, W.OBJ_HEATSINK, budget_bytes=W.SERVING_BUDGET_BYTES,
-                              quantum=250)
+                              quantum=250, policy=pol, fill_tiles=fill)
     serving.serve(eng, [warm], [0.0])
     log(f"batched replay of {n} requests at {rate} /s")
     res_b, mk_b = serving.serve(eng, reqs, arrivals, log=log)
@@ -208,6 +216,7 @@ def serving_leg(n, rate):
         sizes[key] = sizes.get(key, 0) + 1
     return {"requests": n, "arrivals": f"Poisson {rate} /s, seeded", "grids": sizes,
             "budget_GB": W.SERVING_BUDGET_BYTES / 1e9, "quantum_steps": 250,
+            "policy": policy if policy == "all" else f"{policy}, fill {fill} tiles",
             "tol": reqs[0].tol, "max_steps": reqs[0].max_steps,
             "batched": serving.summarize(res_b, mk_b),
             "back_to_back": serving.summarize(res_s, mk_s),
@@ -230,7 +239,8 @@ def main():
         return
     if args.serving_only:
         print(json.dumps({"serving": serving_leg(args.serving_requests or 256,
-                                                 args.serving_rate)}), flush=True)
+                                                 args.serving_rate, args.serving_policy,
+                                                 args.serving_fill)}), flush=True)
         return
     import numpy as np
     import torch
@@ -309,7 +319,8 @@ def main():
     }
     prob.close()
     if args.serving_requests > 0:
-        out["serving"] = serving_leg(args.serving_requests, args.serving_rate)
+        out["serving"] = serving_leg(args.serving_requests, args.serving_rate,
+                                     args.serving_policy, args.serving_fill)
     if not args.no_cpu_baseline:
         steps = args.cpu_fwd_steps or 48
         out["cpu_baseline"] = cpu_baseline(w, steps)

@@ -244,10 +244,12 @@ int lbm_lattice(int32_t which, int32_t* e, double* w);
  * one GPU.  lbm_batch_submit queues a request (descriptor, host mask, host
  * design field; all copied).  Each lbm_batch_step call first admits queued
  * requests in arrival order while a slot is free and the request's workspace
- * and fields fit in the arena the caller bound (the HBM budget); then one
- * ragged-batch kernel launch per lattice step advances every resident
- * request by one step of its forward or adjoint sweep, `quantum` times;
- * then every request's residual is checked and requests move from the
+ * and fields fit in the arena the caller bound (the HBM budget).  Work is
+ * issued in quanta on lanes (HIP streams the engine owns): a quantum is
+ * `quantum` ragged-batch kernel launches, each advancing every request of
+ * the lane's run set (chosen by the policy, lbm_batch_set_policy) by one
+ * step of its forward or adjoint sweep.  When a lane's quantum completes,
+ * the residuals of its requests are checked and requests move from the
  * forward sweep to the adjoint sweep to dJ/dgamma exactly as
  * lbm_forward_solve / lbm_adjoint_solve / lbm_sensitivity would, so each
  * result is bit for bit the result of the same request solved alone.  A
@@ -263,6 +265,11 @@ int lbm_lattice(int32_t which, int32_t* e, double* w);
 #define LBM_BATCH_RUNNING 1
 #define LBM_BATCH_DONE 2
 #define LBM_BATCH_FAILED 3
+
+/* Scheduling policies: which resident requests a quantum advances. */
+#define LBM_BATCH_POLICY_ALL 0     /* one lane: every resident request            */
+#define LBM_BATCH_POLICY_SRW 1     /* one lane: shortest remaining work, filled    */
+#define LBM_BATCH_POLICY_OVERLAP 2 /* two concurrent lanes (default)               */
 
 typedef struct lbm_batch lbm_batch_t;
 
@@ -295,13 +302,28 @@ int lbm_batch_create(int32_t thermal, int32_t objective, int32_t max_slots, int3
 size_t lbm_batch_table_bytes(const lbm_batch_t* b, size_t arena_bytes);
 /* Bind caller-owned device memory as the arena (current device). */
 int lbm_batch_bind_arena(lbm_batch_t* b, void* device_ptr, size_t bytes);
+/* Scheduling policy.  ALL (one lane): every resident request advances every
+ * quantum.  SRW (one lane): requests ordered by an upper bound of their
+ * remaining node updates (nodes x steps left to the step caps of both
+ * sweeps), taken greedily while the run set stays within fill_tiles tiles of
+ * 256 nodes (the first is always taken).  OVERLAP (two lanes whose quanta
+ * run concurrently): the latency lane takes requests of at most fill_tiles
+ * tiles in arrival order, greedily up to fill_tiles; the bandwidth lane takes
+ * the oldest remaining request and, if it is that small too, further small
+ * ones up to fill_tiles.  Requests in no run set stay resident and paused.
+ * The policy changes latency and throughput only, never a result.  Default
+ * OVERLAP, fill 512.  LBM_EINVAL on an unknown policy or fill_tiles < 1,
+ * LBM_ESTATE while a quantum is in flight. */
+int lbm_batch_set_policy(lbm_batch_t* b, int32_t policy, int32_t fill_tiles);
 /* Queue a request; validates it (LBM_EINVAL, or LBM_ENOMEM if it can never
  * fit the arena) and returns its ticket. */
 int lbm_batch_submit(lbm_batch_t* b, const lbm_desc_t* desc, const uint8_t* mask,
                      const float* gamma_host, int64_t* ticket);
-/* Admit, advance every resident request by one quantum of steps, check
- * residuals and move phases; synchronises `stream`.  active/queued (may be
- * NULL) receive the resident running requests and the queue length. */
+/* Admit (uploads on `stream`, synchronised), start a quantum on every idle
+ * lane, then wait until at least one lane's quantum has completed and do its
+ * residual checks and phase moves.  Quanta of other lanes may still be in
+ * flight on return.  active/queued (may be NULL) receive the resident
+ * running requests and the queue length. */
 int lbm_batch_step(lbm_batch_t* b, void* stream, int32_t* active, int32_t* queued);
 /* State of a ticket; DONE/FAILED results are returned once and released. */
 int lbm_batch_poll(lbm_batch_t* b, int64_t ticket, lbm_batch_result_t* res, float* dJ_host,

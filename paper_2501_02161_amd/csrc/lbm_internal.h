@@ -106,8 +106,10 @@ struct ThermArgs {
 
 // Ragged batch: one slot per resident problem, one tile per 256-node block of
 // a slot.  A batch launch advances every slot in the forward or adjoint phase
-// by one step; the slot's step in its phase is (launch - start), the A/B
-// buffers alternate with its parity (even steps read buffer 0).
+// by one step; the slot's step in its phase is (launch - start), where the
+// launch index is *base + q (a per-lane device counter plus the launch's place
+// in its quantum); the A/B buffers alternate with the step's parity (even
+// steps read buffer 0).
 struct SlotDev {
   int phase;        // 0 idle, 1 forward, 2 adjoint
   int start;        // launch index of the phase's first step
@@ -138,8 +140,10 @@ hipError_t launch_dissipation_objective(const float* u, const float* gamma, cons
                                         double* partials, const KParams& P, hipStream_t s);
 hipError_t launch_finalize(const double* partials, int nblk, int nvals, double* out,
                            hipStream_t s);
-hipError_t launch_batch(const Tile* tiles, int ntiles, const SlotDev* slots, int launch,
-                        bool thermal, int objective, hipStream_t s);
+hipError_t launch_batch(const Tile* tiles, int ntiles, const SlotDev* slots, const int* base,
+                        int q, bool thermal, int objective, hipStream_t s);
+// *base += q on the device (end of a quantum of q launches).
+hipError_t launch_advance(int* base, int q, hipStream_t s);
 // Per-slot residual sums of the slots' last diagnostic step: out[slot * 4 + v].
 hipError_t launch_finalize_slots(const SlotDev* slots, int nslots, double* out, hipStream_t s);
 

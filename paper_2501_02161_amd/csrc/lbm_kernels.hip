@@ -712,10 +712,12 @@ __global__ __launch_bounds__(kBlock) void k_finalize_slots(const SlotDev* __rest
 // alone.
 template <bool THERMAL, int OBJ>
 __global__ __launch_bounds__(kBlock) void k_batch(const Tile* __restrict__ tiles,
-                                                  const SlotDev* __restrict__ slots, int launch,
-                                                  int xper, int xrem) {
+                                                  const SlotDev* __restrict__ slots,
+                                                  const int* __restrict__ base, int q, int xper,
+                                                  int xrem) {
   const int b = blockIdx.x, xcd = b & 7, idx = b >> 3;
   const int t = xcd < xrem ? xcd * (xper + 1) + idx : xrem * (xper + 1) + (xcd - xrem) * xper + idx;
+  const int launch = *base + q;
   const Tile tl = tiles[t];
   const SlotDev& S = slots[tl.slot];
   const int phase = S.phase;
@@ -744,6 +746,10 @@ __global__ __launch_bounds__(kBlock) void k_batch(const Tile* __restrict__ tiles
     if (diag) adjoint_tile<THERMAL, OBJ, true>(A, tl.blk);
     else adjoint_tile<THERMAL, OBJ, false>(A, tl.blk);
   }
+}
+
+__global__ void k_advance(int* base, int q) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *base += q;
 }
 
 // ---------------------------------------------------------------------------
@@ -922,33 +928,38 @@ hipError_t launch_finalize(const double* partials, int nblk, int nvals, double* 
   return hipGetLastError();
 }
 
-hipError_t launch_batch(const Tile* tiles, int ntiles, const SlotDev* slots, int launch,
-                        bool thermal, int objective, hipStream_t s) {
+hipError_t launch_batch(const Tile* tiles, int ntiles, const SlotDev* slots, const int* base,
+                        int q, bool thermal, int objective, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
   const int xper = ntiles / 8, xrem = ntiles % 8;
   const dim3 grid(ntiles), block(kBlock);
   if (thermal) {
     switch (objective) {
       case OBJ_PRESSURE_DROP:
-        hipLaunchKernelGGL((k_batch<true, OBJ_PRESSURE_DROP>), grid, block, 0, s, tiles, slots, launch, xper, xrem);
+        hipLaunchKernelGGL((k_batch<true, OBJ_PRESSURE_DROP>), grid, block, 0, s, tiles, slots, base, q, xper, xrem);
         break;
       case OBJ_DISSIPATION:
-        hipLaunchKernelGGL((k_batch<true, OBJ_DISSIPATION>), grid, block, 0, s, tiles, slots, launch, xper, xrem);
+        hipLaunchKernelGGL((k_batch<true, OBJ_DISSIPATION>), grid, block, 0, s, tiles, slots, base, q, xper, xrem);
         break;
       default:
-        hipLaunchKernelGGL((k_batch<true, OBJ_HEATSINK>), grid, block, 0, s, tiles, slots, launch, xper, xrem);
+        hipLaunchKernelGGL((k_batch<true, OBJ_HEATSINK>), grid, block, 0, s, tiles, slots, base, q, xper, xrem);
         break;
     }
   } else {
     switch (objective) {
       case OBJ_PRESSURE_DROP:
-        hipLaunchKernelGGL((k_batch<false, OBJ_PRESSURE_DROP>), grid, block, 0, s, tiles, slots, launch, xper, xrem);
+        hipLaunchKernelGGL((k_batch<false, OBJ_PRESSURE_DROP>), grid, block, 0, s, tiles, slots, base, q, xper, xrem);
         break;
       default:
-        hipLaunchKernelGGL((k_batch<false, OBJ_DISSIPATION>), grid, block, 0, s, tiles, slots, launch, xper, xrem);
+        hipLaunchKernelGGL((k_batch<false, OBJ_DISSIPATION>), grid, block, 0, s, tiles, slots, base, q, xper, xrem);
         break;
     }
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_advance(int* base, int q, hipStream_t s) {
+  hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, base, q);
   return hipGetLastError();
 }
 

@@ -67,13 +67,14 @@ class lbm_batch_stats_t(ctypes.Structure):
 
 
 LBM_BATCH_QUEUED, LBM_BATCH_RUNNING, LBM_BATCH_DONE, LBM_BATCH_FAILED = 0, 1, 2, 3
+LBM_BATCH_POLICY_ALL, LBM_BATCH_POLICY_SRW, LBM_BATCH_POLICY_OVERLAP = 0, 1, 2
 
 EXPORTS = ("lbm_problem_create", "lbm_workspace_bytes", "lbm_bind_workspace", "lbm_forward_solve",
            "lbm_forward_continue", "lbm_adjoint_solve", "lbm_adjoint_continue",
            "lbm_thermal_resolve", "lbm_sensitivity",
            "lbm_copy_state", "lbm_set_kernel_timing", "lbm_kernel_timing", "lbm_lattice",
            "lbm_problem_destroy", "lbm_last_error", "lbm_batch_create", "lbm_batch_table_bytes",
-           "lbm_batch_bind_arena", "lbm_batch_submit", "lbm_batch_step", "lbm_batch_poll",
+           "lbm_batch_bind_arena", "lbm_batch_set_policy", "lbm_batch_submit", "lbm_batch_step", "lbm_batch_poll",
            "lbm_batch_stats", "lbm_batch_destroy")
 
 _lib = None
@@ -125,6 +126,8 @@ def load_library(path: str = LIB_PATH):
     lib.lbm_batch_table_bytes.restype = c_size_t
     lib.lbm_batch_bind_arena.argtypes = [P, P, c_size_t]
     lib.lbm_batch_bind_arena.restype = c_int
+    lib.lbm_batch_set_policy.argtypes = [P, c_int32, c_int32]
+    lib.lbm_batch_set_policy.restype = c_int
     lib.lbm_batch_submit.argtypes = [P, POINTER(lbm_desc_t), P, P, POINTER(ctypes.c_int64)]
     lib.lbm_batch_submit.restype = c_int
     lib.lbm_batch_step.argtypes = [P, P, POINTER(c_int32), POINTER(c_int32)]
@@ -272,6 +275,10 @@ def lbm_batch_table_bytes(b, arena_bytes: int) -> int:
 
 def lbm_batch_bind_arena(b, arena: torch.Tensor) -> None:
     _check(load_library().lbm_batch_bind_arena(b, c_void_p(arena.data_ptr()), arena.numel()))
+
+
+def lbm_batch_set_policy(b, policy: int, fill_tiles: int = 512) -> None:
+    _check(load_library().lbm_batch_set_policy(b, int(policy), int(fill_tiles)))
 
 
 def lbm_batch_submit(b, desc: lbm_desc_t, mask, gamma) -> int:

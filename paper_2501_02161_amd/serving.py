@@ -2,7 +2,8 @@
 
 `BatchEngine` wraps the library's batch engine (lbm_batch_*): requests are
 queued, admitted by an HBM budget as slots and memory free up, and advanced
-together by one ragged-batch kernel launch per lattice step.  `serve` replays
+together by ragged-batch kernel launches (one per lattice step of a lane's
+run set) on the engine's concurrent lanes.  `serve` replays
 an arrival trace against it in wall-clock time; `serve_back_to_back` replays
 the same trace with one plain solve at a time (lbm_forward_solve,
 lbm_adjoint_solve, lbm_sensitivity), which is the comparison the serving
@@ -20,9 +21,11 @@ from . import lbm
 
 class BatchEngine:
     def __init__(self, thermal: bool, objective: int, budget_bytes: int, max_slots: int = 256,
-                 quantum: int = 250, device="cuda:0"):
+                 quantum: int = 250, device="cuda:0", policy: int = lbm.LBM_BATCH_POLICY_OVERLAP,
+                 fill_tiles: int = 512):
         self.device = torch.device(device)
         self.h = lbm.lbm_batch_create(thermal, objective, max_slots, quantum)
+        lbm.lbm_batch_set_policy(self.h, policy, fill_tiles)
         self.quantum = quantum
         with torch.cuda.device(self.device):
             total = int(budget_bytes) + lbm.lbm_batch_table_bytes(self.h, int(budget_bytes)) + 512
@@ -78,7 +81,8 @@ def serve(engine: BatchEngine, requests, arrivals, time_scale: float = 1.0, log=
             a, i = pending.pop(0)
             tickets[engine.submit(requests[i])] = (i, a)
         active, queued = engine.step()
-        for t, (i, a) in list(tickets.items()):
+        finished = engine.stats()["finished"]
+        for t, (i, a) in (list(tickets.items()) if finished else []):
             w = requests[i]
             r = engine.collect(t, w.N)
             if r is None:

@@ -111,3 +111,31 @@ def test_unbound_problem_reports_state_error(lbm):
     rc = lib.lbm_forward_solve(h, None, None, None, None, ctypes.byref(info), None)
     assert rc == lbm.LBM_ESTATE
     lbm.lbm_problem_destroy(h)
+
+
+def test_batch_parameters_are_validated(lbm):
+    """Engine creation and policy checks are host-only."""
+    for bad in [(2, 2, 8, 250), (1, 3, 8, 250), (1, 2, 0, 250), (1, 2, 8, 0)]:
+        with pytest.raises(lbm.LBMError) as e:
+            _raw_batch_create(lbm, *bad)
+        assert e.value.code == lbm.LBM_EINVAL
+    b = lbm.lbm_batch_create(True, W.OBJ_HEATSINK, 8, 250)
+    lbm.lbm_batch_set_policy(b, lbm.LBM_BATCH_POLICY_ALL, 1)
+    lbm.lbm_batch_set_policy(b, lbm.LBM_BATCH_POLICY_SRW, 512)
+    lbm.lbm_batch_set_policy(b, lbm.LBM_BATCH_POLICY_OVERLAP, 512)
+    for policy, fill in [(3, 512), (-1, 512), (lbm.LBM_BATCH_POLICY_SRW, 0)]:
+        with pytest.raises(lbm.LBMError) as e:
+            lbm.lbm_batch_set_policy(b, policy, fill)
+        assert e.value.code == lbm.LBM_EINVAL
+    # no arena bound yet: stepping is a state error
+    lib = lbm.load_library()
+    assert lib.lbm_batch_step(b, None, None, None) == lbm.LBM_ESTATE
+    lbm.lbm_batch_destroy(b)
+
+
+def _raw_batch_create(lbm, thermal, objective, slots, quantum):
+    h = ctypes.c_void_p()
+    rc = lbm.load_library().lbm_batch_create(thermal, objective, slots, quantum, ctypes.byref(h))
+    if rc:
+        raise lbm.LBMError(rc, lbm.lbm_last_error())
+    return h

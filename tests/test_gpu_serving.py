@@ -86,6 +86,37 @@ def test_batch_results_equal_single_solves():
     print(f"[serving] batched results identical to single solves; stats {st}", flush=True)
 
 
+@pytest.mark.parametrize("policy,fill", [(lbm.LBM_BATCH_POLICY_ALL, 512),
+                                         (lbm.LBM_BATCH_POLICY_SRW, 1),
+                                         (lbm.LBM_BATCH_POLICY_SRW, 150),
+                                         (lbm.LBM_BATCH_POLICY_OVERLAP, 1),
+                                         (lbm.LBM_BATCH_POLICY_OVERLAP, 20)])
+def test_policy_changes_no_result(policy, fill):
+    """Whatever the run set of each quantum (all resident requests; one at a
+    time; a few by shortest remaining work; two concurrent lanes, requests
+    moving between them), paused requests resume where they stopped and
+    every result equals the single solve bit for bit."""
+    reqs = small_requests()
+    refs = [alone(w) for w in reqs]
+    eng = serving.BatchEngine(True, W.OBJ_HEATSINK, budget_bytes=2 << 30, max_slots=8, quantum=Q,
+                              policy=policy, fill_tiles=fill)
+    tickets = {eng.submit(reqs[0]): 0, eng.submit(reqs[1]): 1, eng.submit(reqs[2]): 2}
+    eng.step()
+    tickets[eng.submit(reqs[3])] = 3
+    eng.step()
+    tickets[eng.submit(reqs[4])] = 4
+    results = _drain(eng, tickets, reqs)
+    assert len(results) == len(reqs)
+    for i, w in enumerate(reqs):
+        _check_same(w, results[i], refs[i], refs[i][1])
+    st = eng.stats()
+    assert st["running"] == 0 and st["bytes_in_use"] == 0
+    # node updates counted = the work of the requests
+    want = sum((results[i]["fwd_steps"] + results[i]["adj_steps"]) * w.N
+               for i, w in enumerate(reqs))
+    assert st["node_updates"] >= want
+
+
 def test_budget_bounds_residency():
     reqs = small_requests()[:3]
     refs = [alone(w) for w in reqs]

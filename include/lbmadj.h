@@ -112,6 +112,21 @@ extern "C" {
 #define LBM_OBJ_DISSIPATION 1
 #define LBM_OBJ_HEATSINK 2
 
+/* Adjoint kinds (lbm_desc_t.adjoint_kind).
+ *   DISCRETE    the fully consistent discrete adjoint of Sec. 2.4 (Eqs. 53-65).
+ *   CONTINUOUS  the continuous adjoint of Sec. 2.3 discretised as Eq. (30):
+ *               same collision and streaming, stepped collision -> streaming
+ *               -> boundary, with the boundary step of Eqs. (25)-(29)
+ *               generalised to any axis normal (every direction leaving the
+ *               domain at a port: f*_j = f*_jbar - 12 sum_{e_k.n>0} w_k f*_k
+ *               at an outlet, f*_j = f*_jbar - 2 dJ/drho at an inlet); the
+ *               inlet-pressure objective enters through that step.  Kept for
+ *               comparison: its boundary step cannot satisfy all of Eq. (25),
+ *               its dJ/dgamma is not the gradient and it loses stability at
+ *               lower Re.  Flow lattice only (LBM_EINVAL with thermal). */
+#define LBM_ADJOINT_DISCRETE 0
+#define LBM_ADJOINT_CONTINUOUS 1
+
 typedef struct lbm_desc {
   int32_t nx, ny, nz;      /* grid, each >= 3 (nz >= 3 too: D3Q19 only)      */
   int32_t thermal;         /* 0: flow only; 1: coupled D3Q7 temperature       */
@@ -130,6 +145,8 @@ typedef struct lbm_desc {
   int32_t max_steps;       /* step cap of each solve, >= 1                    */
   int32_t check_every;     /* steps between residual checks (0: never)        */
   double tol;              /* residual tolerance (0: run max_steps)           */
+  int32_t adjoint_kind;    /* LBM_ADJOINT_DISCRETE or LBM_ADJOINT_CONTINUOUS  */
+  int32_t reserved;        /* 0                                               */
 } lbm_desc_t;
 
 /* Result of a solve.  Residuals follow Sec. 3.1: |I(t) - I(t - c)| / |I(t)|

@@ -72,6 +72,9 @@ def _load():
         lib.orc_adjoint_d.restype = ctypes.c_int
         lib.orc_adjoint_d.argtypes = [P, P, P, P, P, P, ctypes.c_int, ctypes.c_double,
                                       ctypes.c_int, ctypes.c_int, P, P]
+        lib.orc_cont_adjoint_d.restype = ctypes.c_int
+        lib.orc_cont_adjoint_d.argtypes = [P, P, P, P, ctypes.c_int, ctypes.c_double,
+                                           ctypes.c_int, ctypes.c_int, P, P]
         lib.orc_bc_matrix.argtypes = [P, ctypes.c_int, P]
         lib.orc_bc_matrix_thermal.argtypes = [P, ctypes.c_int, P]
         lib.orc_lattice.argtypes = [P, ctypes.c_int, P, P]
@@ -321,6 +324,51 @@ class Oracle:
         return {"fsC": fsC, "gsC": gsC if self.thermal else None, "steps": int(steps[0]),
                 "status": int(st), "res": res}
 
+    # ------------------------------------------------- continuous adjoint (Sec. 2.3)
+    def cont_adjoint_bc(self, fsS, jfb=None):
+        """Boundary step of the continuous adjoint on streamed values fsS
+        [N, Q]; jfb is the boundary part of dJ/df (zero if None)."""
+        fsS = np.ascontiguousarray(fsS, dtype=np.float64)
+        jfb = np.zeros_like(fsS) if jfb is None else np.ascontiguousarray(jfb, dtype=np.float64)
+        out = np.zeros_like(fsS)
+        self.lib.orc_cont_adjoint_bc_d(self.h, _ptr(jfb), _ptr(fsS), _ptr(out))
+        return out
+
+    def cont_adjoint(self, f, gamma=None, max_steps=None, tol=None, check_every=None,
+                     state=None):
+        """Continuous adjoint solve (Eqs. 23-30, boundary step generalised from
+        Eqs. 25-29) from the converged forward state f; flow lattice only.
+        Returns dict(fsB, steps, status, res)."""
+        if self.thermal:
+            raise ValueError("oracle: the continuous adjoint is for the flow lattice only")
+        w = self.w
+        max_steps = w.max_steps if max_steps is None else max_steps
+        tol = w.tol if tol is None else tol
+        check_every = w.check_every if check_every is None else check_every
+        if state is None:
+            fsB = np.zeros((self.N, self.Q))
+            warm = 0
+        else:
+            fsB = np.array(state, dtype=np.float64, order="C", copy=True)
+            warm = 1
+        steps = np.zeros(1, dtype=np.int32)
+        res = np.zeros(2)
+        st = self.lib.orc_cont_adjoint_d(self.h, _ptr(self._gam(gamma)),
+                                         _ptr(np.ascontiguousarray(f, dtype=np.float64)),
+                                         _ptr(fsB), int(max_steps), float(tol), int(check_every),
+                                         warm, _ptr(steps), _ptr(res))
+        return {"fsB": fsB, "steps": int(steps[0]), "status": int(st), "res": res}
+
+    def cont_sensitivity(self, f, fsB, gamma=None):
+        """dJ/dgamma of the continuous adjoint (Eq. 32 with the exact
+        derivative of Eq. 12, as in Eq. 66)."""
+        dJ = np.zeros(self.N)
+        self.lib.orc_cont_sensitivity_d(self.h, _ptr(self._gam(gamma)),
+                                        _ptr(np.ascontiguousarray(f, dtype=np.float64)),
+                                        _ptr(np.ascontiguousarray(fsB, dtype=np.float64)),
+                                        _ptr(dJ))
+        return dJ
+
     def adjoint_monitor(self, fsS, gsS=None):
         out = np.zeros(2)
         self.lib.orc_adjoint_monitor_d(self.h, _ptr(np.ascontiguousarray(fsS, dtype=np.float64)),
@@ -354,6 +402,12 @@ class Oracle:
         f, g = fw["f"], fw["g"]
         rho, u, T = self.macro(f, g)
         J = self.objective(f, g, gamma)
+        if getattr(self.w, "adjoint_kind", 0) == 1:
+            ca = self.cont_adjoint(f, gamma, max_steps=adj_steps, tol=tol, check_every=check_every)
+            dJ = self.cont_sensitivity(f, ca["fsB"], gamma)
+            return {"f": f, "g": g, "rho": rho, "u": u, "T": T, "J": J, "dJ": dJ,
+                    "fwd_steps": fw["steps"], "fwd_status": fw["status"],
+                    "adj_steps": ca["steps"], "adj_status": ca["status"], "fsB": ca["fsB"]}
         ad = self.adjoint(f, g, gamma, max_steps=adj_steps, tol=tol, check_every=check_every)
         dJ = self.sensitivity(f, g, ad["fsC"], ad["gsC"], gamma)
         return {"f": f, "g": g, "rho": rho, "u": u, "T": T, "J": J, "dJ": dJ,

@@ -831,6 +831,116 @@ int adjoint(const Problem& P, const double* gamma, const double* f, const double
 }
 
 // ---------------------------------------------------------------------------
+// Continuous adjoint variant (Sec. 2.3): the adjoint equation discretised as in
+// Eq. (30), stepped in the order adjoint collision -> adjoint streaming ->
+// adjoint boundary condition, starting from f* = 0 (Eq. 24).  Collision and
+// streaming are the operators of the discrete adjoint above; the boundary
+// step is the one obtained from the boundary integral of Eq. (21):
+//   walls: bounce back (the adjoint of bounce back);
+//   ports: for every direction j leaving the domain through the port
+//          (e_j . n < 0, n the inward normal) the coefficient of delta f_j in
+//          sum_i (e_i . n_out) f*_i delta f_i + dJ, with the unknown
+//          delta f_k (e_k . n > 0) expressed through the boundary scheme,
+//          delta f_k = sum_j B_kj delta f_j, must vanish (Eqs. 25-26, 28):
+//            f*_j = sum_{k unknown} B_kj f*_k - sum_i B_ij dJ/df_i ,
+//          the other directions keep their streamed values.  The coefficients
+//          of the other delta f_j cannot be made zero as well; that is the
+//          inconsistency Sec. 2.3 points out.  For the D2Q9 outlet on the
+//          bottom wall and inlet on the left wall this is Eqs. (27) and (29).
+// The objective enters here only through its boundary part (the inlet
+// pressure of the pressure-drop objective, Eq. 22); a volume objective
+// (dissipation) stays a source in the collision.  Flow lattice only.
+// ---------------------------------------------------------------------------
+void cont_adjoint_bc(const Problem& P, const double* jfb, const double* fsS, double* fsB) {
+  const Lattice& L = P.F;
+  const int Q = L.Q;
+#pragma omp parallel for schedule(static)
+  for (int n = 0; n < P.N; ++n) {
+    const double* a = fsS + (size_t)n * Q;
+    double* out = fsB + (size_t)n * Q;
+    const int k = P.kind[n];
+    if (k == K_WALL || k == K_HEATED) {
+      for (int i = 0; i < Q; ++i) out[i] = a[L.opp[i]];
+      continue;
+    }
+    for (int i = 0; i < Q; ++i) out[i] = a[i];
+    if (k != K_INLET && k != K_OUTLET) continue;
+    double B[19 * 19];
+    bc_matrix(P, n, B);
+    const int* nv = NORMAL_VEC[P.ncode[n]];
+    for (int j = 0; j < Q; ++j) {
+      if (dir_class(L, j, nv) != -1) continue;
+      double v = 0.0;
+      for (int kk = 0; kk < Q; ++kk)
+        if (dir_class(L, kk, nv) == 1) v += B[kk * Q + j] * a[kk];
+      for (int i = 0; i < Q; ++i) v -= B[i * Q + j] * jfb[(size_t)n * Q + i];
+      out[j] = v;
+    }
+  }
+}
+
+// Split dJ/df into its boundary part (handled by the boundary step of the
+// continuous adjoint) and its volume part (a collision source).
+void cont_split_objective(const Problem& P, const double* jf, double* jfb, double* jfv) {
+  const size_t M = (size_t)P.N * P.F.Q;
+  const bool boundary = P.c.objective == OBJ_PRESSURE_DROP;
+  for (size_t i = 0; i < M; ++i) {
+    jfb[i] = boundary ? jf[i] : 0.0;
+    jfv[i] = boundary ? 0.0 : jf[i];
+  }
+}
+
+// One continuous adjoint step: y = C^T f*_B - (volume source), then
+// f*_S = S^T y (returned for the residual), f*_B = boundary step of f*_S.
+void cont_adjoint_step(const Problem& P, const double* gamma, const double* f, const double* jfb,
+                       const double* jfv, double* fsB, double* y, double* fsS) {
+  adjoint_collide(P, gamma, f, nullptr, fsB, nullptr, jfv, nullptr, y, nullptr);
+  adjoint_stream(P, y, nullptr, fsS, nullptr);
+  cont_adjoint_bc(P, jfb, fsS, fsB);
+}
+
+// Continuous adjoint solve from f*_B = 0 (or the given state when warm), with
+// the residual of the discrete solve taken on the streamed values.
+int cont_adjoint(const Problem& P, const double* gamma, const double* f, double* fsB, int max_steps,
+                 double tol, int check_every, int warm, int* steps_out, double* res_out) {
+  const int Q = P.F.Q;
+  const size_t M = (size_t)P.N * Q;
+  std::vector<double> jf(M), jg(1), jgam(P.N), jfb(M), jfv(M), y(M), fsS(M);
+  objective_grad(P, gamma, f, nullptr, jf.data(), jg.data(), jgam.data());
+  cont_split_objective(P, jf.data(), jfb.data(), jfv.data());
+  if (!warm) std::fill(fsB, fsB + M, 0.0);
+  double prev = 0, res = 0;
+  bool have_prev = false;
+  int status = 1, k = 0;
+  for (k = 1; k <= max_steps; ++k) {
+    cont_adjoint_step(P, gamma, f, jfb.data(), jfv.data(), fsB, y.data(), fsS.data());
+    if (check_every > 0 && k % check_every == 0) {
+      double If, Ig;
+      adjoint_monitor(P, fsS.data(), nullptr, If, Ig);
+      if (!std::isfinite(If)) {
+        status = -1;
+        break;
+      }
+      if (have_prev) {
+        res = std::fabs(If - prev) / std::max(std::fabs(If), 1e-300);
+        if (rel_converged(If, prev, tol)) {
+          status = 0;
+          break;
+        }
+      }
+      prev = If;
+      have_prev = true;
+    }
+  }
+  if (steps_out) *steps_out = std::min(k, max_steps);
+  if (res_out) {
+    res_out[0] = res;
+    res_out[1] = 0.0;
+  }
+  return status;
+}
+
+// ---------------------------------------------------------------------------
 // Sensitivity contraction of Eq. (66) (first equality), with the exact
 // derivative of the collision with respect to the design variable:
 //   sum_i f*_S,i dC_i/dgamma + sum_i g*_S,i dC^g_i/dgamma, where
@@ -1143,6 +1253,33 @@ void orc_sensitivity_d(void* h, const double* gam, const double* f, const double
   std::vector<double> jf((size_t)P.N * Q), jg(P.thermal ? (size_t)P.N * Qg : 1), jgam(P.N), c(P.N);
   objective_grad(P, gam, f, g, jf.data(), jg.data(), jgam.data());
   sens_contract(P, gam, f, g, fsS.data(), gsS.data(), c.data());
+  for (int n = 0; n < P.N; ++n) dJ[n] = P.is_design(n) ? jgam[n] - c[n] : 0.0;
+}
+
+void orc_cont_adjoint_bc_d(void* h, const double* jfb, const double* fsS, double* fsB) {
+  cont_adjoint_bc(*static_cast<Problem*>(h), jfb, fsS, fsB);
+}
+
+int orc_cont_adjoint_d(void* h, const double* gam, const double* f, double* fsB, int max_steps, double tol,
+                       int check_every, int warm, int32_t* steps, double* res) {
+  const Problem& P = *static_cast<Problem*>(h);
+  if (P.thermal) {
+    g_err = "continuous adjoint: flow lattice only";
+    return -2;
+  }
+  return cont_adjoint(P, gam, f, fsB, max_steps, tol, check_every, warm, steps, res);
+}
+
+// Continuous sensitivity, Eq. (32) with the exact derivative of Eq. (12) (as
+// in Eq. 66): explicit dJ/dgamma - sum_i f*_i dC_i/dgamma with f* the adjoint
+// state after the boundary step (equal to the streamed values at the design
+// nodes, which are interior).
+void orc_cont_sensitivity_d(void* h, const double* gam, const double* f, const double* fsB, double* dJ) {
+  const Problem& P = *static_cast<Problem*>(h);
+  const int Q = P.F.Q;
+  std::vector<double> jf((size_t)P.N * Q), jg(1), jgam(P.N), c(P.N);
+  objective_grad(P, gam, f, nullptr, jf.data(), jg.data(), jgam.data());
+  sens_contract(P, gam, f, nullptr, fsB, nullptr, c.data());
   for (int n = 0; n < P.N; ++n) dJ[n] = P.is_design(n) ? jgam[n] - c[n] : 0.0;
 }
 

@@ -67,6 +67,11 @@ int validate_and_setup(lbm_problem* p, const lbm_desc_t& d, const uint8_t* mask)
   if (d.max_steps < 1) return fail(LBM_EINVAL, "max_steps must be >= 1");
   if (d.check_every < 0) return fail(LBM_EINVAL, "check_every must be >= 0");
   if (!(d.tol >= 0.0)) return fail(LBM_EINVAL, "tol must be >= 0");
+  if (d.adjoint_kind != LBM_ADJOINT_DISCRETE && d.adjoint_kind != LBM_ADJOINT_CONTINUOUS)
+    return fail(LBM_EINVAL, "unknown adjoint kind");
+  if (d.adjoint_kind == LBM_ADJOINT_CONTINUOUS && d.thermal)
+    return fail(LBM_EINVAL, "the continuous adjoint is for the flow lattice only");
+  if (d.reserved != 0) return fail(LBM_EINVAL, "reserved must be 0");
   if (!(d.alpha_max >= 0.0) || !(d.q_brink > 0.0)) return fail(LBM_EINVAL, "need alpha_max >= 0, q > 0");
   if (!(d.tau * d.alpha_max < 1.0)) return fail(LBM_EINVAL, "tau * alpha_max must be < 1 (chi > 0)");
   if (d.thermal) {
@@ -205,6 +210,7 @@ int validate_and_setup(lbm_problem* p, const lbm_desc_t& d, const uint8_t* mask)
   k.c_layer = p->n_layer > 0 ? (float)(1.0 / p->n_layer) : 0.0f;
   k.two_nu = (float)(2.0 * nu);
   k.nu = (float)nu;
+  k.cont = d.adjoint_kind == LBM_ADJOINT_CONTINUOUS ? 1 : 0;
   return LBM_OK;
 }
 

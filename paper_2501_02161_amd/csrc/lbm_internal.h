@@ -45,6 +45,7 @@ struct KParams {
   float c_layer;                 // 1 / N_layer: dJ/dg_i at objective-layer nodes
   float two_nu;                  // 2 nu (dissipation source)
   float nu;
+  int cont;                      // adjoint: 1 = continuous variant (flow lattice only)
 };
 
 struct FwdArgs {

@@ -192,6 +192,31 @@ __device__ __forceinline__ void zou_he(float (&h)[19], Normal nv, bool inlet, fl
 //   f*_j = c_j - 1/2 e_j.P - [outlet] S6,
 // for outgoing j:  f*_j = c_j + c_jbar - [outlet] 2 S6,
 // with P = sum_{unknown i} e_i c_i and S6 = sum_{unknown i} 6 w_i c_i.
+// Boundary step of the continuous adjoint (Sec. 2.3, Eqs. 25-29 generalised to
+// any axis normal): on the streamed values of a port node, every direction
+// leaving the domain (e_j . n < 0) takes
+//   f*_j = f*_jbar - 12 sum_{e_k.n > 0} w_k f*_k   (pressure outlet)
+//   f*_j = f*_jbar - src                         (velocity inlet; src = twice
+//                                                  the objective's weight)
+// which zeroes the coefficient of delta f_j in the boundary integral of
+// Eq. (21); the other directions keep their values.
+__device__ __forceinline__ void zou_he_continuous(float (&a)[19], Normal nv, bool outlet, float src) {
+  float S12 = 0.f;
+  sfor<19>([&](auto I) {
+    constexpr int i = I;
+    const int cl = Q19::ex[i] * nv.x + Q19::ey[i] * nv.y + Q19::ez[i] * nv.z;
+    S12 += (cl > 0) ? (12.0f * Q19::w[i]) * a[i] : 0.f;
+  });
+  const float sub = outlet ? S12 : src;
+  float o[19];
+  sfor<19>([&](auto I) {
+    constexpr int j = I;
+    const int cl = Q19::ex[j] * nv.x + Q19::ey[j] * nv.y + Q19::ez[j] * nv.z;
+    o[j] = (cl < 0) ? a[Q19::opp[j]] - sub : a[j];
+  });
+  sfor<19>([&](auto I) { a[I] = o[I]; });
+}
+
 __device__ __forceinline__ void zou_he_transpose(float (&c)[19], Normal nv, bool outlet) {
   float S6 = 0.f, Px = 0.f, Py = 0.f, Pz = 0.f;
   sfor<19>([&](auto I) {
@@ -391,8 +416,9 @@ __global__ __launch_bounds__(kBlock) void k_forward(FwdArgs A) {
 // the coupling from the thermal lattice adds e_i.W, W = 4 T/(tau_g rho0) sum w b e,
 // and the thermal transpose is (1 - 1/tau_g) b_i + (1/tau_g) sum w b (1 + 4 e.u).
 // ---------------------------------------------------------------------------
-template <bool THERMAL, int OBJ, bool DIAG>
+template <bool THERMAL, int OBJ, bool DIAG, bool CONT = false>
 __device__ __forceinline__ void adjoint_tile(const AdjArgs& A, int blk) {
+  static_assert(!(CONT && THERMAL), "the continuous variant is for the flow lattice");
   const KParams& P = A.P;
   const int n = blk * kBlock + threadIdx.x;
   double acc[kRedAdj] = {0.0, 0.0};
@@ -434,6 +460,15 @@ __device__ __forceinline__ void adjoint_tile(const AdjArgs& A, int blk) {
           sfor<7>([&](auto I) { sb += b[I]; });
           acc[1] = fabs((double)sb);
         }
+      }
+    }
+    if constexpr (CONT) {
+      // continuous variant: boundary step on the streamed values, before the
+      // collision (order collision -> streaming -> boundary of Eq. 30); the
+      // inlet-pressure objective enters here and not as a collision source
+      if (kind == K_INLET || kind == K_OUTLET) {
+        const float src = (OBJ == OBJ_PRESSURE_DROP && kind == K_INLET) ? 2.0f * P.c_in : 0.0f;
+        zou_he_continuous(a, normal_of(nc), kind == K_OUTLET, src);
       }
     }
     if (kind >= K_WALL) {
@@ -490,7 +525,7 @@ __device__ __forceinline__ void adjoint_tile(const AdjArgs& A, int blk) {
       }
       // objective sources dJ/df_i = c + e_i.G and dJ/dg_i = d
       float csrc = 0.f, dsrc = 0.f, Gx = 0.f, Gy = 0.f, Gz = 0.f;
-      if constexpr (OBJ == OBJ_PRESSURE_DROP || OBJ == OBJ_HEATSINK) {
+      if constexpr ((OBJ == OBJ_PRESSURE_DROP || OBJ == OBJ_HEATSINK) && !CONT) {
         if (kind == K_INLET) csrc = P.c_in;
       }
       if constexpr (OBJ == OBJ_HEATSINK) {
@@ -514,8 +549,10 @@ __device__ __forceinline__ void adjoint_tile(const AdjArgs& A, int blk) {
         if constexpr (Q19::ez[i] != 0) v += float(Q19::ez[i]) * Sz;
         c[i] = v;
       });
-      if (kind == K_INLET || kind == K_OUTLET)
-        zou_he_transpose(c, normal_of(nc), kind == K_OUTLET);
+      if constexpr (!CONT) {
+        if (kind == K_INLET || kind == K_OUTLET)
+          zou_he_transpose(c, normal_of(nc), kind == K_OUTLET);
+      }
       sfor<19>([&](auto I) { A.aout[(size_t)I * P.Np + n] = c[I]; });
       if constexpr (THERMAL) {
         float cg[7];
@@ -538,9 +575,9 @@ __device__ __forceinline__ void adjoint_tile(const AdjArgs& A, int blk) {
   if constexpr (DIAG) block_reduce_store<kRedAdj>(acc, A.partials + (size_t)blk * kRedAdj);
 }
 
-template <bool THERMAL, int OBJ, bool DIAG>
+template <bool THERMAL, int OBJ, bool DIAG, bool CONT = false>
 __global__ __launch_bounds__(kBlock) void k_adjoint(AdjArgs A) {
-  adjoint_tile<THERMAL, OBJ, DIAG>(A, remap_block(blockIdx.x, A.P));
+  adjoint_tile<THERMAL, OBJ, DIAG, CONT>(A, remap_block(blockIdx.x, A.P));
 }
 
 // ---------------------------------------------------------------------------
@@ -743,6 +780,13 @@ __global__ __launch_bounds__(kBlock) void k_batch(const Tile* __restrict__ tiles
       A.bin = S.aa.bout;
       A.bout = const_cast<float*>(S.aa.bin);
     }
+    if constexpr (!THERMAL) {
+      if (A.P.cont) {
+        if (diag) adjoint_tile<THERMAL, OBJ, true, true>(A, tl.blk);
+        else adjoint_tile<THERMAL, OBJ, false, true>(A, tl.blk);
+        return;
+      }
+    }
     if (diag) adjoint_tile<THERMAL, OBJ, true>(A, tl.blk);
     else adjoint_tile<THERMAL, OBJ, false>(A, tl.blk);
   }
@@ -871,6 +915,13 @@ hipError_t launch_forward(const FwdArgs& a, bool thermal, bool diag, hipStream_t
 
 template <bool TH, int OBJ>
 static void adj_dispatch(const AdjArgs& a, bool diag, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+  if constexpr (!TH) {
+    if (a.P.cont) {
+      if (diag) launch_step(k_adjoint<TH, OBJ, true, true>, a.P.nblk, a, s, ev0, ev1);
+      else launch_step(k_adjoint<TH, OBJ, false, true>, a.P.nblk, a, s, ev0, ev1);
+      return;
+    }
+  }
   if (diag) launch_step(k_adjoint<TH, OBJ, true>, a.P.nblk, a, s, ev0, ev1);
   else launch_step(k_adjoint<TH, OBJ, false>, a.P.nblk, a, s, ev0, ev1);
 }

@@ -19,6 +19,7 @@ import torch
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_build", "liblbmadj.so")
 
 LBM_OK, LBM_NOT_CONVERGED = 0, 1
+LBM_ADJOINT_DISCRETE, LBM_ADJOINT_CONTINUOUS = 0, 1
 LBM_EINVAL, LBM_ESTATE, LBM_ENOMEM, LBM_EDEVICE, LBM_EDIVERGED = -1, -2, -3, -4, -5
 STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "EINVAL", -2: "ESTATE", -3: "ENOMEM",
                 -4: "EDEVICE", -5: "EDIVERGED"}
@@ -40,7 +41,8 @@ class lbm_desc_t(ctypes.Structure):
                 ("alpha_max", c_double), ("q_brink", c_double), ("Pr", c_double),
                 ("k_ratio", c_double), ("q_ramp", c_double), ("q_w", c_double),
                 ("T_in", c_double), ("w_dp", c_double),
-                ("max_steps", c_int32), ("check_every", c_int32), ("tol", c_double)]
+                ("max_steps", c_int32), ("check_every", c_int32), ("tol", c_double),
+                ("adjoint_kind", c_int32), ("reserved", c_int32)]
 
 
 class lbm_info_t(ctypes.Structure):
@@ -329,6 +331,7 @@ def make_desc(spec) -> lbm_desc_t:
         setattr(d, name, float(getattr(spec, name)))
     d.max_steps = int(spec.max_steps)
     d.check_every = int(spec.check_every)
+    d.adjoint_kind = int(getattr(spec, "adjoint_kind", LBM_ADJOINT_DISCRETE))
     return d
 
 

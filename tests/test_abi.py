@@ -36,9 +36,10 @@ def test_every_declared_symbol_is_exported(lbm):
 
 
 def test_struct_layout_matches_header(lbm):
-    # doubles start at offset 32 and the struct is 144 bytes (see the header)
+    # doubles start at offset 32 and the struct is 152 bytes (see the header)
     assert lbm.lbm_desc_t.tau.offset == 32
-    assert ctypes.sizeof(lbm.lbm_desc_t) == 144
+    assert lbm.lbm_desc_t.adjoint_kind.offset == 144
+    assert ctypes.sizeof(lbm.lbm_desc_t) == 152
     assert ctypes.sizeof(lbm.lbm_info_t) == 48
 
 

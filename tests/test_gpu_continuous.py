@@ -1,0 +1,96 @@
+"""GPU parity of the continuous adjoint variant (Sec. 2.3, adjoint_kind =
+LBM_ADJOINT_CONTINUOUS) against the oracle's continuous adjoint:
+
+* fixed step counts on a small 3D pipe bend, both flow objectives
+  (pressure drop: the objective enters through the inlet boundary step;
+  dissipation: a volume source), fields 1e-5 and dJ/dgamma 1e-4;
+* converged solves on a 32^3 pipe bend;
+* one adjoint step from the GPU's own state on the full 96^3 pipe bend.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+from _parity import compare_solution, gpu_fields, gpu_pops, kinds, rel, run_gpu, run_oracle
+from paper_2501_02161_amd import lbm
+
+pytestmark = pytest.mark.gpu
+
+CONT = lbm.LBM_ADJOINT_CONTINUOUS
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    torch.cuda.set_device(0)
+    yield
+
+
+@pytest.mark.parametrize("objective", [W.OBJ_PRESSURE_DROP, W.OBJ_DISSIPATION])
+def test_continuous_fixed_steps_parity(objective):
+    w = W.tiny_pipe_bend_3d(n=14, objective=objective, Re=5.0).replace(adjoint_kind=CONT)
+    print(f"[cont] fixed steps, objective {objective}", flush=True)
+    prob, res = run_gpu(w, steps=600, tol=0.0, check_every=200)
+    o, ref = run_oracle(w, steps=600, tol=0.0, check_every=200)
+    err = compare_solution(w, prob, ref)
+    print(f"[cont] objective {objective} errors {err}", flush=True)
+    assert res["adjoint"]["steps"] == 600
+
+
+def test_continuous_converged_parity():
+    w = W.pipe_bend_3d(n=32, tau=0.8, Re=10.0, port=8, objective=W.OBJ_PRESSURE_DROP)
+    w = w.replace(adjoint_kind=CONT, max_steps=40000, tol=1e-7, check_every=500)
+    print(f"[cont] converged {w.nx}^3", flush=True)
+    prob, res = run_gpu(w)
+    assert res["forward"]["status"] == 0 and res["adjoint"]["status"] == 0
+    o = oracle.Oracle(w)
+    ref = o.solve(tol=1e-11, check_every=500, fwd_steps=200000, adj_steps=200000)
+    assert ref["fwd_status"] == 0 and ref["adj_status"] == 0
+    err = compare_solution(w, prob, ref)
+    # the discrete gradient of the same problem differs: the variant is not the gradient
+    pd = lbm.Problem(w.replace(adjoint_kind=lbm.LBM_ADJOINT_DISCRETE), device="cuda:0")
+    pd.solve(w.gamma)
+    d = kinds(w) == W.DESIGN
+    g_disc = pd.dJ.reshape(-1).cpu().numpy().astype(np.float64)[d]
+    g_cont = prob.dJ.reshape(-1).cpu().numpy().astype(np.float64)[d]
+    print(f"[cont] steps gpu {res['forward']['steps']}/{res['adjoint']['steps']} errors {err}; "
+          f"continuous vs discrete gradient {rel(g_cont, g_disc):.3f}", flush=True)
+    assert rel(g_cont, g_disc) > 1e-2
+
+
+def test_continuous_full_size_step_parity():
+    w = W.pipe_bend_3d(objective=W.OBJ_PRESSURE_DROP).replace(adjoint_kind=CONT)
+    print(f"[cont] full {w.nx}^3 one-step check", flush=True)
+    prob = lbm.Problem(w.replace(max_steps=200, tol=0.0, check_every=100), device="cuda:0")
+    o = oracle.Oracle(w)
+    k = kinds(w)
+    live, design = k < W.WALL, k == W.DESIGN
+    prob.forward(w.gamma)
+    prob.adjoint(w.gamma)
+    y0 = gpu_pops(prob, lbm.STATE_ADJ_FLOW, o)
+    prob.adjoint_continue(1)
+    torch.cuda.synchronize()
+    drho, u, _, _ = gpu_fields(prob)
+    e19, w19 = o.lattice(0)
+    f_state = w19[None, :] * ((w.rho0 + drho)[:, None] + 3.0 * w.rho0 * (u @ e19.T.astype(float)))
+    jf, _, jgam = o.objective_grad(f_state)
+    fsS, _ = o.adjoint_stream(y0)
+    fsB = o.cont_adjoint_bc(fsS, jf)               # pressure drop: boundary objective
+    y1, _ = o.adjoint_collide(f_state, None, fsB, None, np.zeros_like(jf))
+    err = {"adj_step_f": rel(gpu_pops(prob, lbm.STATE_ADJ_FLOW, o)[live], y1[live])}
+    prob.sensitivity()
+    torch.cuda.synchronize()
+    fsS1, _ = o.adjoint_stream(gpu_pops(prob, lbm.STATE_ADJ_FLOW, o))
+    dJ_ref = jgam - o.sens_contract(f_state, None, fsS1)
+    err["sens"] = rel(prob.dJ.reshape(-1).cpu().numpy()[design], dJ_ref[design])
+    print(f"[cont] full errors {err}", flush=True)
+    assert err["adj_step_f"] < 1e-5 and err["sens"] < 1e-4
+
+
+def test_continuous_rejected_with_thermal():
+    w = W.tiny_heat_sink().replace(adjoint_kind=CONT)
+    with pytest.raises(lbm.LBMError) as e:
+        lbm.Problem(w, device="cuda:0")
+    assert e.value.code == lbm.LBM_EINVAL

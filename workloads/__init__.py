@@ -67,6 +67,7 @@ class Workload:
     tol: float = 1e-7
     check_every: int = 1000
     seed: int = 0
+    adjoint_kind: int = 0                 # 0 discrete (Sec. 2.4), 1 continuous (Sec. 2.3)
 
     @property
     def N(self) -> int:

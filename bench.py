@@ -76,6 +76,11 @@ def parse():
                          "resident request every quantum (all)")
     ap.add_argument("--serving-fill", type=int, default=512,
                     help="tiles of 256 nodes per launch the srw policy fills up to")
+    ap.add_argument("--stability", action="store_true",
+                    help="run the adjoint stability sweep (3D pipe bend, discrete vs continuous "
+                         "adjoint) and print its JSON object")
+    ap.add_argument("--stability-steps", type=int, default=1000000,
+                    help="step cap of each forward and adjoint solve in the stability sweep")
     ap.add_argument("--serving-only", action="store_true",
                     help="run only the serving leg and print its JSON object")
     return ap.parse_args()
@@ -224,6 +229,28 @@ def serving_leg(n, rate, policy="srw", fill=512):
             "batch_launches": st["launches"]}
 
 
+def stability_leg(steps):
+    """Largest stable inlet speed per relaxation time for the primal, discrete
+    adjoint and continuous adjoint solves (Sec. 3.1) on the 3D pipe bend
+    32^3, every point a request of the batch engine."""
+    import torch
+    from paper_2501_02161_amd import stability
+
+    torch.cuda.set_device(0)
+    taus = (0.52, 0.55, 0.6, 0.7, 0.8, 1.0)
+    speeds = (0.02, 0.04, 0.06, 0.08, 0.1, 0.12, 0.15, 0.2, 0.25, 0.3, 0.35, 0.4, 0.5)
+    t0 = time.perf_counter()
+    points, limits = stability.sweep(
+        taus, speeds, n=32, max_steps=steps,
+        log=lambda m: print(f"[stability] {m}", file=sys.stderr, flush=True))
+    el = time.perf_counter() - t0
+    table = {f"{tau:g}": {k: v for k, v in lim.items()} for tau, lim in limits.items()}
+    pts = {f"tau {t:g} u {u:g} {'cont' if k else 'disc'}": list(v) for (t, u, k), v in points.items()}
+    return {"workload": "pipe_bend_3d_32^3 (port 5, pressure drop)", "steps_cap": steps,
+            "taus": list(taus), "speeds": list(speeds), "max_stable_speed": table,
+            "seconds": round(el, 1), "points": pts}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -236,6 +263,9 @@ def main():
         return
     if args.copy_bw:
         copy_bandwidth()
+        return
+    if args.stability:
+        print(json.dumps({"stability": stability_leg(args.stability_steps)}), flush=True)
         return
     if args.serving_only:
         print(json.dumps({"serving": serving_leg(args.serving_requests or 256,

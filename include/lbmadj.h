@@ -295,8 +295,9 @@ typedef struct lbm_batch_result {
   int32_t state;           /* LBM_BATCH_*                                      */
   int32_t status;          /* LBM_OK, LBM_NOT_CONVERGED or LBM_EDIVERGED        */
   int32_t nodes;           /* N of the request                                  */
-  int32_t fwd_steps;       /* steps taken (so far) by the forward sweep         */
-  int32_t adj_steps;       /* steps taken (so far) by the adjoint sweep         */
+  int32_t fwd_steps;       /* steps taken (so far, or until it failed) by the   */
+                           /* forward sweep                                     */
+  int32_t adj_steps;       /* same for the adjoint sweep (0: never started)     */
   int32_t reserved;
   double J;                /* objective (DONE only)                             */
 } lbm_batch_result_t;

@@ -424,6 +424,8 @@ int after_quantum(lbm_batch* b, int i, Lane& ln) {
   s.mon[1] = sums[1] / p->n_nonwall;
   if (!std::isfinite(s.mon[0]) || !std::isfinite(s.mon[1])) {
     s.error = std::string(s.phase == PH_FORWARD ? "forward" : "adjoint") + " sweep diverged";
+    if (s.phase == PH_FORWARD) s.fwd_steps = done;
+    else s.adj_steps = done;  // adj_steps > 0 tells a failed adjoint from a failed forward
     s.phase = PH_FAILED;
     s.status = LBM_EDIVERGED;
     return LBM_OK;

@@ -227,6 +227,19 @@ def serving_request(i: int, base_seed: int = SEED_BASE + 4) -> Workload:
     return w
 
 
+def stability_case(n: int, tau: float, u_peak: float, adjoint_kind: int, seed: int = SEED_BASE + 6,
+                   max_steps: int = 1000000, tol: float = 1e-9) -> Workload:
+    """One point of the stability test (a 3D pipe bend on n^3 at relaxation
+    time tau and peak inlet speed u_peak, pressure-drop objective, given
+    adjoint kind): Re = u_peak L / nu with L the port width."""
+    w = pipe_bend_3d(n=n, tau=tau, Re=1.0, sigma=max(1.0, n / 24.0), seed=seed,
+                     port=max(4, n // 6), objective=OBJ_PRESSURE_DROP)
+    nu = (tau - 0.5) / 3.0
+    return w.replace(Re=u_peak * w.L_ref / nu, adjoint_kind=adjoint_kind, max_steps=max_steps,
+                     tol=tol, check_every=1000,
+                     name=f"stability_{n}_tau{tau:g}_u{u_peak:g}_k{adjoint_kind}")
+
+
 def poisson_arrivals(n: int, rate: float, seed: int = SEED_BASE + 5) -> np.ndarray:
     """Arrival times (seconds) of n requests with exponential gaps at `rate`/s."""
     rng = np.random.Generator(np.random.PCG64(seed))

@@ -34,6 +34,14 @@ sys.path.insert(0, ROOT)
 METRIC = "fwd+adj MLUPS & % HBM peak (D3Q19+D3Q7 FP32); p50/p99 sensitivity latency"
 HBM_PEAK_GBS = 8000.0
 
+def bytes_per_node(kernel, w):
+    """Algorithmic bytes per node-update of a step kernel for workload w."""
+    b = BYTES_PER_NODE[(kernel, bool(w.thermal))]
+    if kernel == "adjoint" and w.objective == 1:  # dissipation: source G (3 floats)
+        b += 12
+    return b
+
+
 # Algorithmic bytes per node-update: every population read once and written
 # once (4 B each), plus the per-node inputs each kernel reads once.
 BYTES_PER_NODE = {
@@ -53,7 +61,11 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="heat_sink_Re200",
                     choices=["heat_sink_Re50", "heat_sink_Re200", "heat_sink_Re400",
-                             "heat_sink_320x160x80_Re200"])
+                             "heat_sink_320x160x80_Re200", "pipe_bend_96", "pipe_bend_96_dp"])
+    ap.add_argument("--re", type=float, default=0.0,
+                    help="Reynolds number of a pipe-bend workload (0: the workload's own)")
+    ap.add_argument("--adjoint", default="discrete", choices=["discrete", "continuous"],
+                    help="adjoint kind (the continuous variant is for the flow-only pipe bend)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-fwd-steps", type=int, default=0,
                     help="oracle sample size in forward steps (0: 48)")
@@ -99,7 +111,7 @@ def profile_run(args):
     for _ in range(2):
         dst.copy_(src)
     torch.cuda.synchronize()
-    w = make_workload(args.workload).replace(max_steps=args.fixed_steps, tol=0.0,
+    w = make_workload(args.workload, args.adjoint, args.re).replace(max_steps=args.fixed_steps, tol=0.0,
                                              check_every=1000)
     prob = lbm.Problem(w, device="cuda:0")
     res = prob.solve(w.gamma)
@@ -153,8 +165,14 @@ def counter_traffic(workload, kernel):
     return int((k["fetch_kib"] * c["fetch_scale"] + k["write_kib"] * c["write_scale"]) * 1024)
 
 
-def make_workload(name):
+def make_workload(name, adjoint="discrete", Re=0.0):
     import workloads as W
+    kind = 1 if adjoint == "continuous" else 0
+    if name.startswith("pipe_bend_96"):
+        obj = W.OBJ_PRESSURE_DROP if name.endswith("_dp") else W.OBJ_DISSIPATION
+        w = W.pipe_bend_3d(objective=obj, **({"Re": Re} if Re > 0 else {}))
+        return w.replace(adjoint_kind=kind, name=w.name + ("_dp" if name.endswith("_dp") else "")
+                         + (f"_Re{Re:g}" if Re > 0 else "") + ("_continuous" if kind else ""))
     if name == "heat_sink_320x160x80_Re200":
         return W.heat_sink(320, 160, 80, Re=200.0, name="heat_sink_320x160x80_Re200")
     Re = float(name.split("Re")[1])
@@ -171,7 +189,10 @@ def cpu_baseline(w, fwd_steps):
     fw = o.forward(max_steps=fwd_steps, tol=0.0, check_every=0)
     t1 = time.perf_counter()
     adj_steps = max(1, fwd_steps // 4)
-    o.adjoint(fw["f"], fw["g"], max_steps=adj_steps, tol=0.0, check_every=0)
+    if getattr(w, "adjoint_kind", 0) == 1:
+        o.cont_adjoint(fw["f"], max_steps=adj_steps, tol=0.0, check_every=0)
+    else:
+        o.adjoint(fw["f"], fw["g"], max_steps=adj_steps, tol=0.0, check_every=0)
     t2 = time.perf_counter()
     tf = (t1 - t0) / fwd_steps
     ta = (t2 - t1) / adj_steps
@@ -278,7 +299,7 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    w = make_workload(args.workload)
+    w = make_workload(args.workload, args.adjoint, args.re)
     prob = lbm.Problem(w, device="cuda:0")
     gamma = prob.gamma_tensor(w.gamma)
     stream = torch.cuda.current_stream()
@@ -310,11 +331,11 @@ def main():
     kernels = {"forward": (ms_f, n_f), "adjoint": (ms_a, n_a)}
     dom = max(kernels, key=lambda k: kernels[k][0])
     ms_tot, n_launch = kernels[dom]
-    bpn = BYTES_PER_NODE[(dom, bool(w.thermal))]
+    bpn = bytes_per_node(dom, w)
     achieved = bpn * w.N / (ms_tot / 1e3 / n_launch) / 1e9 if n_launch else None
     per_kernel = {}
     for k, (ms, n) in kernels.items():
-        b = BYTES_PER_NODE[(k, bool(w.thermal))]
+        b = bytes_per_node(k, w)
         per_kernel[k] = {"avg_us": round(ms * 1e3 / n, 3) if n else None, "launches": n,
                          "bytes_per_node": b,
                          "GBps": round(b * w.N / (ms / 1e3 / n) / 1e9, 1) if n else None}
@@ -331,8 +352,12 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": w.name, "nodes": w.N, "lattice": "D3Q19+D3Q7",
-                   "objective": "mean floor-layer T + 0.1 pressure drop", "tau": round(w.tau, 6),
+        "config": {"workload": w.name, "nodes": w.N,
+                   "lattice": "D3Q19+D3Q7" if w.thermal else "D3Q19",
+                   "objective": {0: "pressure drop", 1: "viscous dissipation",
+                                 2: "mean floor-layer T + 0.1 pressure drop"}[w.objective],
+                   "adjoint": "continuous" if w.adjoint_kind else "discrete",
+                   "tau": round(w.tau, 6),
                    "tol": w.tol, "max_steps": w.max_steps, "fwd_steps": fi["steps"],
                    "adj_steps": ai["steps"], "J": J},
         "roofline": {"bound": "hbm", "kernel": dom,
@@ -343,8 +368,8 @@ def main():
                      "algorithmic_bytes_per_launch": bpn * w.N},
         "kernels": per_kernel,
         "hbm_frac_whole_job": round(
-            (BYTES_PER_NODE[("forward", bool(w.thermal))] * w.N * fi["steps"] +
-             BYTES_PER_NODE[("adjoint", bool(w.thermal))] * w.N * ai["steps"]) * args.steps /
+            (bytes_per_node("forward", w) * w.N * fi["steps"] +
+             bytes_per_node("adjoint", w) * w.N * ai["steps"]) * args.steps /
             elapsed / 1e9 / HBM_PEAK_GBS, 4),
     }
     prob.close()

@@ -46,7 +46,9 @@ class OrcConfig(ctypes.Structure):
                 ("L_ref", ctypes.c_double), ("alpha_max", ctypes.c_double),
                 ("q_brink", ctypes.c_double), ("Pr", ctypes.c_double),
                 ("k_ratio", ctypes.c_double), ("q_ramp", ctypes.c_double),
-                ("q_w", ctypes.c_double), ("T_in", ctypes.c_double), ("w_dp", ctypes.c_double)]
+                ("q_w", ctypes.c_double), ("T_in", ctypes.c_double), ("w_dp", ctypes.c_double),
+                ("symmetric", ctypes.c_int32 * 3), ("pad", ctypes.c_int32),
+                ("inlet_rho", ctypes.c_double), ("beta_max", ctypes.c_double)]
 
 
 def _load():
@@ -99,7 +101,10 @@ class Oracle:
                         objective=int(w.objective), tau=w.tau, rho0=w.rho0, Re=w.Re,
                         L_ref=w.L_ref, alpha_max=w.alpha_max, q_brink=w.q_brink, Pr=w.Pr,
                         k_ratio=w.k_ratio, q_ramp=w.q_ramp, q_w=w.q_w, T_in=w.T_in,
-                        w_dp=w.w_dp)
+                        w_dp=w.w_dp, inlet_rho=float(getattr(w, "inlet_rho", 0.0)),
+                        beta_max=float(getattr(w, "beta_max", 0.0)))
+        for a, v in enumerate(getattr(w, "symmetric", (0, 0, 0))):
+            cfg.symmetric[a] = int(bool(v))
         self._cfg = cfg
         mask = np.ascontiguousarray(w.mask, dtype=np.uint8).reshape(-1)
         self._mask = mask

@@ -46,8 +46,8 @@ inline double re(double v) { return v; }
 inline double re(const cplx& v) { return v.real(); }
 
 // Node kinds and normal codes of the mask byte (input format).
-enum Kind { K_DESIGN = 0, K_FLUID = 1, K_INLET = 2, K_OUTLET = 3, K_WALL = 4, K_HEATED = 5 };
-enum Objective { OBJ_PRESSURE_DROP = 0, OBJ_DISSIPATION = 1, OBJ_HEATSINK = 2 };
+enum Kind { K_DESIGN = 0, K_FLUID = 1, K_INLET = 2, K_OUTLET = 3, K_WALL = 4, K_HEATED = 5, K_SYM = 6 };
+enum Objective { OBJ_PRESSURE_DROP = 0, OBJ_DISSIPATION = 1, OBJ_HEATSINK = 2, OBJ_HEATGEN = 3 };
 const int NORMAL_VEC[6][3] = {{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
 
 // ---------------------------------------------------------------------------
@@ -121,6 +121,11 @@ Lattice make_d3q7() {
 struct OrcConfig {
   int32_t nx, ny, nz, dim, thermal, objective;
   double tau, rho0, Re, L_ref, alpha_max, q_brink, Pr, k_ratio, q_ramp, q_w, T_in, w_dp;
+  // symmetric[a] = 1: mirror plane between layers n_a - 2 and n_a - 1 of axis a
+  // (layer n_a - 1 holds SYM nodes); inlet_rho > 0: pressure inlets at that
+  // density; beta_max > 0: volumetric heat generation beta(gamma) (1 - T)
+  int32_t symmetric[3], pad;
+  double inlet_rho, beta_max;
 };
 
 namespace {
@@ -132,6 +137,9 @@ struct Problem {
   bool thermal = false;
   double nu = 0, U_peak = 0, Df = 0;
   std::vector<int> kind, ncode;   // per node
+  // streaming as a gather: slot (n, i) of the streamed state takes slot
+  // src[n*Q + i] of the post-collision state (flow F, thermal G)
+  std::vector<int64_t> srcF, srcG;
   std::vector<double> u_in;       // prescribed normal inlet speed
   std::vector<char> layer;        // objective layer (first layer on a heated wall)
   int n_inlet = 0, n_layer = 0, n_nonwall = 0;
@@ -151,7 +159,9 @@ struct Problem {
     z = ((z + s * e[2]) % nz + nz) % nz;
     return idx(x, y, z);
   }
-  bool is_wall(int n) const { return kind[n] == K_WALL || kind[n] == K_HEATED; }
+  // nodes that do not collide and are not part of the fluid: walls, heated
+  // walls and the layers beyond a symmetry plane (never read)
+  bool is_wall(int n) const { return kind[n] == K_WALL || kind[n] == K_HEATED || kind[n] == K_SYM; }
   bool collides(int n) const { return !is_wall(n); }
   bool is_design(int n) const { return kind[n] == K_DESIGN; }
   // index of the lattice direction equal to the node's inward normal
@@ -213,6 +223,16 @@ S tau_g_d(const Problem& P, int n, const S& g) {
   return P.Df * khat_d(P, g) / P.G.cs2;
 }
 
+// Volumetric heat generation of the paper's heat sink (Eqs. 68, 69, 71):
+// Q = beta(gamma) (1 - T) with beta(gamma) = beta_max (1 - gamma) on design
+// nodes (gamma = 1 fluid, 0 solid: heat is generated in the solid), 0 elsewhere.
+template <class S>
+S beta_of(const Problem& P, int n, const S& g) {
+  if (!P.is_design(n) || P.c.beta_max <= 0.0) return S(0.0);
+  return P.c.beta_max * (1.0 - g);
+}
+double beta_d(const Problem& P, int n) { return (P.is_design(n) && P.c.beta_max > 0.0) ? -P.c.beta_max : 0.0; }
+
 // Macroscopic moments of Eq. (6) at one node.
 template <class S>
 void moments(const Problem& P, const S* f, S& rho, S u[3]) {
@@ -254,37 +274,64 @@ void collide(const Problem& P, const S* gamma, S* f, S* g) {
       S T = 0.0;
       for (int i = 0; i < Qg; ++i) T += gn[i];
       const S tg = tau_g(P, n, gamma[n]);
+      const S Qh = beta_of(P, n, gamma[n]) * (1.0 - T);  // heat source of Eq. (71)
       for (int i = 0; i < Qg; ++i) {
         const S eu = double(P.G.e[i][0]) * u[0] + double(P.G.e[i][1]) * u[1] + double(P.G.e[i][2]) * u[2];
         const S geq = P.G.w[i] * T * (1.0 + eu / P.G.cs2);
-        gn[i] = gn[i] - (gn[i] - geq) / tg;
+        gn[i] = gn[i] - (gn[i] - geq) / tg + P.G.w[i] * Qh;
       }
     }
   }
 }
 
-// Source node of the thermal streaming for slot (i, n).  Streaming pulls from
-// n - e_i (periodic); the one exception is the thermal outflow: at an OUTLET
-// node the population along the inward normal would come from outside, and
-// takes the node's own post-collision value instead (zero-gradient outflow,
-// a reading: the paper's Ref. [14] is not given).
-int thermal_source(const Problem& P, int i, int n) {
-  if (P.kind[n] == K_OUTLET && i == P.normal_dir(P.G, n)) return n;
-  return P.shift(n, P.G.e[i], -1);
+// Source slot of streaming for slot (n, i) of lattice L.  Streaming pulls
+// from n - e_i (periodic wrap, so S is a permutation as in Sec. 2.4 (2)).  A
+// source on the layer beyond a symmetry plane is replaced by its mirror image:
+// the node one layer back, with the direction's normal component reversed
+// (specular reflection at a plane midway between the two layers; the paper's
+// quarter-domain heat sink, Sec. 3.3).  To keep S a permutation, the nodes of
+// that layer keep their own slots and a source that would wrap around the
+// other end of a symmetric axis reverses direction at the node itself; both
+// only ever touch slots that no fluid node reads.  The thermal outflow is the
+// other exception: at an OUTLET node the population along the inward normal
+// would come from outside and takes the node's own post-collision value
+// instead (zero-gradient outflow, a reading: the paper's Ref. [14] is not
+// given).
+int64_t stream_source(const Problem& P, const Lattice& L, bool thermal, int n, int i) {
+  if (P.kind[n] == K_SYM) return (int64_t)n * L.Q + i;
+  if (thermal && P.kind[n] == K_OUTLET && i == P.normal_dir(L, n)) return (int64_t)n * L.Q + i;
+  const int lim[3] = {P.nx, P.ny, P.nz};
+  int x[3], e[3] = {L.e[i][0], L.e[i][1], L.e[i][2]};
+  P.coords(n, x[0], x[1], x[2]);
+  int c[3];
+  for (int a = 0; a < 3; ++a) {
+    c[a] = x[a] - e[a];
+    if (P.c.symmetric[a] && c[a] == lim[a] - 1) {
+      c[a] = lim[a] - 2;
+      e[a] = -e[a];
+    } else if (P.c.symmetric[a] && c[a] < 0) {
+      c[a] = x[a];
+      e[a] = -e[a];
+    }
+    c[a] = (c[a] % lim[a] + lim[a]) % lim[a];
+  }
+  int d = -1;
+  for (int j = 0; j < L.Q; ++j)
+    if (L.e[j][0] == e[0] && L.e[j][1] == e[1] && L.e[j][2] == e[2]) d = j;
+  return (int64_t)P.idx(c[0], c[1], c[2]) * L.Q + d;
 }
 
 // ---------------------------------------------------------------------------
-// Streaming, Eq. (37): f_S,i(x) = f_C,i(x - e_i), periodic, so S is a
-// permutation (thermal: with the outflow exception above).
+// Streaming, Eq. (37), as the gather S: f_S(slot) = f_C(src(slot)).
 // ---------------------------------------------------------------------------
 template <class S>
 void stream(const Problem& P, const S* fC, const S* gC, S* fS, S* gS) {
   const int Q = P.F.Q, Qg = P.G.Q;
 #pragma omp parallel for schedule(static)
   for (int n = 0; n < P.N; ++n) {
-    for (int i = 0; i < Q; ++i) fS[(size_t)n * Q + i] = fC[(size_t)P.shift(n, P.F.e[i], -1) * Q + i];
+    for (int i = 0; i < Q; ++i) fS[(size_t)n * Q + i] = fC[P.srcF[(size_t)n * Q + i]];
     if (P.thermal)
-      for (int i = 0; i < Qg; ++i) gS[(size_t)n * Qg + i] = gC[(size_t)thermal_source(P, i, n) * Qg + i];
+      for (int i = 0; i < Qg; ++i) gS[(size_t)n * Qg + i] = gC[P.srcG[(size_t)n * Qg + i]];
   }
 }
 
@@ -310,7 +357,9 @@ int tangential_axes(const Problem& P, const int* nv, int* t) {
 //                  N_t = sum over tangential j of (e_j.t) f_j.
 // Velocity inlet: u_n is the prescribed normal speed (tangential speed 0, as in
 // Eq. 7).  Pressure outlet (rho = rho0, Eq. 8):
-//                  rho0 u_n = rho0 - sum_tangential f - 2 sum_outgoing f.
+//                  rho0 u_n = rho0 - sum_tangential f - 2 sum_outgoing f,
+// and a pressure inlet (the paper's heat sink is driven by a fixed inlet
+// pressure, Sec. 3.3) by the same rule with rho_in in place of rho0.
 // For D2Q9 at the left inlet and the bottom outlet this is Eq. (7) and Eq. (8)
 // term by term.
 // ---------------------------------------------------------------------------
@@ -332,10 +381,10 @@ void zou_he(const Problem& P, int n, S* f) {
     }
   }
   S jn;  // rho0 * u_n
-  if (P.kind[n] == K_INLET)
+  if (P.kind[n] == K_INLET && P.c.inlet_rho <= 0.0)
     jn = P.c.rho0 * P.u_in[n];
-  else
-    jn = P.c.rho0 - sumT0 - 2.0 * sumO;
+  else  // pressure outlet (rho0), or pressure inlet (inlet_rho) by the same rule
+    jn = (P.kind[n] == K_INLET ? P.c.inlet_rho : P.c.rho0) - sumT0 - 2.0 * sumO;
   for (int i = 0; i < L.Q; ++i) {
     if (dir_class(L, i, nv) != 1) continue;
     S v = f[L.opp[i]] + 6.0 * L.w[i] * jn;
@@ -492,6 +541,15 @@ S objective(const Problem& P, const S* gamma, const S* f, const S* g) {
     }
     J += s / double(P.n_layer);
   }
+  if (obj == OBJ_HEATGEN) {
+    // J = - sum_j Q(x_j) = - sum_j beta(gamma_j) (1 - T_j)   (Eq. 72)
+    for (int n = 0; n < P.N; ++n) {
+      if (!P.is_design(n)) continue;
+      S T = 0.0;
+      for (int i = 0; i < P.G.Q; ++i) T += g[(size_t)n * P.G.Q + i];
+      J -= beta_of(P, n, gamma[n]) * (1.0 - T);
+    }
+  }
   if (obj == OBJ_DISSIPATION) {
     std::vector<S> u((size_t)P.N * 3);
     for (int n = 0; n < P.N; ++n) {
@@ -542,6 +600,17 @@ void objective_grad(const Problem& P, const double* gamma, const double* f, cons
       if (P.layer[n])
         for (int i = 0; i < Qg; ++i) jg[(size_t)n * Qg + i] += c;
   }
+  if (obj == OBJ_HEATGEN) {
+    // dJ/dg_i = beta(gamma) (T = sum g), explicit dJ/dgamma = -beta'(gamma) (1 - T)
+    for (int n = 0; n < P.N; ++n) {
+      if (!P.is_design(n)) continue;
+      double T = 0.0;
+      for (int i = 0; i < Qg; ++i) T += g[(size_t)n * Qg + i];
+      const double b = beta_of(P, n, gamma[n]);
+      for (int i = 0; i < Qg; ++i) jg[(size_t)n * Qg + i] += b;
+      jgam[n] += -beta_d(P, n) * (1.0 - T);
+    }
+  }
   if (obj == OBJ_DISSIPATION) {
     std::vector<double> u((size_t)P.N * 3), dJdu((size_t)P.N * 3, 0.0);
     for (int n = 0; n < P.N; ++n) {
@@ -588,9 +657,10 @@ void objective_grad(const Problem& P, const double* gamma, const double* f, cons
 // out from the Zou-He rule above: identity rows for the known populations, and
 // for unknown i
 //   B_ij = [j == ibar] - 1/2 [j tangential] sum_t (e_i.t)(e_j.t) - 6 w_i c_j,
-// with c_j = 0 at an inlet, and at an outlet c_j = 1 for tangential j and 2 for
-// outgoing j (from rho0 u_n = rho0 - sum_T f - 2 sum_O f).  For the D2Q9 inlet
-// this is the matrix printed as Eq. (58).
+// with c_j = 0 at a velocity inlet, and at an outlet or a pressure inlet
+// c_j = 1 for tangential j and 2 for outgoing j (from rho0 u_n = rho_b -
+// sum_T f - 2 sum_O f).  For the D2Q9 inlet this is the matrix printed as
+// Eq. (58).
 // ---------------------------------------------------------------------------
 void bc_matrix(const Problem& P, int n, double* B) {
   const Lattice& L = P.F;
@@ -618,7 +688,7 @@ void bc_matrix(const Problem& P, int n, double* B) {
       double v = (j == L.opp[i]) ? 1.0 : 0.0;
       if (cj == 0)
         for (int kk = 0; kk < nt; ++kk) v -= 0.5 * L.e[i][t[kk]] * L.e[j][t[kk]];
-      if (k == K_OUTLET) v -= 6.0 * L.w[i] * (cj == 0 ? 1.0 : (cj < 0 ? 2.0 : 0.0));
+      if (k == K_OUTLET || P.c.inlet_rho > 0.0) v -= 6.0 * L.w[i] * (cj == 0 ? 1.0 : (cj < 0 ? 2.0 : 0.0));
       B[i * Q + j] = v;
     }
   }
@@ -665,34 +735,26 @@ void adjoint_bc(const Problem& P, const double* fsC, const double* gsC, double* 
   }
 }
 
-// Adjoint streaming, Eqs. (55) and (61): f*_S,i(x) = f*_i(x + e_i), the reverse
-// of the periodic permutation.  The thermal streaming is not a permutation at
-// the outflow, so its transpose is written as a gather over the slots each
-// source feeds.
+// Adjoint streaming, Eqs. (55) and (61): the transpose of the gather S,
+// f*_S(src) = sum over the slots d with src(d) = src of f*(d).  Without
+// symmetry planes and outflow this is f*_S,i(x) = f*_i(x + e_i), the reverse
+// of the periodic permutation; the thermal outflow copy and the mirror
+// images make some sources feed two slots or none.
 void adjoint_stream(const Problem& P, const double* fs, const double* gs, double* fsS, double* gsS) {
-  const int Q = P.F.Q, Qg = P.G.Q;
-#pragma omp parallel for schedule(static)
-  for (int n = 0; n < P.N; ++n) {
-    for (int i = 0; i < Q; ++i) fsS[(size_t)n * Q + i] = fs[(size_t)P.shift(n, P.F.e[i], +1) * Q + i];
-    if (!P.thermal) continue;
-    for (int i = 0; i < Qg; ++i) {
-      // destinations y whose slot i is fed from slot i of node n
-      const int cand[2] = {P.shift(n, P.G.e[i], +1), n};
-      double s = 0.0;
-      for (int c = 0; c < 2; ++c) {
-        if (c == 1 && cand[1] == cand[0]) break;
-        if (thermal_source(P, i, cand[c]) == n) s += gs[(size_t)cand[c] * Qg + i];
-      }
-      gsS[(size_t)n * Qg + i] = s;
-    }
-  }
+  const size_t MF = (size_t)P.N * P.F.Q, MG = (size_t)P.N * P.G.Q;
+  std::fill(fsS, fsS + MF, 0.0);
+  for (size_t d = 0; d < MF; ++d) fsS[P.srcF[d]] += fs[d];
+  if (!P.thermal) return;
+  std::fill(gsS, gsS + MG, 0.0);
+  for (size_t d = 0; d < MG; ++d) gsS[P.srcG[d]] += gs[d];
 }
 
 // ---------------------------------------------------------------------------
 // Adjoint collision, Eqs. (56), (63)-(65):
 //   f*_C,i = f*_S,i - (1/tau)[f*_S,i - sum_m (d feq_m / d f_i) f*_S,m]
 //            + sum_m (d C^g_m / d f_i) g*_S,m - dJ/df_i
-//   g*_C,i = g*_S,i - (1/tau_g)[g*_S,i - sum_m (d geq_m / d g_i) g*_S,m] - dJ/dg_i
+//   g*_C,i = g*_S,i - (1/tau_g)[g*_S,i - sum_m (d geq_m / d g_i) g*_S,m]
+//            - beta(gamma) sum_m w^g_m g*_S,m - dJ/dg_i
 // with, from Eq. (12) and rho = sum f, rho0 u = sum e f (Eq. 6),
 //   d feq_m / d f_i = w_m [1 + 3 chi e_m.e_i + 9 chi^2 (e_m.u)(e_m.e_i) - 3 chi^2 u.e_i],
 //   d C^g_m / d f_i = (1/tau_g) w^g_m T (e^g_m.e_i) / (cs2 rho0),
@@ -743,13 +805,17 @@ void adjoint_collide(const Problem& P, const double* gamma, const double* f, con
       fsC[(size_t)n * Q + i] = v - jf[(size_t)n * Q + i];
     }
     if (P.thermal) {
+      // heat source w_m beta (1 - T) of Eq. (71): d/dg_i = -w_m beta
+      const double bq = beta_of(P, n, gamma[n]);
+      double wb = 0.0;
+      for (int m = 0; m < Qg; ++m) wb += G.w[m] * b[m];
       for (int i = 0; i < Qg; ++i) {
         double s = 0.0;
         for (int m = 0; m < Qg; ++m) {
           const double emu = G.e[m][0] * u[0] + G.e[m][1] * u[1] + G.e[m][2] * u[2];
           s += G.w[m] * (1.0 + emu / G.cs2) * b[m];
         }
-        gsC[(size_t)n * Qg + i] = b[i] - (b[i] - s) / tg - jg[(size_t)n * Qg + i];
+        gsC[(size_t)n * Qg + i] = b[i] - (b[i] - s) / tg - bq * wb - jg[(size_t)n * Qg + i];
       }
     }
   }
@@ -945,7 +1011,7 @@ int cont_adjoint(const Problem& P, const double* gamma, const double* f, double*
 // derivative of the collision with respect to the design variable:
 //   sum_i f*_S,i dC_i/dgamma + sum_i g*_S,i dC^g_i/dgamma, where
 //   dC_i/dgamma   = (1/tau) w_i rho0 [3 e_i.u + 9 chi (e_i.u)^2 - 3 chi |u|^2] chi'(gamma)
-//   dC^g_i/dgamma = (g_i - geq_i) tau_g'(gamma) / tau_g^2
+//   dC^g_i/dgamma = (g_i - geq_i) tau_g'(gamma) / tau_g^2 + w^g_i beta'(gamma) (1 - T)
 // (the bracket printed in Eq. (66) is the secant feq(u) - feq(0); the exact
 // derivative is used so that the result is the gradient of the discrete J).
 // Non-design nodes give 0.
@@ -973,10 +1039,11 @@ void sens_contract(const Problem& P, const double* gamma, const double* f, const
       for (int i = 0; i < Qg; ++i) T += g[(size_t)n * Qg + i];
       const double tg = tau_g(P, n, gamma[n]);
       const double dtg = tau_g_d(P, n, gamma[n]);
+      const double db = beta_d(P, n);
       for (int i = 0; i < Qg; ++i) {
         const double eu = P.G.e[i][0] * u[0] + P.G.e[i][1] * u[1] + P.G.e[i][2] * u[2];
         const double geq = P.G.w[i] * T * (1.0 + eu / P.G.cs2);
-        const double dC = (g[(size_t)n * Qg + i] - geq) * dtg / (tg * tg);
+        const double dC = (g[(size_t)n * Qg + i] - geq) * dtg / (tg * tg) + P.G.w[i] * db * (1.0 - T);
         s += gsS[(size_t)n * Qg + i] * dC;
       }
     }
@@ -1020,7 +1087,7 @@ bool build_problem(const OrcConfig& c, const uint8_t* mask, Problem& P, std::str
   P.layer.assign(P.N, 0);
   for (int n = 0; n < P.N; ++n) {
     const int k = mask[n] & 7, nc = (mask[n] >> 3) & 7;
-    if (k > K_HEATED || (mask[n] >> 6) != 0) {
+    if (k > K_SYM || (mask[n] >> 6) != 0) {
       err = "bad mask byte";
       return false;
     }
@@ -1031,8 +1098,42 @@ bool build_problem(const OrcConfig& c, const uint8_t* mask, Problem& P, std::str
       return false;
     }
   }
-  // inlet profile, per normal code
+  // symmetry planes: layer n_a - 1 of a symmetric axis holds SYM nodes only,
+  // and SYM nodes appear nowhere else
   const int lim[3] = {P.nx, P.ny, P.nz};
+  for (int a = 0; a < 3; ++a) {
+    if (c.symmetric[a] != 0 && c.symmetric[a] != 1) {
+      err = "symmetric must be 0 or 1";
+      return false;
+    }
+    if (c.symmetric[a] && (lim[a] < 4 || (c.dim == 2 && a == 2))) {
+      err = "a symmetric axis needs at least 4 layers";
+      return false;
+    }
+  }
+  for (int n = 0; n < P.N; ++n) {
+    int x[3];
+    P.coords(n, x[0], x[1], x[2]);
+    bool on = false;
+    for (int a = 0; a < 3; ++a) on = on || (c.symmetric[a] && x[a] == lim[a] - 1);
+    if (on != (P.kind[n] == K_SYM)) {
+      err = "SYM nodes must fill exactly the last layer of each symmetric axis";
+      return false;
+    }
+  }
+  if (c.beta_max < 0.0 || (c.beta_max > 0.0 && !c.thermal)) {
+    err = "beta_max must be >= 0 and needs the thermal lattice";
+    return false;
+  }
+  if (c.objective == OBJ_HEATGEN && (!c.thermal || c.beta_max <= 0.0)) {
+    err = "heat-generation objective needs the thermal lattice and beta_max > 0";
+    return false;
+  }
+  if (c.inlet_rho < 0.0) {
+    err = "inlet_rho must be >= 0";
+    return false;
+  }
+  // inlet profile, per normal code
   for (int code = 0; code < 6; ++code) {
     int lo[3] = {1 << 30, 1 << 30, 1 << 30}, hi[3] = {-1, -1, -1};
     bool any = false;
@@ -1056,7 +1157,9 @@ bool build_problem(const OrcConfig& c, const uint8_t* mask, Problem& P, std::str
       for (int a = 0; a < c.dim; ++a) {
         if (nv[a] != 0) continue;
         if (lo[a] == 0 && hi[a] == lim[a] - 1) continue;
-        const double s = (x[a] - lo[a] + 0.5) / double(hi[a] - lo[a] + 1);
+        // an inlet set reaching a symmetry plane continues in its mirror image
+        const int h = (c.symmetric[a] && hi[a] == lim[a] - 2) ? 2 * lim[a] - 3 - lo[a] : hi[a];
+        const double s = (x[a] - lo[a] + 0.5) / double(h - lo[a] + 1);
         prof *= 4.0 * s * (1.0 - s);
       }
       P.u_in[n] = P.U_peak * prof;
@@ -1082,6 +1185,15 @@ bool build_problem(const OrcConfig& c, const uint8_t* mask, Problem& P, std::str
     }
   }
   for (int n = 0; n < P.N; ++n) P.n_layer += P.layer[n];
+  // streaming gather maps
+  P.srcF.resize((size_t)P.N * P.F.Q);
+  for (int n = 0; n < P.N; ++n)
+    for (int i = 0; i < P.F.Q; ++i) P.srcF[(size_t)n * P.F.Q + i] = stream_source(P, P.F, false, n, i);
+  if (P.thermal) {
+    P.srcG.resize((size_t)P.N * P.G.Q);
+    for (int n = 0; n < P.N; ++n)
+      for (int i = 0; i < P.G.Q; ++i) P.srcG[(size_t)n * P.G.Q + i] = stream_source(P, P.G, true, n, i);
+  }
   if ((c.objective == OBJ_PRESSURE_DROP || c.objective == OBJ_HEATSINK) && c.w_dp != 0.0 && P.n_inlet == 0) {
     err = "pressure-drop term needs inlet nodes";
     return false;

@@ -23,10 +23,10 @@ from typing import Optional
 import numpy as np
 from scipy import ndimage
 
-DESIGN, FLUID, INLET, OUTLET, WALL, HEATED = 0, 1, 2, 3, 4, 5
+DESIGN, FLUID, INLET, OUTLET, WALL, HEATED, SYM = 0, 1, 2, 3, 4, 5, 6
 NPX, NMX, NPY, NMY, NPZ, NMZ = 0, 1, 2, 3, 4, 5
 
-OBJ_PRESSURE_DROP, OBJ_DISSIPATION, OBJ_HEATSINK = 0, 1, 2
+OBJ_PRESSURE_DROP, OBJ_DISSIPATION, OBJ_HEATSINK, OBJ_HEATGEN = 0, 1, 2, 3
 OBJECTIVE_NAMES = {OBJ_PRESSURE_DROP: "pressure_drop", OBJ_DISSIPATION: "dissipation",
                    OBJ_HEATSINK: "heatsink"}
 
@@ -68,6 +68,9 @@ class Workload:
     check_every: int = 1000
     seed: int = 0
     adjoint_kind: int = 0                 # 0 discrete (Sec. 2.4), 1 continuous (Sec. 2.3)
+    symmetric: tuple = (False, False, False)  # mirror plane before the last layer of an axis
+    inlet_rho: float = 0.0                # > 0: pressure inlets at this density
+    beta_max: float = 0.0                 # volumetric heat generation coefficient
 
     @property
     def N(self) -> int:
@@ -199,6 +202,72 @@ def differentiable_case(seed: Optional[int] = None) -> Workload:
     seed = SEED_BASE + 3 if seed is None else seed
     return heat_sink(128, 64, 32, Re=200.0, u_peak=0.15, seed=seed, buffer=6,
                      name="heat_sink_128x64x32_Re200")
+
+
+def paper_heat_sink(nx: int = 128, ny: int = 33, nz: int = 25, Re: float = 60.0,
+                    tau: float = 0.6, Pr: float = 7.1, beta_max: float = 1e-5,
+                    k_ratio: float = 100.0, alpha_max: float = 0.1, buffer: int = 4,
+                    sigma: float = 3.0, seed: Optional[int] = None,
+                    name: Optional[str] = None) -> Workload:
+    """The paper's own 3D microchannel heat sink (Sec. 3.3, Eqs. 68-72) on a
+    quarter of the domain: mirror planes before the last y and z layers (SYM
+    nodes), no-slip adiabatic walls at y = 0 and z = 0, a pressure inlet over
+    face x = 0 and a pressure outlet over face x = nx-1 (their interiors),
+    `buffer` fluid layers after the inlet and before the outlet, the design
+    domain between them.  Heat is generated in the solid, Q = beta(gamma)
+    (1 - T) with beta = beta_max (1 - gamma) (Eq. 69); the inlet fluid is at
+    T = 0; objective J = -sum Q (Eq. 72).  Re follows Eq. (70): the velocity
+    scale sqrt(dp / rho0) of the pressure drop, length L = the full channel
+    height between the walls, 2 (nz - 2) + 1 nodes; at the given tau the inlet
+    density is rho0 + 3 dp with dp = rho0 (Re nu / L)^2."""
+    seed = SEED_BASE + 7 if seed is None else seed
+    m = np.full((nz, ny, nx), DESIGN, dtype=np.uint8)
+    m[0, :, :] = WALL
+    m[:, 0, :] = WALL
+    m[:, :, 0] = WALL
+    m[:, :, nx - 1] = WALL
+    m[1:nz - 1, 1:ny - 1, 0] = code(INLET, NPX)
+    m[1:nz - 1, 1:ny - 1, nx - 1] = code(OUTLET, NMX)
+    if buffer > 0:
+        m[1:nz - 1, 1:ny - 1, 1:1 + buffer] = FLUID
+        m[1:nz - 1, 1:ny - 1, nx - 1 - buffer:nx - 1] = FLUID
+    m[nz - 1, :, :] = SYM
+    m[:, ny - 1, :] = SYM
+    L = float(2 * (nz - 2) + 1)
+    nu = (tau - 0.5) / 3.0
+    dp = (Re * nu / L) ** 2
+    gamma = smoothed_noise((nz, ny, nx), sigma, seed)
+    return Workload(name=name or f"paper_heat_sink_{nx}x{ny}x{nz}_Re{Re:g}", dim=3, nx=nx, ny=ny,
+                    nz=nz, thermal=True, tau=tau, Re=Re, L_ref=L, objective=OBJ_HEATGEN, mask=m,
+                    gamma=gamma, alpha_max=alpha_max, q_brink=0.1, Pr=Pr, k_ratio=k_ratio,
+                    q_ramp=1.0, q_w=0.0, T_in=0.0, w_dp=0.0, seed=seed,
+                    symmetric=(False, True, True), inlet_rho=1.0 + 3.0 * dp, beta_max=beta_max)
+
+
+def mirror_full(w: Workload) -> Workload:
+    """The full-domain problem whose quarter (or half) is w: every symmetric
+    axis is unfolded about its mirror plane (the SYM layer dropped, the rest
+    reflected), mask and design field alike."""
+    m, g = w.mask, w.gamma
+    for a, ax in ((0, 2), (1, 1), (2, 0)):   # x, y, z -> array axes 2, 1, 0
+        if not w.symmetric[a]:
+            continue
+        sl = [slice(None)] * 3
+        sl[ax] = slice(0, m.shape[ax] - 1)
+        m, g = m[tuple(sl)], g[tuple(sl)]
+        m = np.concatenate([m, np.flip(m, axis=ax)], axis=ax)
+        g = np.concatenate([g, np.flip(g, axis=ax)], axis=ax)
+    nz, ny, nx = m.shape
+    return w.replace(mask=np.ascontiguousarray(m), gamma=np.ascontiguousarray(g), nx=nx, ny=ny,
+                     nz=nz, symmetric=(False, False, False), name=w.name + "_full")
+
+
+def tiny_paper_heat_sink(nx: int = 12, ny: int = 6, nz: int = 5, Re: float = 10.0,
+                         tau: float = 0.8, beta_max: float = 2e-3, seed: int = 9) -> Workload:
+    """A small quarter-domain heat sink of the paper's formulation, for pins."""
+    return paper_heat_sink(nx, ny, nz, Re=Re, tau=tau, Pr=1.0, beta_max=beta_max,
+                           alpha_max=0.2, buffer=1, sigma=1.0, seed=seed,
+                           name=f"tiny_paper_heat_sink_{nx}x{ny}x{nz}")
 
 
 SERVING_GRIDS = ((64, 32, 16), (128, 64, 32), (192, 96, 48))

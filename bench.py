@@ -61,7 +61,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="heat_sink_Re200",
                     choices=["heat_sink_Re50", "heat_sink_Re200", "heat_sink_Re400",
-                             "heat_sink_320x160x80_Re200", "pipe_bend_96", "pipe_bend_96_dp"])
+                             "heat_sink_320x160x80_Re200", "pipe_bend_96", "pipe_bend_96_dp",
+                             "paper_heat_sink_Re60", "paper_heat_sink_Re120",
+                             "paper_heat_sink_Re240"])
     ap.add_argument("--re", type=float, default=0.0,
                     help="Reynolds number of a pipe-bend workload (0: the workload's own)")
     ap.add_argument("--adjoint", default="discrete", choices=["discrete", "continuous"],
@@ -93,6 +95,14 @@ def parse():
                          "adjoint) and print its JSON object")
     ap.add_argument("--stability-steps", type=int, default=1000000,
                     help="step cap of each forward and adjoint solve in the stability sweep")
+    ap.add_argument("--optimize", type=int, default=0,
+                    help="run this many level-set optimisation iterations on --workload "
+                         "(Sec. 2.2) and print their JSON object")
+    ap.add_argument("--opt-k", type=float, default=0.1, help="level-set step size K (Eq. 14)")
+    ap.add_argument("--opt-sigma", type=float, default=5e-3,
+                    help="level-set regularisation coefficient sigma (Eq. 14)")
+    ap.add_argument("--opt-vmax", type=float, default=0.5,
+                    help="upper limit of the design domain's fluid fraction (Eq. 10)")
     ap.add_argument("--serving-only", action="store_true",
                     help="run only the serving leg and print its JSON object")
     return ap.parse_args()
@@ -173,6 +183,8 @@ def make_workload(name, adjoint="discrete", Re=0.0):
         w = W.pipe_bend_3d(objective=obj, **({"Re": Re} if Re > 0 else {}))
         return w.replace(adjoint_kind=kind, name=w.name + ("_dp" if name.endswith("_dp") else "")
                          + (f"_Re{Re:g}" if Re > 0 else "") + ("_continuous" if kind else ""))
+    if name.startswith("paper_heat_sink"):
+        return W.paper_heat_sink(Re=float(name.split("Re")[1]))
     if name == "heat_sink_320x160x80_Re200":
         return W.heat_sink(320, 160, 80, Re=200.0, name="heat_sink_320x160x80_Re200")
     Re = float(name.split("Re")[1])
@@ -272,6 +284,28 @@ def stability_leg(steps):
             "seconds": round(el, 1), "points": pts}
 
 
+def optimize_leg(args):
+    """Level-set topology optimisation (Sec. 2.2) on --workload from the
+    empty chamber: per iteration a warm-started forward solve, adjoint solve,
+    sensitivity and level-set update, all on the GPU."""
+    import torch
+    from paper_2501_02161_amd import optimize
+
+    torch.cuda.set_device(0)
+    w = make_workload(args.workload, args.adjoint, args.re)
+    opt = optimize.LevelSetOptimizer(w, K=args.opt_k, sigma=args.opt_sigma, vmax=args.opt_vmax)
+    t0 = time.perf_counter()
+    hist = opt.run(args.optimize, log=lambda r: print(f"[optimize] {json.dumps(r)}",
+                                                      file=sys.stderr, flush=True))
+    el = time.perf_counter() - t0
+    return {"workload": w.name, "lattice": [w.nx, w.ny, w.nz], "K": args.opt_k,
+            "sigma": args.opt_sigma, "vmax": args.opt_vmax, "iterations": len(hist),
+            "seconds": round(el, 3), "seconds_per_iteration": round(el / max(1, len(hist)), 4),
+            "node_updates_per_s": opt.updates / el,
+            "J": [h["J"] for h in hist], "volume": [h["volume"] for h in hist],
+            "fwd_steps": [h["fwd_steps"] for h in hist], "adj_steps": [h["adj_steps"] for h in hist]}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -287,6 +321,9 @@ def main():
         return
     if args.stability:
         print(json.dumps({"stability": stability_leg(args.stability_steps)}), flush=True)
+        return
+    if args.optimize > 0:
+        print(json.dumps({"optimize": optimize_leg(args)}), flush=True)
         return
     if args.serving_only:
         print(json.dumps({"serving": serving_leg(args.serving_requests or 256,
@@ -355,7 +392,8 @@ def main():
         "config": {"workload": w.name, "nodes": w.N,
                    "lattice": "D3Q19+D3Q7" if w.thermal else "D3Q19",
                    "objective": {0: "pressure drop", 1: "viscous dissipation",
-                                 2: "mean floor-layer T + 0.1 pressure drop"}[w.objective],
+                                 2: "mean floor-layer T + 0.1 pressure drop",
+                                 3: "heat generated, -sum beta (1 - T)"}[w.objective],
                    "adjoint": "continuous" if w.adjoint_kind else "discrete",
                    "tau": round(w.tau, 6),
                    "tol": w.tol, "max_steps": w.max_steps, "fwd_steps": fi["steps"],

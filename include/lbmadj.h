@@ -76,22 +76,28 @@ extern "C" {
  *   DESIGN  interior node whose chi and k follow gamma
  *   FLUID   interior node with chi = 1, k = 1 (not designable)
  *   INLET   Zou-He velocity inlet (Eq. 7 generalised to any axis normal and
- *           to D3Q19); thermal Dirichlet T = T_in
+ *           to D3Q19), or a pressure inlet at desc.inlet_rho (the outlet
+ *           rule at that density); thermal Dirichlet T = T_in
  *   OUTLET  Zou-He pressure outlet rho = rho0 (Eq. 8 generalised); thermal
  *           zero-gradient outflow
  *   WALL    full-way bounce-back (Eq. 9): every pair is swapped, no
  *           collision; adiabatic for the thermal lattice
  *   HEATED  a WALL that adds the heat flux q_w per step to the thermal
  *           population along its inward normal
+ *   SYM     the layer beyond a mirror plane (desc.symmetric): never read;
+ *           a pull that would reach it reads the mirror image instead (the
+ *           node's own layer along that axis, the direction reflected in it)
  * On every non-periodic axis the two outer layers must be WALL, HEATED,
- * INLET or OUTLET nodes; a port's normal must be the inward normal of its
- * face and ports may not sit on an edge of two non-periodic faces. */
+ * INLET, OUTLET or SYM nodes; SYM nodes fill exactly the last layer of each
+ * symmetric axis; a port's normal must be the inward normal of its face and
+ * ports may not sit on an edge of two non-periodic faces. */
 #define LBM_NODE_DESIGN 0
 #define LBM_NODE_FLUID 1
 #define LBM_NODE_INLET 2
 #define LBM_NODE_OUTLET 3
 #define LBM_NODE_WALL 4
 #define LBM_NODE_HEATED 5
+#define LBM_NODE_SYM 6
 #define LBM_NORMAL_PX 0
 #define LBM_NORMAL_MX 1
 #define LBM_NORMAL_PY 2
@@ -111,6 +117,10 @@ extern "C" {
 #define LBM_OBJ_PRESSURE_DROP 0
 #define LBM_OBJ_DISSIPATION 1
 #define LBM_OBJ_HEATSINK 2
+/*   HEATGEN        J = - sum over design nodes of beta(gamma) (1 - T), the
+ *                  heat generated in the solid (Eq. 72 with Eqs. 69, 71);
+ *                  needs the thermal lattice and beta_max > 0. */
+#define LBM_OBJ_HEATGEN 3
 
 /* Adjoint kinds (lbm_desc_t.adjoint_kind).
  *   DISCRETE    the fully consistent discrete adjoint of Sec. 2.4 (Eqs. 53-65).
@@ -146,7 +156,12 @@ typedef struct lbm_desc {
   int32_t check_every;     /* steps between residual checks (0: never)        */
   double tol;              /* residual tolerance (0: run max_steps)           */
   int32_t adjoint_kind;    /* LBM_ADJOINT_DISCRETE or LBM_ADJOINT_CONTINUOUS  */
-  int32_t reserved;        /* 0                                               */
+  int32_t symmetric[3];    /* 1: mirror plane between layers n-2 and n-1 of  */
+                           /* the axis; layer n-1 holds LBM_NODE_SYM nodes    */
+  double inlet_rho;        /* > 0: every inlet is a pressure inlet at this    */
+                           /* density (Re, L_ref then unused); 0: velocity    */
+  double beta_max;         /* heat generation beta(gamma) (1 - T) per step,   */
+                           /* beta = beta_max (1 - gamma) on design nodes     */
 } lbm_desc_t;
 
 /* Result of a solve.  Residuals follow Sec. 3.1: |I(t) - I(t - c)| / |I(t)|
@@ -215,6 +230,39 @@ int lbm_adjoint_solve(lbm_problem_t* p, const float* gamma, const float* drho, c
  * lattice. */
 int lbm_thermal_resolve(lbm_problem_t* p, const float* gamma, const float* u, const float* T,
                         lbm_info_t* info, void* stream);
+
+/* Warm restarts for an optimisation loop: continue the forward (adjoint)
+ * solve from its current state, with a possibly changed gamma, under the
+ * descriptor's residual criterion (max_steps, tol, check_every), writing the
+ * same outputs as lbm_forward_solve (lbm_adjoint_solve).  LBM_ESTATE without
+ * a previous solve of that kind (and, with the thermal lattice, for the
+ * adjoint without the thermal state of a forward solve). */
+int lbm_forward_resume(lbm_problem_t* p, const float* gamma, float* drho, float* u, float* T,
+                       lbm_info_t* info, void* stream);
+int lbm_adjoint_resume(lbm_problem_t* p, const float* gamma, const float* drho, const float* u,
+                       const float* T, lbm_info_t* info, void* stream);
+
+/* Level-set design update of the topology-optimisation loop (Sec. 2.2,
+ * Eqs. 13-15 and 67), on the design nodes of the problem:
+ *   r      = J' / s + lambda - sigma lap(phi),  s = mean |J'| (design nodes)
+ *   lambda = exp(G) mean |J'/s - sigma lap(phi)|,  G = V - vmax   (Eq. 67)
+ *   phi'   = clamp(phi - K r, -1, 1)   (explicit step of Eq. 14)
+ *   gamma  = 1 where phi' >= 0, else 0 (Eq. 15)
+ * V is the fluid fraction (phi >= 0) of the design domain before the step;
+ * lap is the 7-point Laplacian with no flux to non-design nodes.  phi,
+ * phi_out, dJ (the sensitivity J'), gamma: device [N] float; phi_out must
+ * not alias phi; non-design entries of phi_out copy phi, of gamma are left
+ * unchanged.  Synchronises the stream (two small reductions).  LBM_EINVAL
+ * for K <= 0, sigma < 0, vmax outside (0, 1], or no design nodes. */
+typedef struct lbm_levelset_info {
+  double lambda;           /* Eq. (67)                                        */
+  double volume;           /* fluid fraction of the design domain (before)    */
+  double G;                /* volume - vmax                                   */
+  double scale;            /* mean |J'| over the design domain                */
+} lbm_levelset_info_t;
+int lbm_levelset_update(lbm_problem_t* p, const float* phi, float* phi_out, const float* dJ,
+                        float* gamma, double K, double sigma, double vmax,
+                        lbm_levelset_info_t* info, void* stream);
 
 /* Run exactly nsteps more adjoint steps from the current adjoint state. */
 int lbm_adjoint_continue(lbm_problem_t* p, const float* gamma, const float* drho,

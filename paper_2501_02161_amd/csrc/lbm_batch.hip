@@ -311,7 +311,10 @@ int bind_slot(lbm_batch* b, Slot& s, const Request& r, hipStream_t st) {
   HIPCHK(hipMemcpyAsync(p->flags, fl, p->Np, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(s.gamma, gam, (size_t)p->N * sizeof(float), hipMemcpyHostToDevice, st));
   HIPCHK(launch_fill(p->f[0], (size_t)19 * p->Np, st));
-  if (th) HIPCHK(launch_fill(p->g[0], (size_t)7 * p->Np, st));
+  if (th) {
+    HIPCHK(launch_fill(p->g[0], (size_t)7 * p->Np, st));
+    HIPCHK(launch_heat_init(p->g[0], s.gamma, p->flags, p->kp, st));
+  }
   HIPCHK(hipStreamSynchronize(st));  // the staging is reused
   return LBM_OK;
 }
@@ -454,6 +457,8 @@ int after_quantum(lbm_batch* b, int i, Lane& ln) {
       HIPCHK(hipStreamSynchronize(st));
       J = ln.h_sums[(size_t)i * 4];
       HIPCHK(launch_dissipation_source(s.u, s.gamma, p->flags, p->G, p->kp, st));
+    } else if (p->d.objective == LBM_OBJ_HEATGEN) {
+      J = -sums[3];
     } else {
       if (p->n_inlet > 0) J += p->d.w_dp * (sums[2] / p->n_inlet) / 3.0;
       if (p->d.objective == LBM_OBJ_HEATSINK) J += sums[3] / p->n_layer;
@@ -806,7 +811,7 @@ int lbm_batch_create(int32_t thermal, int32_t objective, int32_t max_slots, int3
   last_error().clear();
   if (!out) return fail(LBM_EINVAL, "out is NULL");
   *out = nullptr;
-  if ((thermal != 0 && thermal != 1) || objective < 0 || objective > 2 || max_slots < 1 ||
+  if ((thermal != 0 && thermal != 1) || objective < 0 || objective > 3 || max_slots < 1 ||
       max_slots > 4096 || quantum < 1)
     return fail(LBM_EINVAL, "bad batch parameters");
   lbm_batch* b = new lbm_batch();

@@ -63,7 +63,7 @@ int validate_and_setup(lbm_problem* p, const lbm_desc_t& d, const uint8_t* mask)
   if (d.thermal != 0 && d.thermal != 1) return fail(LBM_EINVAL, "thermal must be 0 or 1");
   for (int a = 0; a < 3; ++a)
     if (d.periodic[a] != 0 && d.periodic[a] != 1) return fail(LBM_EINVAL, "periodic must be 0 or 1");
-  if (d.objective < 0 || d.objective > 2) return fail(LBM_EINVAL, "unknown objective");
+  if (d.objective < 0 || d.objective > 3) return fail(LBM_EINVAL, "unknown objective");
   if (d.max_steps < 1) return fail(LBM_EINVAL, "max_steps must be >= 1");
   if (d.check_every < 0) return fail(LBM_EINVAL, "check_every must be >= 0");
   if (!(d.tol >= 0.0)) return fail(LBM_EINVAL, "tol must be >= 0");
@@ -71,7 +71,18 @@ int validate_and_setup(lbm_problem* p, const lbm_desc_t& d, const uint8_t* mask)
     return fail(LBM_EINVAL, "unknown adjoint kind");
   if (d.adjoint_kind == LBM_ADJOINT_CONTINUOUS && d.thermal)
     return fail(LBM_EINVAL, "the continuous adjoint is for the flow lattice only");
-  if (d.reserved != 0) return fail(LBM_EINVAL, "reserved must be 0");
+  for (int a = 0; a < 3; ++a) {
+    if (d.symmetric[a] != 0 && d.symmetric[a] != 1) return fail(LBM_EINVAL, "symmetric must be 0 or 1");
+    if (d.symmetric[a] && d.periodic[a]) return fail(LBM_EINVAL, "an axis cannot be periodic and symmetric");
+  }
+  if (d.symmetric[0] && d.nx < 4) return fail(LBM_EINVAL, "a symmetric axis needs at least 4 layers");
+  if (d.symmetric[1] && d.ny < 4) return fail(LBM_EINVAL, "a symmetric axis needs at least 4 layers");
+  if (d.symmetric[2] && d.nz < 4) return fail(LBM_EINVAL, "a symmetric axis needs at least 4 layers");
+  if (!(d.inlet_rho >= 0.0)) return fail(LBM_EINVAL, "inlet_rho must be >= 0");
+  if (!(d.beta_max >= 0.0) || (d.beta_max > 0.0 && !d.thermal))
+    return fail(LBM_EINVAL, "beta_max must be >= 0 and needs the thermal lattice");
+  if (d.objective == LBM_OBJ_HEATGEN && (!d.thermal || !(d.beta_max > 0.0)))
+    return fail(LBM_EINVAL, "the heat-generation objective needs the thermal lattice and beta_max > 0");
   if (!(d.alpha_max >= 0.0) || !(d.q_brink > 0.0)) return fail(LBM_EINVAL, "need alpha_max >= 0, q > 0");
   if (!(d.tau * d.alpha_max < 1.0)) return fail(LBM_EINVAL, "tau * alpha_max must be < 1 (chi > 0)");
   if (d.thermal) {
@@ -98,9 +109,14 @@ int validate_and_setup(lbm_problem* p, const lbm_desc_t& d, const uint8_t* mask)
   for (long long n = 0; n < N; ++n) {
     const unsigned m = mask[n];
     const int kind = m & 7, nc = (m >> 3) & 7;
-    if ((m >> 6) != 0 || kind > K_HEATED) return fail(LBM_EINVAL, "bad mask byte at node " + std::to_string(n));
+    if ((m >> 6) != 0 || kind > K_SYM) return fail(LBM_EINVAL, "bad mask byte at node " + std::to_string(n));
     int c[3];
     coords(n, c);
+    bool on_sym = false;
+    for (int a = 0; a < 3; ++a) on_sym = on_sym || (d.symmetric[a] && c[a] == lim[a] - 1);
+    if (on_sym != (kind == K_SYM))
+      return fail(LBM_EINVAL, "SYM nodes must fill exactly the last layer of each symmetric axis (node " +
+                                  std::to_string(n) + ")");
     bool on_face[3];
     for (int a = 0; a < 3; ++a) on_face[a] = !d.periodic[a] && (c[a] == 0 || c[a] == lim[a] - 1);
     const bool boundary_kind = kind >= K_INLET;
@@ -128,10 +144,11 @@ int validate_and_setup(lbm_problem* p, const lbm_desc_t& d, const uint8_t* mask)
     }
   }
   // counts, objective layer
-  p->n_inlet = p->n_layer = p->n_nonwall = 0;
+  p->n_inlet = p->n_layer = p->n_nonwall = p->n_design = 0;
   for (long long n = 0; n < N; ++n) {
     const int kind = p->flags_host[n] & 7;
     if (kind == K_INLET) ++p->n_inlet;
+    if (kind == K_DESIGN) ++p->n_design;
     if (kind < K_WALL) ++p->n_nonwall;
     if (kind == K_HEATED) {
       const int nc = (p->flags_host[n] >> 3) & 7;
@@ -150,8 +167,9 @@ int validate_and_setup(lbm_problem* p, const lbm_desc_t& d, const uint8_t* mask)
   if (d.objective == LBM_OBJ_HEATSINK && p->n_layer == 0)
     return fail(LBM_EINVAL, "the heat-sink objective needs HEATED walls next to non-wall nodes");
   const double nu = (d.tau - 0.5) / 3.0;
-  if (p->n_inlet > 0 && !(d.L_ref > 0.0)) return fail(LBM_EINVAL, "L_ref must be > 0 with inlets");
-  const double U = p->n_inlet > 0 ? d.Re * nu / d.L_ref : 0.0;
+  const bool pin = d.inlet_rho > 0.0;  // pressure inlets
+  if (p->n_inlet > 0 && !pin && !(d.L_ref > 0.0)) return fail(LBM_EINVAL, "L_ref must be > 0 with inlets");
+  const double U = (p->n_inlet > 0 && !pin) ? d.Re * nu / d.L_ref : 0.0;
   // inlet profile: product of parabolas over the inlet set of each normal
   for (int code = 0; code < 6; ++code) {
     int lo[3] = {1 << 30, 1 << 30, 1 << 30}, hi[3] = {-1, -1, -1};
@@ -175,7 +193,9 @@ int validate_and_setup(lbm_problem* p, const lbm_desc_t& d, const uint8_t* mask)
       for (int a = 0; a < 3; ++a) {
         if (NVEC_HOST[code][a] != 0) continue;
         if (lo[a] == 0 && hi[a] == lim[a] - 1) continue;
-        const double s = (c[a] - lo[a] + 0.5) / double(hi[a] - lo[a] + 1);
+        // an inlet set reaching a mirror plane continues in its image
+        const int h = (d.symmetric[a] && hi[a] == lim[a] - 2) ? 2 * lim[a] - 3 - lo[a] : hi[a];
+        const double s = (c[a] - lo[a] + 0.5) / double(h - lo[a] + 1);
         prof *= 4.0 * s * (1.0 - s);
       }
       p->uin_host[n] = (float)(U * prof);
@@ -211,6 +231,13 @@ int validate_and_setup(lbm_problem* p, const lbm_desc_t& d, const uint8_t* mask)
   k.two_nu = (float)(2.0 * nu);
   k.nu = (float)nu;
   k.cont = d.adjoint_kind == LBM_ADJOINT_CONTINUOUS ? 1 : 0;
+  k.sx = d.symmetric[0];
+  k.sy = d.symmetric[1];
+  k.sz = d.symmetric[2];
+  k.pin = pin ? 1 : 0;
+  k.drho_in = pin ? (float)(d.inlet_rho - d.rho0) : 0.0f;
+  k.beta = (float)d.beta_max;
+  k.heatgen = d.objective == LBM_OBJ_HEATGEN ? 1 : 0;
   return LBM_OK;
 }
 
@@ -274,6 +301,10 @@ int objective_value(lbm_problem* p, const float* gamma, const float* u, hipStrea
   }
   // p->pinned holds the forward partial sums of the last diagnostic step
   double v = 0.0;
+  if (d.objective == LBM_OBJ_HEATGEN) {
+    *J = -p->pinned[3];  // J = -sum_j Q(x_j)
+    return LBM_OK;
+  }
   if (p->n_inlet > 0) v += d.w_dp * (p->pinned[2] / p->n_inlet) / 3.0;
   if (d.objective == LBM_OBJ_HEATSINK) v += p->pinned[3] / p->n_layer;
   *J = v;
@@ -379,7 +410,7 @@ int run_adjoint(lbm_problem* p, const float* gamma, const float* u, const float*
     mon[0] = p->pinned[0] / p->n_nonwall;
     mon[1] = p->pinned[1] / p->n_nonwall;
     if (!std::isfinite(mon[0]) || !std::isfinite(mon[1])) {
-      p->adj_done = false;
+      p->adj_done = p->adj_state = false;
       return fail(LBM_EDIVERGED, "adjoint solve diverged at step " + std::to_string(k));
     }
     if (at_check) {
@@ -398,7 +429,7 @@ int run_adjoint(lbm_problem* p, const float* gamma, const float* u, const float*
   }
   int rc = sweep_end(p, 1, std::min(k, nsteps), s);
   if (rc) return rc;
-  p->adj_done = true;
+  p->adj_done = p->adj_state = true;
   if (info) {
     info->steps = std::min(k, nsteps);
     info->status = status;
@@ -542,7 +573,7 @@ int lbm_bind_workspace(lbm_problem_t* p, void* device_ptr, size_t bytes) {
   std::copy(p->flags_host.begin(), p->flags_host.end(), fl.begin());
   HIPCHK(hipMemcpy(p->uin, uin.data(), p->Np * sizeof(float), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(p->flags, fl.data(), p->Np, hipMemcpyHostToDevice));
-  p->fwd_done = p->adj_done = false;
+  p->fwd_done = p->adj_done = p->adj_state = false;
   return LBM_OK;
 }
 
@@ -557,7 +588,10 @@ int lbm_forward_solve(lbm_problem_t* p, const float* gamma, float* drho, float* 
   p->fwd_done = p->adj_done = p->have_gneq = false;
   p->fcur = 0;
   HIPCHK(launch_fill(p->f[0], (size_t)19 * p->Np, s));
-  if (thermal_of(p)) HIPCHK(launch_fill(p->g[0], (size_t)7 * p->Np, s));
+  if (thermal_of(p)) {
+    HIPCHK(launch_fill(p->g[0], (size_t)7 * p->Np, s));
+    HIPCHK(launch_heat_init(p->g[0], gamma, p->flags, p->kp, s));
+  }
   return run_forward(p, gamma, drho, u, T, p->d.max_steps, p->d.check_every, p->d.tol, s, info);
 }
 
@@ -584,7 +618,7 @@ int lbm_adjoint_solve(lbm_problem_t* p, const float* gamma, const float* drho, c
   if (!gamma || !u || (thermal_of(p) && !T)) return fail(LBM_EINVAL, "null field pointer");
   DeviceGuard guard(p->dev);
   hipStream_t s = (hipStream_t)stream;
-  p->adj_done = false;
+  p->adj_done = p->adj_state = false;
   p->acur = 0;
   if (p->d.objective == LBM_OBJ_DISSIPATION)
     HIPCHK(launch_dissipation_source(u, gamma, p->flags, p->G, p->kp, s));
@@ -603,6 +637,70 @@ int lbm_thermal_resolve(lbm_problem_t* p, const float* gamma, const float* u, co
   DeviceGuard guard(p->dev);
   return run_thermal(p, gamma, u, T, p->d.max_steps, p->d.check_every, p->d.tol, (hipStream_t)stream,
                      info);
+}
+
+int lbm_forward_resume(lbm_problem_t* p, const float* gamma, float* drho, float* u, float* T,
+                       lbm_info_t* info, void* stream) {
+  last_error().clear();
+  int rc = check_bound(p);
+  if (rc) return rc;
+  if (!p->fwd_done) return fail(LBM_ESTATE, "no forward state to resume");
+  if (!gamma || !drho || !u || (thermal_of(p) && !T)) return fail(LBM_EINVAL, "null field pointer");
+  DeviceGuard guard(p->dev);
+  return run_forward(p, gamma, drho, u, T, p->d.max_steps, p->d.check_every, p->d.tol,
+                     (hipStream_t)stream, info);
+}
+
+int lbm_adjoint_resume(lbm_problem_t* p, const float* gamma, const float* drho, const float* u,
+                       const float* T, lbm_info_t* info, void* stream) {
+  (void)drho;
+  last_error().clear();
+  int rc = check_bound(p);
+  if (rc) return rc;
+  if (!p->adj_state) return fail(LBM_ESTATE, "no adjoint state to resume");
+  if (thermal_of(p) && !p->have_gneq)
+    return fail(LBM_ESTATE, "adjoint resume needs the thermal state of a forward solve");
+  if (!gamma || !u || (thermal_of(p) && !T)) return fail(LBM_EINVAL, "null field pointer");
+  DeviceGuard guard(p->dev);
+  hipStream_t s = (hipStream_t)stream;
+  if (p->d.objective == LBM_OBJ_DISSIPATION)
+    HIPCHK(launch_dissipation_source(u, gamma, p->flags, p->G, p->kp, s));
+  return run_adjoint(p, gamma, u, T, p->d.max_steps, p->d.check_every, p->d.tol, s, info);
+}
+
+int lbm_levelset_update(lbm_problem_t* p, const float* phi, float* phi_out, const float* dJ,
+                        float* gamma, double K, double sigma, double vmax,
+                        lbm_levelset_info_t* info, void* stream) {
+  last_error().clear();
+  int rc = check_bound(p);
+  if (rc) return rc;
+  if (!phi || !phi_out || !dJ || !gamma) return fail(LBM_EINVAL, "null field pointer");
+  if (phi == phi_out) return fail(LBM_EINVAL, "phi and phi_out must differ (stencil)");
+  if (!(K > 0.0) || !(sigma >= 0.0) || !(vmax > 0.0 && vmax <= 1.0))
+    return fail(LBM_EINVAL, "need K > 0, sigma >= 0, 0 < vmax <= 1");
+  if (p->n_design == 0) return fail(LBM_EINVAL, "the problem has no design nodes");
+  DeviceGuard guard(p->dev);
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHK(launch_levelset_stats(phi, dJ, p->flags, p->partials, p->kp, s));
+  rc = read_sums(p, 2, s);
+  if (rc) return rc;
+  const double scale = p->pinned[0] / p->n_design;  // mean |J'| over the design domain
+  const double volume = p->pinned[1] / p->n_design; // fluid fraction (phi >= 0, Eq. 15)
+  const double G = volume - vmax;                     // volume constraint of Eq. (10)
+  const float inv_scale = scale > 0.0 ? (float)(1.0 / scale) : 0.0f;
+  HIPCHK(launch_levelset_lambda(phi, dJ, p->flags, inv_scale, (float)sigma, p->partials, p->kp, s));
+  rc = read_sums(p, 1, s);
+  if (rc) return rc;
+  const double lambda = std::exp(G) * p->pinned[0] / p->n_design;  // Eq. (67)
+  HIPCHK(launch_levelset_update(phi, phi_out, dJ, p->flags, gamma, inv_scale, (float)sigma, (float)K,
+                                (float)lambda, p->kp, s));
+  if (info) {
+    info->lambda = lambda;
+    info->volume = volume;
+    info->G = G;
+    info->scale = scale;
+  }
+  return LBM_OK;
 }
 
 int lbm_adjoint_continue(lbm_problem_t* p, const float* gamma, const float* drho, const float* u,

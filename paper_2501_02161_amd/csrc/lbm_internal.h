@@ -21,10 +21,10 @@ constexpr int kRedDiss = 1;      // dissipation objective
 
 // Node flag byte on the device: bits 0-2 kind, 3-5 inward-normal code (as in
 // the mask), bit 6 = node of the heat-sink objective layer.
-enum : int { K_DESIGN = 0, K_FLUID = 1, K_INLET = 2, K_OUTLET = 3, K_WALL = 4, K_HEATED = 5 };
+enum : int { K_DESIGN = 0, K_FLUID = 1, K_INLET = 2, K_OUTLET = 3, K_WALL = 4, K_HEATED = 5, K_SYM = 6 };
 constexpr unsigned kLayerBit = 0x40u;
 
-enum : int { OBJ_PRESSURE_DROP = 0, OBJ_DISSIPATION = 1, OBJ_HEATSINK = 2 };
+enum : int { OBJ_PRESSURE_DROP = 0, OBJ_DISSIPATION = 1, OBJ_HEATSINK = 2, OBJ_HEATGEN = 3 };
 
 // Per-problem constants handed to every kernel by value.
 struct KParams {
@@ -46,6 +46,11 @@ struct KParams {
   float two_nu;                  // 2 nu (dissipation source)
   float nu;
   int cont;                      // adjoint: 1 = continuous variant (flow lattice only)
+  int sx, sy, sz;                // mirror plane before the last layer of the axis
+  int pin;                       // 1: inlets are pressure inlets at rho0 + drho_in
+  float drho_in;
+  float beta;                    // heat generation beta_max (0: none)
+  int heatgen;                   // objective J = -sum beta (1 - T): forward partial 3
 };
 
 struct FwdArgs {
@@ -126,6 +131,19 @@ struct Tile {
 
 // Launchers (return the hipError_t of the launch).
 hipError_t launch_fill(float* p, size_t count, hipStream_t s);
+// Level-set design update (per-block FP64 partials: stats 2 values, lambda 1).
+hipError_t launch_levelset_stats(const float* phi, const float* dJ, const uint8_t* flags,
+                                 double* partials, const KParams& P, hipStream_t s);
+hipError_t launch_levelset_lambda(const float* phi, const float* dJ, const uint8_t* flags,
+                                  float inv_scale, float sigma, double* partials, const KParams& P,
+                                  hipStream_t s);
+hipError_t launch_levelset_update(const float* phi, float* phi_out, const float* dJ,
+                                  const uint8_t* flags, float* gamma, float inv_scale, float sigma,
+                                  float K, float lambda, const KParams& P, hipStream_t s);
+// Adds the first collision's heat source to a zero-filled thermal state
+// (no-op without heat generation).
+hipError_t launch_heat_init(float* g, const float* gamma, const uint8_t* flags, const KParams& P,
+                            hipStream_t s);
 // Step kernels; with non-null events the launch records them at the start and
 // end of the kernel itself (hipExtLaunchKernelGGL), for per-launch timing.
 hipError_t launch_forward(const FwdArgs& a, bool thermal, bool diag, hipStream_t s,
@@ -191,7 +209,7 @@ struct lbm_problem {
   int N = 0, Np = 0, nblk = 0;
   std::vector<uint8_t> flags_host;
   std::vector<float> uin_host;
-  int n_inlet = 0, n_layer = 0, n_nonwall = 0;
+  int n_inlet = 0, n_layer = 0, n_nonwall = 0, n_design = 0;
   lbmadj::KParams kp{};
   // workspace
   char* ws = nullptr;
@@ -210,6 +228,7 @@ struct lbm_problem {
   double* pinned = nullptr;
   int fcur = 0, acur = 0;
   bool fwd_done = false, adj_done = false;
+  bool adj_state = false;  // the adjoint populations hold a finished adjoint solve (resumable)
   bool have_gneq = false;  // thermal non-equilibrium of a converged state in the workspace
   double J = 0.0;
   // sweep timing: one event pair around each forward / adjoint sweep

@@ -31,6 +31,7 @@ namespace {
 // the axis direction with normal code c (+x 0, -x 1, ... -z 5) is index c + 1.
 // ----------------------------------------------------------------------------
 struct Q19 {
+  static constexpr int Q = 19;
   static constexpr int ex[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
   static constexpr int ey[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
   static constexpr int ez[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
@@ -41,6 +42,7 @@ struct Q19 {
                                   1.f / 36.f, 1.f / 36.f, 1.f / 36.f, 1.f / 36.f};
 };
 struct Q7 {
+  static constexpr int Q = 7;
   static constexpr int ex[7] = {0, 1, -1, 0, 0, 0, 0};
   static constexpr int ey[7] = {0, 0, 0, 1, -1, 0, 0};
   static constexpr int ez[7] = {0, 0, 0, 0, 0, 1, -1};
@@ -129,6 +131,60 @@ __device__ __forceinline__ float load_nbr(const float* __restrict__ base, const 
   return v ? r : 0.0f;
 }
 
+// Direction index of lattice L with velocity (ex, ey, ez), and of direction I
+// reflected in the axes of mask M (bit 0 x, 1 y, 2 z).
+template <class L>
+constexpr int find_dir(int ex, int ey, int ez) {
+  for (int i = 0; i < L::Q; ++i)
+    if (L::ex[i] == ex && L::ey[i] == ey && L::ez[i] == ez) return i;
+  return -1;
+}
+template <class L, int I, int M>
+constexpr int mirror_dir() {
+  return find_dir<L>((M & 1) ? -L::ex[I] : L::ex[I], (M & 2) ? -L::ey[I] : L::ey[I],
+                     (M & 4) ? -L::ez[I] : L::ez[I]);
+}
+
+// Whether the + neighbour along each axis is the layer beyond a mirror plane.
+struct Mirror {
+  bool x, y, z;
+};
+__device__ __forceinline__ Mirror mirror_of(int x, int y, int z, const KParams& P) {
+  Mirror m;
+  m.x = P.sx && x == P.nx - 2;
+  m.y = P.sy && y == P.ny - 2;
+  m.z = P.sz && z == P.nz - 2;
+  return m;
+}
+
+// Population I pulled from the neighbour n + (DX, DY, DZ) (zero beyond a
+// non-periodic face).  Where that neighbour lies beyond a mirror plane (only
+// possible on the + side of an axis), the mirror image is read instead: the
+// node's own layer along that axis and direction I reflected in it (specular
+// reflection at the plane midway between the two layers; the quarter-domain
+// heat sink).  Forward pulls use (-e_I), adjoint pulls (+e_I); in both the
+// reflected slot is the transpose of the other's.
+template <class L, int I, int DX, int DY, int DZ>
+__device__ __forceinline__ float load_pull(const float* __restrict__ base, size_t Np, const Nbr& b,
+                                           int n, const Mirror& m) {
+  if constexpr (DX != 1 && DY != 1 && DZ != 1) {
+    return load_nbr<DX, DY, DZ>(base + (size_t)I * Np, b, n);
+  } else {
+    const bool rx = (DX == 1) && m.x, ry = (DY == 1) && m.y, rz = (DZ == 1) && m.z;
+    constexpr int I1 = mirror_dir<L, I, 1>(), I2 = mirror_dir<L, I, 2>(), I3 = mirror_dir<L, I, 3>();
+    constexpr int I4 = mirror_dir<L, I, 4>(), I5 = mirror_dir<L, I, 5>(), I6 = mirror_dir<L, I, 6>();
+    constexpr int I7 = mirror_dir<L, I, 7>();
+    const int p = rz ? (ry ? (rx ? I7 : I6) : (rx ? I5 : I4)) : (ry ? (rx ? I3 : I2) : (rx ? I1 : I));
+    const int X = rx ? b.X[1] : b.X[DX + 1];
+    const int Yo = ry ? b.Yo[1] : b.Yo[DY + 1];
+    const int Zo = rz ? b.Zo[1] : b.Zo[DZ + 1];
+    const bool v = (rx || b.vx[DX + 1]) && (ry || b.vy[DY + 1]) && (rz || b.vz[DZ + 1]);
+    const int s = v ? X + Yo + Zo : n;
+    const float r = base[(size_t)p * Np + s];
+    return v ? r : 0.0f;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Design parametrisation (see the header): chi, a_B, thermal tau and their
 // derivatives with respect to gamma.
@@ -161,7 +217,11 @@ __device__ __forceinline__ Normal normal_of(int c) {
 // gives j_n = -sum_{e.n=0} h - 2 sum_{e.n<0} h.  Written with selects on the
 // runtime normal so the populations stay in registers.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void zou_he(float (&h)[19], Normal nv, bool inlet, float jn_in) {
+// Generic Zou-He rule on shifted populations (f - w rho0).  Velocity inlet:
+// prescribed rho0 u_n = jn_in.  Pressure outlet / pressure inlet:
+// rho0 u_n = rho_b - sum_T f - 2 sum_O f, i.e. drho_b - (sum_T h + 2 sum_O h).
+__device__ __forceinline__ void zou_he(float (&h)[19], Normal nv, bool inlet, float jn_in,
+                                       float drho_b = 0.0f) {
   float sT = 0.f, sO = 0.f, Nx = 0.f, Ny = 0.f, Nz = 0.f;
   sfor<19>([&](auto I) {
     constexpr int i = I;
@@ -173,7 +233,7 @@ __device__ __forceinline__ void zou_he(float (&h)[19], Normal nv, bool inlet, fl
     if constexpr (Q19::ey[i] != 0) Ny += float(Q19::ey[i]) * t;
     if constexpr (Q19::ez[i] != 0) Nz += float(Q19::ez[i]) * t;
   });
-  const float jn = inlet ? jn_in : -(sT + 2.0f * sO);
+  const float jn = inlet ? jn_in : drho_b - (sT + 2.0f * sO);
   float o[19];
   sfor<19>([&](auto I) {
     constexpr int i = I;
@@ -281,18 +341,19 @@ __device__ __forceinline__ void forward_tile(const FwdArgs& A, int blk) {
   if (n < P.N) {
     const int x = n % P.nx, t = n / P.nx, y = t % P.ny, z = t / P.ny;
     const Nbr nb = make_nbr(x, y, z, P);
+    const Mirror mr = mirror_of(x, y, z, P);
     const unsigned fl = A.flags[n];
     const int kind = fl & 7, nc = (fl >> 3) & 7;
     float h[19];
     sfor<19>([&](auto I) {
       constexpr int i = I;
-      h[i] = load_nbr<-Q19::ex[i], -Q19::ey[i], -Q19::ez[i]>(A.fin + (size_t)i * P.Np, nb, n);
+      h[i] = load_pull<Q19, i, -Q19::ex[i], -Q19::ey[i], -Q19::ez[i]>(A.fin, P.Np, nb, n, mr);
     });
     float k[7];
     if constexpr (THERMAL) {
       sfor<7>([&](auto I) {
         constexpr int i = I;
-        k[i] = load_nbr<-Q7::ex[i], -Q7::ey[i], -Q7::ez[i]>(A.gin + (size_t)i * P.Np, nb, n);
+        k[i] = load_pull<Q7, i, -Q7::ex[i], -Q7::ey[i], -Q7::ez[i]>(A.gin, P.Np, nb, n, mr);
       });
       // zero-gradient outflow: the population along the inward normal takes
       // the node's own post-collision value
@@ -335,8 +396,9 @@ __device__ __forceinline__ void forward_tile(const FwdArgs& A, int blk) {
       }
     } else {
       if (kind == K_INLET || kind == K_OUTLET) {
-        const float jn = (kind == K_INLET) ? A.uin[n] * P.rho0 : 0.f;
-        zou_he(h, normal_of(nc), kind == K_INLET, jn);
+        const bool vin = kind == K_INLET && !P.pin;   // velocity inlet
+        const float jn = vin ? A.uin[n] * P.rho0 : 0.f;
+        zou_he(h, normal_of(nc), vin, jn, (kind == K_INLET) ? P.drho_in : 0.0f);
       }
       if constexpr (THERMAL) {
         if (kind == K_INLET) {
@@ -376,13 +438,18 @@ __device__ __forceinline__ void forward_tile(const FwdArgs& A, int blk) {
         Tabs = P.T_ref + dT;
         const float tg = 0.5f + P.dfc * ((kind == K_DESIGN) ? khat_of(gam, P) : 1.0f);
         const float og = 1.0f / tg;
+        // heat generation Q = beta_max (1 - gamma) (1 - T) in the design domain
+        const float Qh = (kind == K_DESIGN) ? P.beta * (1.0f - gam) * (1.0f - Tabs) : 0.0f;
         sfor<7>([&](auto I) {
           constexpr int i = I;
           const float eu = float(Q7::ex[i]) * ux + float(Q7::ey[i]) * uy + float(Q7::ez[i]) * uz;
           const float keq = Q7::w[i] * (dT + 4.0f * Tabs * eu);
-          A.gout[(size_t)i * P.Np + n] = k[i] + og * (keq - k[i]);
+          A.gout[(size_t)i * P.Np + n] = k[i] + og * (keq - k[i]) + Q7::w[i] * Qh;
           if constexpr (DIAG) A.gneq[(size_t)i * P.Np + n] = k[i] - keq;
         });
+        if constexpr (DIAG) {
+          if (P.heatgen) acc[3] = (double)Qh;
+        }
       }
       if constexpr (DIAG) {
         A.drho[n] = drho;
@@ -425,18 +492,19 @@ __device__ __forceinline__ void adjoint_tile(const AdjArgs& A, int blk) {
   if (n < P.N) {
     const int x = n % P.nx, t = n / P.nx, y = t % P.ny, z = t / P.ny;
     const Nbr nb = make_nbr(x, y, z, P);
+    const Mirror mr = mirror_of(x, y, z, P);
     const unsigned fl = A.flags[n];
     const int kind = fl & 7, nc = (fl >> 3) & 7;
     float a[19];
     sfor<19>([&](auto I) {
       constexpr int i = I;
-      a[i] = load_nbr<Q19::ex[i], Q19::ey[i], Q19::ez[i]>(A.ain + (size_t)i * P.Np, nb, n);
+      a[i] = load_pull<Q19, i, Q19::ex[i], Q19::ey[i], Q19::ez[i]>(A.ain, P.Np, nb, n, mr);
     });
     float b[7];
     if constexpr (THERMAL) {
       sfor<7>([&](auto I) {
         constexpr int i = I;
-        b[i] = load_nbr<Q7::ex[i], Q7::ey[i], Q7::ez[i]>(A.bin + (size_t)i * P.Np, nb, n);
+        b[i] = load_pull<Q7, i, Q7::ex[i], Q7::ey[i], Q7::ez[i]>(A.bin, P.Np, nb, n, mr);
       });
       // transpose of the outflow self-copy
       if (kind == K_OUTLET) {
@@ -467,8 +535,11 @@ __device__ __forceinline__ void adjoint_tile(const AdjArgs& A, int blk) {
       // collision (order collision -> streaming -> boundary of Eq. 30); the
       // inlet-pressure objective enters here and not as a collision source
       if (kind == K_INLET || kind == K_OUTLET) {
-        const float src = (OBJ == OBJ_PRESSURE_DROP && kind == K_INLET) ? 2.0f * P.c_in : 0.0f;
-        zou_he_continuous(a, normal_of(nc), kind == K_OUTLET, src);
+        // a pressure inlet follows the outlet rule; the inlet pressure it fixes
+        // gives the objective no boundary term there
+        const bool prs = kind == K_OUTLET || P.pin;
+        const float src = (OBJ == OBJ_PRESSURE_DROP && !prs) ? 2.0f * P.c_in : 0.0f;
+        zou_he_continuous(a, normal_of(nc), prs, src);
       }
     }
     if (kind >= K_WALL) {
@@ -503,7 +574,7 @@ __device__ __forceinline__ void adjoint_tile(const AdjArgs& A, int blk) {
       const float Vy = chi * (3.0f * M1y + 9.0f * Ky - 3.0f * M0 * vy);
       const float Vz = chi * (3.0f * M1z + 9.0f * Kz - 3.0f * M0 * vz);
       float Wx = 0.f, Wy = 0.f, Wz = 0.f;
-      float Bg = 0.f, og = 0.f;
+      float Bg = 0.f, og = 0.f, Sbw = 0.f;
       if constexpr (THERMAL) {
         const float Tn = A.T[n];
         const float tg = 0.5f + P.dfc * ((kind == K_DESIGN) ? khat_of(gam, P) : 1.0f);
@@ -518,6 +589,7 @@ __device__ __forceinline__ void adjoint_tile(const AdjArgs& A, int blk) {
           if constexpr (Q7::ez[i] != 0) Mbz += float(Q7::ez[i]) * wb;
         });
         Bg = Sb + 4.0f * (ux * Mbx + uy * Mby + uz * Mbz);
+        Sbw = Sb;
         const float cW = 4.0f * og * Tn / P.rho0;
         Wx = cW * Mbx;
         Wy = cW * Mby;
@@ -531,6 +603,10 @@ __device__ __forceinline__ void adjoint_tile(const AdjArgs& A, int blk) {
       if constexpr (OBJ == OBJ_HEATSINK) {
         if (fl & kLayerBit) dsrc = P.c_layer;
       }
+      // heat generation beta (1 - T): its d/dg_j in the collision, and
+      // dJ/dg_j = beta for J = -sum beta (1 - T)
+      const float bq = (THERMAL && kind == K_DESIGN) ? P.beta * (1.0f - gam) : 0.0f;
+      if constexpr (OBJ == OBJ_HEATGEN) dsrc = bq;
       if constexpr (OBJ == OBJ_DISSIPATION) {
         Gx = A.G[n];
         Gy = A.G[(size_t)P.Np + n];
@@ -551,12 +627,12 @@ __device__ __forceinline__ void adjoint_tile(const AdjArgs& A, int blk) {
       });
       if constexpr (!CONT) {
         if (kind == K_INLET || kind == K_OUTLET)
-          zou_he_transpose(c, normal_of(nc), kind == K_OUTLET);
+          zou_he_transpose(c, normal_of(nc), kind == K_OUTLET || P.pin);
       }
       sfor<19>([&](auto I) { A.aout[(size_t)I * P.Np + n] = c[I]; });
       if constexpr (THERMAL) {
         float cg[7];
-        const float bb = og * Bg - dsrc;
+        const float bb = og * Bg - dsrc - bq * Sbw;
         sfor<7>([&](auto I) {
           constexpr int i = I;
           cg[i] = (1.0f - og) * b[i] + bb;
@@ -584,7 +660,9 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(AdjArgs A) {
 // Sensitivity, Eq. (66) with the exact derivative of the collision:
 // dJ/dgamma = explicit - (1/tau) chi' rho0 sum_i w_i a_i [3 e.u + 9 chi (e.u)^2
 // - 3 chi |u|^2] - (tau_g'/tau_g^2) sum_i b_i (g_i - geq_i), a, b the reversed
-// pulls of the final adjoint state.  Non-design nodes get 0.
+// pulls of the final adjoint state; with heat generation also
+// + beta_max (1 - T) sum_i w_i b_i (and + beta_max (1 - T) for J = -sum Q).
+// Non-design nodes get 0.
 // ---------------------------------------------------------------------------
 template <bool THERMAL>
 __global__ __launch_bounds__(kBlock) void k_sensitivity(SensArgs A) {
@@ -599,6 +677,7 @@ __global__ __launch_bounds__(kBlock) void k_sensitivity(SensArgs A) {
     if (kind == K_DESIGN) {
       const int x = n % P.nx, t = n / P.nx, y = t % P.ny, z = t / P.ny;
       const Nbr nb = make_nbr(x, y, z, P);
+      const Mirror mr = mirror_of(x, y, z, P);
       const float ux = A.u[n], uy = A.u[P.N + n], uz = A.u[2 * P.N + n];
       const float gam = A.gamma[n];
       const float chi = chi_of(gam, P);
@@ -608,7 +687,7 @@ __global__ __launch_bounds__(kBlock) void k_sensitivity(SensArgs A) {
       float s = 0.f;
       sfor<19>([&](auto I) {
         constexpr int i = I;
-        const float a = load_nbr<Q19::ex[i], Q19::ey[i], Q19::ez[i]>(A.ain + (size_t)i * P.Np, nb, n);
+        const float a = load_pull<Q19, i, Q19::ex[i], Q19::ey[i], Q19::ez[i]>(A.ain, P.Np, nb, n, mr);
         const float eu = float(Q19::ex[i]) * ux + float(Q19::ey[i]) * uy + float(Q19::ez[i]) * uz;
         s += Q19::w[i] * a * (3.0f * eu + 9.0f * chi * eu * eu - 3.0f * chi * uu);
       });
@@ -619,13 +698,21 @@ __global__ __launch_bounds__(kBlock) void k_sensitivity(SensArgs A) {
         const float dkh = (1.0f - P.kr) * (1.0f + P.qr) / (den * den);
         const float tg = 0.5f + P.dfc * kh;
         const float dtg = P.dfc * dkh;
-        float sg = 0.f;
+        float sg = 0.f, swb = 0.f;
         sfor<7>([&](auto I) {
           constexpr int i = I;
-          const float b = load_nbr<Q7::ex[i], Q7::ey[i], Q7::ez[i]>(A.bin + (size_t)i * P.Np, nb, n);
+          const float b = load_pull<Q7, i, Q7::ex[i], Q7::ey[i], Q7::ez[i]>(A.bin, P.Np, nb, n, mr);
           sg += b * A.gneq[(size_t)i * P.Np + n];
+          swb += Q7::w[i] * b;
         });
         out -= dtg / (tg * tg) * sg;
+        // heat generation: d(w_i beta (1 - T))/dgamma = -w_i beta_max (1 - T),
+        // and the explicit dJ/dgamma = beta_max (1 - T) of J = -sum Q
+        if (P.beta > 0.0f) {
+          const float q = P.beta * (1.0f - A.T[n]);
+          out += q * swb;
+          if (A.objective == OBJ_HEATGEN) out += q;
+        }
       }
       if (A.objective == OBJ_DISSIPATION) {
         const float dab = -P.amq * (1.0f + P.qb) / (qg * qg);
@@ -811,12 +898,13 @@ __global__ __launch_bounds__(kBlock) void k_thermal(ThermArgs A) {
   if (n < P.N) {
     const int x = n % P.nx, t = n / P.nx, y = t % P.ny, z = t / P.ny;
     const Nbr nb = make_nbr(x, y, z, P);
+    const Mirror mr = mirror_of(x, y, z, P);
     const unsigned fl = A.flags[n];
     const int kind = fl & 7, nc = (fl >> 3) & 7;
     float k[7];
     sfor<7>([&](auto I) {
       constexpr int i = I;
-      k[i] = load_nbr<-Q7::ex[i], -Q7::ey[i], -Q7::ez[i]>(A.gin + (size_t)i * P.Np, nb, n);
+      k[i] = load_pull<Q7, i, -Q7::ex[i], -Q7::ey[i], -Q7::ez[i]>(A.gin, P.Np, nb, n, mr);
     });
     const int d = nc + 1;
     if (kind == K_OUTLET) {
@@ -839,13 +927,15 @@ __global__ __launch_bounds__(kBlock) void k_thermal(ThermArgs A) {
       float dT = 0.f;
       sfor<7>([&](auto I) { dT += k[I]; });
       const float Tabs = P.T_ref + dT;
-      const float tg = 0.5f + P.dfc * ((kind == K_DESIGN) ? khat_of(A.gamma[n], P) : 1.0f);
+      const float gm = (kind == K_DESIGN) ? A.gamma[n] : 1.0f;
+      const float tg = 0.5f + P.dfc * ((kind == K_DESIGN) ? khat_of(gm, P) : 1.0f);
       const float og = 1.0f / tg;
+      const float Qh = (kind == K_DESIGN) ? P.beta * (1.0f - gm) * (1.0f - Tabs) : 0.0f;
       sfor<7>([&](auto I) {
         constexpr int i = I;
         const float eu = float(Q7::ex[i]) * ux + float(Q7::ey[i]) * uy + float(Q7::ez[i]) * uz;
         const float keq = Q7::w[i] * (dT + 4.0f * Tabs * eu);
-        A.gout[(size_t)i * P.Np + n] = k[i] + og * (keq - k[i]);
+        A.gout[(size_t)i * P.Np + n] = k[i] + og * (keq - k[i]) + Q7::w[i] * Qh;
         if constexpr (DIAG) A.gneq[(size_t)i * P.Np + n] = k[i] - keq;
       });
       if constexpr (DIAG) {
@@ -884,6 +974,127 @@ __global__ void k_fill(float* __restrict__ p, size_t count) {
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// Level-set update of the design (Eqs. 14, 15, 67) on the design nodes.
+// Laplacian: 7-point stencil over design nodes; a neighbour that is not a
+// design node (or lies outside the box) counts as the node itself (no flux).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float levelset_laplacian(const float* __restrict__ phi,
+                                                    const uint8_t* __restrict__ flags, int n,
+                                                    const KParams& P) {
+  const int x = n % P.nx, t = n / P.nx, y = t % P.ny, z = t / P.ny;
+  const float c = phi[n];
+  float s = 0.f;
+  int cnt = 0;
+  auto add = [&](bool ok, int m) {
+    const bool d = ok && (flags[m] & 7) == K_DESIGN;
+    s += d ? phi[m] : c;
+    ++cnt;
+  };
+  add(x > 0, x > 0 ? n - 1 : n);
+  add(x < P.nx - 1, x < P.nx - 1 ? n + 1 : n);
+  add(y > 0, y > 0 ? n - P.nx : n);
+  add(y < P.ny - 1, y < P.ny - 1 ? n + P.nx : n);
+  add(z > 0, z > 0 ? n - P.plane : n);
+  add(z < P.nz - 1, z < P.nz - 1 ? n + P.plane : n);
+  return s - float(cnt) * c;
+}
+
+// Pass 1: sum |J'| and the fluid count (phi >= 0) over design nodes.
+__global__ __launch_bounds__(kBlock) void k_levelset_stats(const float* __restrict__ phi,
+                                                           const float* __restrict__ dJ,
+                                                           const uint8_t* __restrict__ flags,
+                                                           double* __restrict__ partials,
+                                                           KParams P) {
+  const int n = blockIdx.x * kBlock + threadIdx.x;
+  double acc[2] = {0.0, 0.0};
+  if (n < P.N && (flags[n] & 7) == K_DESIGN) {
+    acc[0] = fabs((double)dJ[n]);
+    acc[1] = phi[n] >= 0.0f ? 1.0 : 0.0;
+  }
+  block_reduce_store<2>(acc, partials + (size_t)blockIdx.x * 2);
+}
+
+// Pass 2: sum |J'/scale - sigma lap(phi)| over design nodes (for lambda).
+__global__ __launch_bounds__(kBlock) void k_levelset_lambda(const float* __restrict__ phi,
+                                                            const float* __restrict__ dJ,
+                                                            const uint8_t* __restrict__ flags,
+                                                            float inv_scale, float sigma,
+                                                            double* __restrict__ partials,
+                                                            KParams P) {
+  const int n = blockIdx.x * kBlock + threadIdx.x;
+  double acc[1] = {0.0};
+  if (n < P.N && (flags[n] & 7) == K_DESIGN)
+    acc[0] = fabs((double)(dJ[n] * inv_scale - sigma * levelset_laplacian(phi, flags, n, P)));
+  block_reduce_store<1>(acc, partials + blockIdx.x);
+}
+
+// Pass 3: phi <- clamp(phi - K (J'/scale + lambda - sigma lap(phi)), -1, 1)
+// (explicit step of Eq. 14), gamma = 1 where phi >= 0 else 0 (Eq. 15).
+__global__ __launch_bounds__(kBlock) void k_levelset_update(const float* __restrict__ phi,
+                                                            float* __restrict__ phi_out,
+                                                            const float* __restrict__ dJ,
+                                                            const uint8_t* __restrict__ flags,
+                                                            float* __restrict__ gamma,
+                                                            float inv_scale, float sigma, float K,
+                                                            float lambda, KParams P) {
+  const int n = blockIdx.x * kBlock + threadIdx.x;
+  if (n >= P.N) return;
+  if ((flags[n] & 7) != K_DESIGN) {
+    phi_out[n] = phi[n];
+    return;
+  }
+  const float r = dJ[n] * inv_scale + lambda - sigma * levelset_laplacian(phi, flags, n, P);
+  const float v = fminf(1.0f, fmaxf(-1.0f, phi[n] - K * r));
+  phi_out[n] = v;
+  gamma[n] = v >= 0.0f ? 1.0f : 0.0f;
+}
+
+hipError_t launch_levelset_stats(const float* phi, const float* dJ, const uint8_t* flags,
+                                 double* partials, const KParams& P, hipStream_t s) {
+  hipLaunchKernelGGL(k_levelset_stats, dim3(P.nblk), dim3(kBlock), 0, s, phi, dJ, flags, partials, P);
+  return hipGetLastError();
+}
+hipError_t launch_levelset_lambda(const float* phi, const float* dJ, const uint8_t* flags,
+                                  float inv_scale, float sigma, double* partials, const KParams& P,
+                                  hipStream_t s) {
+  hipLaunchKernelGGL(k_levelset_lambda, dim3(P.nblk), dim3(kBlock), 0, s, phi, dJ, flags, inv_scale,
+                     sigma, partials, P);
+  return hipGetLastError();
+}
+hipError_t launch_levelset_update(const float* phi, float* phi_out, const float* dJ,
+                                  const uint8_t* flags, float* gamma, float inv_scale, float sigma,
+                                  float K, float lambda, const KParams& P, hipStream_t s) {
+  hipLaunchKernelGGL(k_levelset_update, dim3(P.nblk), dim3(kBlock), 0, s, phi, phi_out, dJ, flags,
+                     gamma, inv_scale, sigma, K, lambda, P);
+  return hipGetLastError();
+}
+
+// Initial thermal state with heat generation: the rest state (zero in shifted
+// variables) after its first collision, which adds w_i Q with
+// Q = beta_max (1 - gamma) (1 - T_in) on design nodes.  The step kernels
+// store post-collision populations, so this makes the stored start the image
+// of the rest state under the collision, as the forward map C -> S -> B from
+// the rest state has it (without a source that collision is the identity).
+__global__ __launch_bounds__(kBlock) void k_heat_init(float* __restrict__ g,
+                                                      const float* __restrict__ gamma,
+                                                      const uint8_t* __restrict__ flags,
+                                                      KParams P) {
+  const int n = blockIdx.x * kBlock + threadIdx.x;
+  if (n >= P.N) return;
+  if ((flags[n] & 7) != K_DESIGN) return;
+  const float Q = P.beta * (1.0f - gamma[n]) * (1.0f - P.T_ref);
+  sfor<7>([&](auto I) { g[(size_t)I * P.Np + n] = Q7::w[I] * Q; });
+}
+
+hipError_t launch_heat_init(float* g, const float* gamma, const uint8_t* flags, const KParams& P,
+                            hipStream_t s) {
+  if (!(P.beta > 0.0f)) return hipSuccess;
+  hipLaunchKernelGGL(k_heat_init, dim3((P.N + kBlock - 1) / kBlock), dim3(kBlock), 0, s, g, gamma,
+                     flags, P);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill(float* p, size_t count, hipStream_t s) {
   if (count == 0) return hipSuccess;
   const unsigned blocks = (unsigned)((count + kBlock - 1) / kBlock);
@@ -932,6 +1143,7 @@ hipError_t launch_adjoint(const AdjArgs& a, bool thermal, int objective, bool di
     switch (objective) {
       case OBJ_PRESSURE_DROP: adj_dispatch<true, OBJ_PRESSURE_DROP>(a, diag, s, ev0, ev1); break;
       case OBJ_DISSIPATION: adj_dispatch<true, OBJ_DISSIPATION>(a, diag, s, ev0, ev1); break;
+      case OBJ_HEATGEN: adj_dispatch<true, OBJ_HEATGEN>(a, diag, s, ev0, ev1); break;
       default: adj_dispatch<true, OBJ_HEATSINK>(a, diag, s, ev0, ev1); break;
     }
   } else {
@@ -991,6 +1203,9 @@ hipError_t launch_batch(const Tile* tiles, int ntiles, const SlotDev* slots, con
         break;
       case OBJ_DISSIPATION:
         hipLaunchKernelGGL((k_batch<true, OBJ_DISSIPATION>), grid, block, 0, s, tiles, slots, base, q, xper, xrem);
+        break;
+      case OBJ_HEATGEN:
+        hipLaunchKernelGGL((k_batch<true, OBJ_HEATGEN>), grid, block, 0, s, tiles, slots, base, q, xper, xrem);
         break;
       default:
         hipLaunchKernelGGL((k_batch<true, OBJ_HEATSINK>), grid, block, 0, s, tiles, slots, base, q, xper, xrem);

@@ -24,7 +24,7 @@ LBM_EINVAL, LBM_ESTATE, LBM_ENOMEM, LBM_EDEVICE, LBM_EDIVERGED = -1, -2, -3, -4,
 STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "EINVAL", -2: "ESTATE", -3: "ENOMEM",
                 -4: "EDEVICE", -5: "EDIVERGED"}
 
-LBM_OBJ_PRESSURE_DROP, LBM_OBJ_DISSIPATION, LBM_OBJ_HEATSINK = 0, 1, 2
+LBM_OBJ_PRESSURE_DROP, LBM_OBJ_DISSIPATION, LBM_OBJ_HEATSINK, LBM_OBJ_HEATGEN = 0, 1, 2, 3
 STATE_FLOW, STATE_THERMAL, STATE_ADJ_FLOW, STATE_ADJ_THERMAL, STATE_GNEQ = 0, 1, 2, 3, 4
 
 
@@ -32,6 +32,11 @@ class LBMError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
         self.code = code
+
+
+class lbm_levelset_info_t(ctypes.Structure):
+    _fields_ = [("lambda_", c_double), ("volume", c_double), ("G", c_double),
+                ("scale", c_double)]
 
 
 class lbm_desc_t(ctypes.Structure):
@@ -42,7 +47,8 @@ class lbm_desc_t(ctypes.Structure):
                 ("k_ratio", c_double), ("q_ramp", c_double), ("q_w", c_double),
                 ("T_in", c_double), ("w_dp", c_double),
                 ("max_steps", c_int32), ("check_every", c_int32), ("tol", c_double),
-                ("adjoint_kind", c_int32), ("reserved", c_int32)]
+                ("adjoint_kind", c_int32), ("symmetric", c_int32 * 3),
+                ("inlet_rho", c_double), ("beta_max", c_double)]
 
 
 class lbm_info_t(ctypes.Structure):
@@ -73,7 +79,8 @@ LBM_BATCH_POLICY_ALL, LBM_BATCH_POLICY_SRW, LBM_BATCH_POLICY_OVERLAP = 0, 1, 2
 
 EXPORTS = ("lbm_problem_create", "lbm_workspace_bytes", "lbm_bind_workspace", "lbm_forward_solve",
            "lbm_forward_continue", "lbm_adjoint_solve", "lbm_adjoint_continue",
-           "lbm_thermal_resolve", "lbm_sensitivity",
+           "lbm_thermal_resolve", "lbm_sensitivity", "lbm_forward_resume",
+           "lbm_adjoint_resume", "lbm_levelset_update",
            "lbm_copy_state", "lbm_set_kernel_timing", "lbm_kernel_timing", "lbm_lattice",
            "lbm_problem_destroy", "lbm_last_error", "lbm_batch_create", "lbm_batch_table_bytes",
            "lbm_batch_bind_arena", "lbm_batch_set_policy", "lbm_batch_submit", "lbm_batch_step", "lbm_batch_poll",
@@ -106,6 +113,13 @@ def load_library(path: str = LIB_PATH):
     lib.lbm_adjoint_solve.restype = c_int
     lib.lbm_adjoint_continue.argtypes = [P, P, P, P, P, c_int32, POINTER(lbm_info_t), P]
     lib.lbm_adjoint_continue.restype = c_int
+    lib.lbm_forward_resume.argtypes = [P, P, P, P, P, POINTER(lbm_info_t), P]
+    lib.lbm_forward_resume.restype = c_int
+    lib.lbm_adjoint_resume.argtypes = [P, P, P, P, P, POINTER(lbm_info_t), P]
+    lib.lbm_adjoint_resume.restype = c_int
+    lib.lbm_levelset_update.argtypes = [P, P, P, P, P, c_double, c_double, c_double,
+                                        POINTER(lbm_levelset_info_t), P]
+    lib.lbm_levelset_update.restype = c_int
     lib.lbm_thermal_resolve.argtypes = [P, P, P, P, POINTER(lbm_info_t), P]
     lib.lbm_thermal_resolve.restype = c_int
     lib.lbm_sensitivity.argtypes = [P, P, P, P, P, P, POINTER(c_double), P]
@@ -211,6 +225,28 @@ def lbm_adjoint_continue(p, gamma, drho, u, T, nsteps, stream=None) -> lbm_info_
     _check(load_library().lbm_adjoint_continue(p, _ptr(gamma), _ptr(drho), _ptr(u), _ptr(T),
                                                int(nsteps), byref(info), _stream(stream)))
     return info
+
+
+def lbm_forward_resume(p, gamma, drho, u, T, stream=None) -> lbm_info_t:
+    info = lbm_info_t()
+    _check(load_library().lbm_forward_resume(p, _ptr(gamma), _ptr(drho), _ptr(u), _ptr(T),
+                                             byref(info), _stream(stream)))
+    return info
+
+
+def lbm_adjoint_resume(p, gamma, drho, u, T, stream=None) -> lbm_info_t:
+    info = lbm_info_t()
+    _check(load_library().lbm_adjoint_resume(p, _ptr(gamma), _ptr(drho), _ptr(u), _ptr(T),
+                                             byref(info), _stream(stream)))
+    return info
+
+
+def lbm_levelset_update(p, phi, phi_out, dJ, gamma, K, sigma, vmax, stream=None) -> dict:
+    info = lbm_levelset_info_t()
+    _check(load_library().lbm_levelset_update(p, _ptr(phi), _ptr(phi_out), _ptr(dJ), _ptr(gamma),
+                                              float(K), float(sigma), float(vmax), byref(info),
+                                              _stream(stream)))
+    return {"lambda": info.lambda_, "volume": info.volume, "G": info.G, "scale": info.scale}
 
 
 def lbm_thermal_resolve(p, gamma, u, T, stream=None) -> lbm_info_t:
@@ -332,6 +368,11 @@ def make_desc(spec) -> lbm_desc_t:
     d.max_steps = int(spec.max_steps)
     d.check_every = int(spec.check_every)
     d.adjoint_kind = int(getattr(spec, "adjoint_kind", LBM_ADJOINT_DISCRETE))
+    sym = getattr(spec, "symmetric", (False, False, False))
+    for a in range(3):
+        d.symmetric[a] = int(bool(sym[a]))
+    d.inlet_rho = float(getattr(spec, "inlet_rho", 0.0))
+    d.beta_max = float(getattr(spec, "beta_max", 0.0))
     return d
 
 
@@ -400,6 +441,23 @@ class Problem:
             self._gamma = g
             self.adj_info = lbm_adjoint_solve(self.h, g, None, self.u if u is None else u,
                                               self.T if T is None else T, stream).as_dict()
+        return self.adj_info
+
+    def forward_resume(self, gamma=None, stream=None) -> dict:
+        """Warm restart of the forward solve (to the residual criterion),
+        with a new design field if given."""
+        with torch.cuda.device(self.device):
+            if gamma is not None:
+                self._gamma = self.gamma_tensor(gamma)
+            self.fwd_info = lbm_forward_resume(self.h, self._gamma, self.drho, self.u, self.T,
+                                               stream).as_dict()
+        return self.fwd_info
+
+    def adjoint_resume(self, stream=None) -> dict:
+        """Warm restart of the adjoint solve about the current forward state."""
+        with torch.cuda.device(self.device):
+            self.adj_info = lbm_adjoint_resume(self.h, self._gamma, None, self.u, self.T,
+                                               stream).as_dict()
         return self.adj_info
 
     def adjoint_continue(self, nsteps: int, stream=None) -> dict:

@@ -36,10 +36,11 @@ def test_every_declared_symbol_is_exported(lbm):
 
 
 def test_struct_layout_matches_header(lbm):
-    # doubles start at offset 32 and the struct is 152 bytes (see the header)
+    # doubles start at offset 32 and the struct is 176 bytes (see the header)
     assert lbm.lbm_desc_t.tau.offset == 32
     assert lbm.lbm_desc_t.adjoint_kind.offset == 144
-    assert ctypes.sizeof(lbm.lbm_desc_t) == 152
+    assert lbm.lbm_desc_t.inlet_rho.offset == 160
+    assert ctypes.sizeof(lbm.lbm_desc_t) == 176
     assert ctypes.sizeof(lbm.lbm_info_t) == 48
 
 
@@ -116,7 +117,7 @@ def test_unbound_problem_reports_state_error(lbm):
 
 def test_batch_parameters_are_validated(lbm):
     """Engine creation and policy checks are host-only."""
-    for bad in [(2, 2, 8, 250), (1, 3, 8, 250), (1, 2, 0, 250), (1, 2, 8, 0)]:
+    for bad in [(2, 2, 8, 250), (1, 4, 8, 250), (1, 2, 0, 250), (1, 2, 8, 0)]:
         with pytest.raises(lbm.LBMError) as e:
             _raw_batch_create(lbm, *bad)
         assert e.value.code == lbm.LBM_EINVAL
@@ -140,3 +141,37 @@ def _raw_batch_create(lbm, thermal, objective, slots, quantum):
     if rc:
         raise lbm.LBMError(rc, lbm.lbm_last_error())
     return h
+
+
+def test_paper_heat_sink_descriptor_accepted(lbm):
+    w = W.tiny_paper_heat_sink()
+    h = _create(lbm, w)
+    assert lbm.lbm_workspace_bytes(h) > 0
+    lbm.lbm_problem_destroy(h)
+
+
+@pytest.mark.parametrize("bad", ["sym_layer_incomplete", "sym_inside", "heatgen_no_beta",
+                                 "beta_no_thermal", "sym_and_periodic", "negative_inlet_rho"])
+def test_invalid_symmetry_and_heat_generation(lbm, bad):
+    w = W.tiny_paper_heat_sink()
+    kw = {}
+    if bad == "sym_layer_incomplete":
+        m = w.mask.copy()
+        m[2, w.ny - 1, 5] = W.WALL
+        kw["mask"] = m
+    elif bad == "sym_inside":
+        m = w.mask.copy()
+        m[2, 2, 5] = W.SYM
+        kw["mask"] = m
+    elif bad == "heatgen_no_beta":
+        kw["beta_max"] = 0.0
+    elif bad == "beta_no_thermal":
+        kw["thermal"] = False
+        kw["objective"] = W.OBJ_PRESSURE_DROP
+    elif bad == "sym_and_periodic":
+        kw["periodic"] = (False, True, False)
+    elif bad == "negative_inlet_rho":
+        kw["inlet_rho"] = -1.0
+    with pytest.raises(lbm.LBMError) as e:
+        _create(lbm, w, **kw)
+    assert e.value.code == lbm.LBM_EINVAL

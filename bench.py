@@ -93,6 +93,8 @@ def parse():
     ap.add_argument("--stability", action="store_true",
                     help="run the adjoint stability sweep (3D pipe bend, discrete vs continuous "
                          "adjoint) and print its JSON object")
+    ap.add_argument("--stability-dim", type=int, default=3, choices=[2, 3],
+                    help="pipe bend of the stability sweep: 3D on 32^3 or 2D (D2Q9) on 64^2")
     ap.add_argument("--stability-steps", type=int, default=1000000,
                     help="step cap of each forward and adjoint solve in the stability sweep")
     ap.add_argument("--optimize", type=int, default=0,
@@ -262,24 +264,27 @@ def serving_leg(n, rate, policy="srw", fill=512):
             "batch_launches": st["launches"]}
 
 
-def stability_leg(steps):
+def stability_leg(steps, dim=3):
     """Largest stable inlet speed per relaxation time for the primal, discrete
-    adjoint and continuous adjoint solves (Sec. 3.1) on the 3D pipe bend
-    32^3, every point a request of the batch engine."""
+    adjoint and continuous adjoint solves (Sec. 3.1) on the pipe bend (3D on
+    32^3 or 2D on 64^2), every point a request of the batch engine."""
     import torch
     from paper_2501_02161_amd import stability
 
     torch.cuda.set_device(0)
     taus = (0.52, 0.55, 0.6, 0.7, 0.8, 1.0)
     speeds = (0.02, 0.04, 0.06, 0.08, 0.1, 0.12, 0.15, 0.2, 0.25, 0.3, 0.35, 0.4, 0.5)
+    n = 32 if dim == 3 else 64
     t0 = time.perf_counter()
     points, limits = stability.sweep(
-        taus, speeds, n=32, max_steps=steps,
+        taus, speeds, n=n, max_steps=steps, dim=dim,
         log=lambda m: print(f"[stability] {m}", file=sys.stderr, flush=True))
     el = time.perf_counter() - t0
     table = {f"{tau:g}": {k: v for k, v in lim.items()} for tau, lim in limits.items()}
     pts = {f"tau {t:g} u {u:g} {'cont' if k else 'disc'}": list(v) for (t, u, k), v in points.items()}
-    return {"workload": "pipe_bend_3d_32^3 (port 5, pressure drop)", "steps_cap": steps,
+    wl = "pipe_bend_3d_32^3 (port 5, pressure drop)" if dim == 3 else \
+        "pipe_bend_2d_64x64 (D2Q9, inlet rows 8-23, outlet columns 40-55, pressure drop)"
+    return {"workload": wl, "steps_cap": steps,
             "taus": list(taus), "speeds": list(speeds), "max_stable_speed": table,
             "seconds": round(el, 1), "points": pts}
 
@@ -320,7 +325,8 @@ def main():
         copy_bandwidth()
         return
     if args.stability:
-        print(json.dumps({"stability": stability_leg(args.stability_steps)}), flush=True)
+        print(json.dumps({"stability": stability_leg(args.stability_steps, args.stability_dim)}),
+              flush=True)
         return
     if args.optimize > 0:
         print(json.dumps({"optimize": optimize_leg(args)}), flush=True)

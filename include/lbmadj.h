@@ -7,7 +7,10 @@
  * One problem = one lattice: a D3Q19 BGK flow lattice with the incompressible
  * equilibrium of Eq. (4), extended by the design field as in Eq. (12), and
  * optionally a coupled D3Q7 BGK advection-diffusion lattice for temperature
- * (Eq. 71 without volumetric source).  Three calls make the hot path:
+ * (Eq. 71, with the volumetric source of Eq. 69 when beta_max > 0).  A grid
+ * with nz == 1 is a 2D problem on the D2Q9 lattice of Eq. (5) (flow only),
+ * for which Eqs. (7), (8) and (58)-(60) are the printed special cases of the
+ * generic port rules.  Three calls make the hot path:
  *
  *   lbm_forward_solve   the steady forward sweep: collision (Eq. 36),
  *                       streaming (Eq. 37), boundary conditions (Eqs. 7-9)
@@ -138,7 +141,9 @@ extern "C" {
 #define LBM_ADJOINT_CONTINUOUS 1
 
 typedef struct lbm_desc {
-  int32_t nx, ny, nz;      /* grid, each >= 3 (nz >= 3 too: D3Q19 only)      */
+  int32_t nx, ny, nz;      /* grid: nx, ny >= 3; nz >= 3 (D3Q19) or nz == 1   */
+                           /* (2D: D2Q9, flow only, z not symmetric and its  */
+                           /* periodic flag ignored, port normals in x or y) */
   int32_t thermal;         /* 0: flow only; 1: coupled D3Q7 temperature       */
   int32_t periodic[3];     /* 1: periodic streaming along x / y / z           */
   int32_t objective;       /* LBM_OBJ_*                                       */
@@ -244,16 +249,24 @@ int lbm_adjoint_resume(lbm_problem_t* p, const float* gamma, const float* drho, 
 
 /* Level-set design update of the topology-optimisation loop (Sec. 2.2,
  * Eqs. 13-15 and 67), on the design nodes of the problem:
- *   r      = J' / s + lambda - sigma lap(phi),  s = mean |J'| (design nodes)
+ *   s      = mean |J'| over the design nodes (J' = dJ, the sensitivity)
  *   lambda = exp(G) mean |J'/s - sigma lap(phi)|,  G = V - vmax   (Eq. 67)
- *   phi'   = clamp(phi - K r, -1, 1)   (explicit step of Eq. 14)
+ *   phi'   solves (I - K sigma lap) phi' = phi - K (J'/s + lambda), the
+ *          step of Eq. (14) with the diffusion term taken at the new level
+ *          set, then phi' = clamp(phi', -1, 1) (Eq. 13)
  *   gamma  = 1 where phi' >= 0, else 0 (Eq. 15)
- * V is the fluid fraction (phi >= 0) of the design domain before the step;
- * lap is the 7-point Laplacian with no flux to non-design nodes.  phi,
- * phi_out, dJ (the sensitivity J'), gamma: device [N] float; phi_out must
- * not alias phi; non-design entries of phi_out copy phi, of gamma are left
- * unchanged.  Synchronises the stream (two small reductions).  LBM_EINVAL
- * for K <= 0, sigma < 0, vmax outside (0, 1], or no design nodes. */
+ * V is the fluid fraction (phi >= 0) of the design domain before the step.
+ * lap is the 7-point Laplacian (5-point in 2D) in lattice units; a
+ * neighbour that is not a design node enters with the fixed phase of its
+ * node (+1 for FLUID, INLET and OUTLET, -1 for WALL and HEATED); one outside
+ * the box or on a SYM layer counts as the node itself.  sigma is in lattice
+ * units (a dimensionless coefficient on a length L is sigma L^2 here).  The
+ * implicit system is solved by red-black Gauss-Seidel sweeps, as many as
+ * take the error below 1e-8 of the starting guess's.  phi, phi_out, dJ,
+ * gamma: device [N] float; phi_out must not alias phi; non-design entries
+ * of phi_out copy phi, of gamma are left unchanged.  Synchronises the
+ * stream (two small reductions).  LBM_EINVAL for K <= 0, sigma < 0, vmax
+ * outside (0, 1], K sigma too large for 100000 sweeps, or no design nodes. */
 typedef struct lbm_levelset_info {
   double lambda;           /* Eq. (67)                                        */
   double volume;           /* fluid fraction of the design domain (before)    */
@@ -277,8 +290,8 @@ int lbm_sensitivity(lbm_problem_t* p, const float* gamma, const float* drho, con
                     const float* T, float* dJdgamma, double* J, void* stream);
 
 /* Copy a workspace state to device memory dst: which 0 = forward flow
- * populations (19 x N), 1 = forward thermal (7 x N), 2 = adjoint flow
- * (19 x N), 3 = adjoint thermal (7 x N), 4 = thermal non-equilibrium
+ * populations (Q x N, Q = 19, or 9 on a 2D lattice), 1 = forward thermal
+ * (7 x N), 2 = adjoint flow (Q x N), 3 = adjoint thermal (7 x N), 4 = thermal non-equilibrium
  * populations of the last forward state (7 x N).  Populations are
  * population-major [q][z][y][x] and stored shifted: f_i - w_i rho0 (forward
  * flow), g_i - w_i T_in (forward thermal); the forward state is the
@@ -299,7 +312,8 @@ int lbm_set_kernel_timing(lbm_problem_t* p, int32_t enable);
 int lbm_kernel_timing(lbm_problem_t* p, double* ms, int64_t* launches, int32_t reset);
 
 /* Direction table of the library: which 0 = D3Q19 (19 entries), 1 = D3Q7
- * (7 entries); e receives 3 ints per direction, w the weight. */
+ * (7 entries), 2 = D2Q9 (9 entries, e_z = 0); e receives 3 ints per
+ * direction, w the weight. */
 int lbm_lattice(int32_t which, int32_t* e, double* w);
 
 /* ---------------------------------------------------------------------------

@@ -310,7 +310,7 @@ int bind_slot(lbm_batch* b, Slot& s, const Request& r, hipStream_t st) {
   HIPCHK(hipMemcpyAsync(p->uin, uin, p->Np * sizeof(float), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(p->flags, fl, p->Np, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(s.gamma, gam, (size_t)p->N * sizeof(float), hipMemcpyHostToDevice, st));
-  HIPCHK(launch_fill(p->f[0], (size_t)19 * p->Np, st));
+  HIPCHK(launch_fill(p->f[0], (size_t)qf_of(p) * p->Np, st));
   if (th) {
     HIPCHK(launch_fill(p->g[0], (size_t)7 * p->Np, st));
     HIPCHK(launch_heat_init(p->g[0], s.gamma, p->flags, p->kp, st));
@@ -464,7 +464,7 @@ int after_quantum(lbm_batch* b, int i, Lane& ln) {
       if (p->d.objective == LBM_OBJ_HEATSINK) J += sums[3] / p->n_layer;
     }
     s.J = J;
-    HIPCHK(launch_fill(p->a[0], (size_t)19 * p->Np, st));
+    HIPCHK(launch_fill(p->a[0], (size_t)qf_of(p) * p->Np, st));
     if (th) HIPCHK(launch_fill(p->b[0], (size_t)7 * p->Np, st));
     s.phase = PH_ADJOINT;
     s.steps = 0;
@@ -476,7 +476,7 @@ int after_quantum(lbm_batch* b, int i, Lane& ln) {
     // final adjoint state is buffer (done & 1)
     p->acur = done & 1;
     SensArgs A{};
-    A.ain = p->a[p->acur];
+    A.ain = p->a[sens_buffer(p)];
     A.bin = p->b[p->acur];
     A.flags = p->flags;
     A.gamma = s.gamma;
@@ -831,8 +831,9 @@ int lbm_batch_create(int32_t thermal, int32_t objective, int32_t max_slots, int3
 
 size_t lbm_batch_table_bytes(const lbm_batch_t* b, size_t arena_bytes) {
   if (!b) return 0;
-  // one tile per 256 nodes; every node needs at least 4 x 19 floats of workspace
-  const size_t max_tiles = arena_bytes / (4 * 19 * 4 * kBlock) + b->max_slots;
+  // one tile per 256 nodes; every node needs at least 4 x 9 floats of
+  // workspace (two forward and two adjoint D2Q9 buffers)
+  const size_t max_tiles = arena_bytes / (4 * 9 * 4 * kBlock) + b->max_slots;
   return kLanes * lane_table_bytes(b->max_slots, (int)max_tiles) + 256;
 }
 
@@ -841,7 +842,7 @@ int lbm_batch_bind_arena(lbm_batch_t* b, void* device_ptr, size_t bytes) {
   if (!b || !device_ptr) return fail(LBM_EINVAL, "batch or arena is NULL");
   for (const Slot& s : b->slots)
     if (s.used) return fail(LBM_ESTATE, "cannot rebind while requests are resident");
-  const size_t max_tiles = bytes / (4 * 19 * 4 * kBlock) + b->max_slots;
+  const size_t max_tiles = bytes / (4 * 9 * 4 * kBlock) + b->max_slots;
   if (max_tiles > (size_t)INT32_MAX) return fail(LBM_EINVAL, "arena too large");
   const size_t tb = lbm_batch_table_bytes(b, bytes);
   if (bytes <= tb + 256) return fail(LBM_EINVAL, "arena too small");

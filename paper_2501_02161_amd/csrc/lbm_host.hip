@@ -29,11 +29,12 @@ std::string& last_error() {
 namespace lbmadj {
 
 bool thermal_of(const lbm_problem* p) { return p->d.thermal != 0; }
+int qf_of(const lbm_problem* p) { return p->d.nz == 1 ? 9 : 19; }
 
 Layout layout_of(const lbm_problem* p) {
   Layout L{};
   size_t off = 0;
-  const size_t pf = (size_t)19 * p->Np * sizeof(float), pg = (size_t)7 * p->Np * sizeof(float);
+  const size_t pf = (size_t)qf_of(p) * p->Np * sizeof(float), pg = (size_t)7 * p->Np * sizeof(float);
   const bool th = thermal_of(p);
   auto take = [&](size_t bytes) {
     const size_t o = off;
@@ -55,7 +56,12 @@ Layout layout_of(const lbm_problem* p) {
 }
 
 int validate_and_setup(lbm_problem* p, const lbm_desc_t& d, const uint8_t* mask) {
-  if (d.nx < 3 || d.ny < 3 || d.nz < 3) return fail(LBM_EINVAL, "nx, ny, nz must be >= 3");
+  if (d.nx < 3 || d.ny < 3 || (d.nz < 3 && d.nz != 1))
+    return fail(LBM_EINVAL, "nx, ny must be >= 3 and nz >= 3 (D3Q19) or nz == 1 (D2Q9)");
+  const bool two_d = d.nz == 1;
+  if (two_d && d.thermal) return fail(LBM_EINVAL, "the 2D lattice (nz == 1) is flow only");
+  if (two_d && d.symmetric[2])
+    return fail(LBM_EINVAL, "the 2D lattice (nz == 1) has no z axis to be symmetric");
   const long long N = (long long)d.nx * d.ny * d.nz;
   if (N > (1LL << 31) / 32) return fail(LBM_EINVAL, "grid too large for 32-bit indexing");
   if (!(d.tau > 0.5)) return fail(LBM_EINVAL, "tau must be > 1/2");
@@ -119,11 +125,12 @@ int validate_and_setup(lbm_problem* p, const lbm_desc_t& d, const uint8_t* mask)
                                   std::to_string(n) + ")");
     bool on_face[3];
     for (int a = 0; a < 3; ++a) on_face[a] = !d.periodic[a] && (c[a] == 0 || c[a] == lim[a] - 1);
+    if (two_d) on_face[2] = false;  // the single layer of a 2D lattice has no z faces
     const bool boundary_kind = kind >= K_INLET;
     if ((on_face[0] || on_face[1] || on_face[2]) && !boundary_kind)
       return fail(LBM_EINVAL, "interior node on a non-periodic face at node " + std::to_string(n));
     if (kind == K_INLET || kind == K_OUTLET || kind == K_HEATED) {
-      if (nc > 5) return fail(LBM_EINVAL, "bad normal code at node " + std::to_string(n));
+      if (nc > (two_d ? 3 : 5)) return fail(LBM_EINVAL, "bad normal code at node " + std::to_string(n));
     } else {
       p->flags_host[n] = (uint8_t)kind;  // normal bits are meaningless here
     }
@@ -238,6 +245,7 @@ int validate_and_setup(lbm_problem* p, const lbm_desc_t& d, const uint8_t* mask)
   k.drho_in = pin ? (float)(d.inlet_rho - d.rho0) : 0.0f;
   k.beta = (float)d.beta_max;
   k.heatgen = d.objective == LBM_OBJ_HEATGEN ? 1 : 0;
+  k.q = d.nz == 1 ? 9 : 19;
   return LBM_OK;
 }
 
@@ -509,6 +517,16 @@ int check_bound(const lbm_problem* p) {
   return LBM_OK;
 }
 
+// Adjoint buffer the sensitivity contracts.  The step kernels store the
+// post-collision state y_k of step k; the contraction pulls it (S^T).  For the
+// discrete adjoint that is the state Eq. (66) takes.  The continuous variant
+// steps collision -> streaming -> boundary, so its complete state after step
+// k is the post-boundary f*_k, which on design nodes (never ports) equals the
+// pulled state of step k - 1: the other buffer.
+int sens_buffer(const lbm_problem* p) {
+  return p->d.adjoint_kind == LBM_ADJOINT_CONTINUOUS ? 1 - p->acur : p->acur;
+}
+
 }  // namespace lbmadj
 
 extern "C" {
@@ -587,7 +605,7 @@ int lbm_forward_solve(lbm_problem_t* p, const float* gamma, float* drho, float* 
   hipStream_t s = (hipStream_t)stream;
   p->fwd_done = p->adj_done = p->have_gneq = false;
   p->fcur = 0;
-  HIPCHK(launch_fill(p->f[0], (size_t)19 * p->Np, s));
+  HIPCHK(launch_fill(p->f[0], (size_t)qf_of(p) * p->Np, s));
   if (thermal_of(p)) {
     HIPCHK(launch_fill(p->g[0], (size_t)7 * p->Np, s));
     HIPCHK(launch_heat_init(p->g[0], gamma, p->flags, p->kp, s));
@@ -622,7 +640,7 @@ int lbm_adjoint_solve(lbm_problem_t* p, const float* gamma, const float* drho, c
   p->acur = 0;
   if (p->d.objective == LBM_OBJ_DISSIPATION)
     HIPCHK(launch_dissipation_source(u, gamma, p->flags, p->G, p->kp, s));
-  HIPCHK(launch_fill(p->a[0], (size_t)19 * p->Np, s));
+  HIPCHK(launch_fill(p->a[0], (size_t)qf_of(p) * p->Np, s));
   if (thermal_of(p)) HIPCHK(launch_fill(p->b[0], (size_t)7 * p->Np, s));
   return run_adjoint(p, gamma, u, T, p->d.max_steps, p->d.check_every, p->d.tol, s, info);
 }
@@ -692,8 +710,21 @@ int lbm_levelset_update(lbm_problem_t* p, const float* phi, float* phi_out, cons
   rc = read_sums(p, 1, s);
   if (rc) return rc;
   const double lambda = std::exp(G) * p->pinned[0] / p->n_design;  // Eq. (67)
-  HIPCHK(launch_levelset_update(phi, phi_out, dJ, p->flags, gamma, inv_scale, (float)sigma, (float)K,
-                                (float)lambda, p->kp, s));
+  // Semi-implicit step (I - K sigma lap) phi_new = phi - K (J'/scale + lambda),
+  // solved by red-black Gauss-Seidel.  The Jacobi iteration of this diagonally
+  // dominant system contracts by rho = 6a / (1 + 6a) (a = K sigma) per sweep;
+  // red-black ordering squares that, so the sweep count brings the error
+  // below 1e-8 of the starting guess's.
+  const double a = K * sigma;
+  int sweeps = 0;
+  if (a > 0.0) {
+    const double rho = 6.0 * a / (1.0 + 6.0 * a);
+    const double n_sw = std::ceil(std::log(1e-8) / (2.0 * std::log(rho))) + 8.0;
+    if (!(n_sw <= 100000.0)) return fail(LBM_EINVAL, "K * sigma too large for the level-set solve");
+    sweeps = (int)n_sw;
+  }
+  HIPCHK(launch_levelset_update(phi, phi_out, dJ, p->flags, gamma, inv_scale, (float)K, (float)lambda,
+                                (float)a, sweeps, p->kp, s));
   if (info) {
     info->lambda = lambda;
     info->volume = volume;
@@ -730,7 +761,7 @@ int lbm_sensitivity(lbm_problem_t* p, const float* gamma, const float* drho, con
   DeviceGuard guard(p->dev);
   hipStream_t s = (hipStream_t)stream;
   SensArgs A{};
-  A.ain = p->a[p->acur];
+  A.ain = p->a[sens_buffer(p)];
   A.bin = p->b[p->acur];
   A.flags = p->flags;
   A.gamma = gamma;
@@ -756,9 +787,9 @@ int lbm_copy_state(const lbm_problem_t* p, int32_t which, float* dst, void* stre
   const float* src = nullptr;
   int q = 0;
   switch (which) {
-    case 0: src = p->f[p->fcur]; q = 19; break;
+    case 0: src = p->f[p->fcur]; q = qf_of(p); break;
     case 1: src = p->g[p->fcur]; q = 7; break;
-    case 2: src = p->a[p->acur]; q = 19; break;
+    case 2: src = p->a[p->acur]; q = qf_of(p); break;
     case 3: src = p->b[p->acur]; q = 7; break;
     case 4: src = p->gneq; q = 7; break;
     default: return fail(LBM_EINVAL, "which must be 0..4");
@@ -800,7 +831,7 @@ int lbm_kernel_timing(lbm_problem_t* p, double* ms, int64_t* launches, int32_t r
 }
 
 int lbm_lattice(int32_t which, int32_t* e, double* w) {
-  if (!e || !w || (which != 0 && which != 1)) return fail(LBM_EINVAL, "bad arguments");
+  if (!e || !w || which < 0 || which > 2) return fail(LBM_EINVAL, "bad arguments");
   lattice_table(which, e, w);
   return LBM_OK;
 }

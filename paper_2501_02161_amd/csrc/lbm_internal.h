@@ -51,6 +51,7 @@ struct KParams {
   float drho_in;
   float beta;                    // heat generation beta_max (0: none)
   int heatgen;                   // objective J = -sum beta (1 - T): forward partial 3
+  int q;                         // flow lattice: 19 (D3Q19) or 9 (D2Q9, nz = 1)
 };
 
 struct FwdArgs {
@@ -137,9 +138,13 @@ hipError_t launch_levelset_stats(const float* phi, const float* dJ, const uint8_
 hipError_t launch_levelset_lambda(const float* phi, const float* dJ, const uint8_t* flags,
                                   float inv_scale, float sigma, double* partials, const KParams& P,
                                   hipStream_t s);
+// Semi-implicit step: r = phi - K (J'/scale + lambda) into phi_out, `sweeps`
+// red-black Gauss-Seidel sweeps of (I - a lap) x = r in place (a = K sigma),
+// then the clamp and gamma = (phi_out >= 0).
 hipError_t launch_levelset_update(const float* phi, float* phi_out, const float* dJ,
-                                  const uint8_t* flags, float* gamma, float inv_scale, float sigma,
-                                  float K, float lambda, const KParams& P, hipStream_t s);
+                                  const uint8_t* flags, float* gamma, float inv_scale, float K,
+                                  float lambda, float a, int sweeps, const KParams& P,
+                                  hipStream_t s);
 // Adds the first collision's heat source to a zero-filled thermal state
 // (no-op without heat generation).
 hipError_t launch_heat_init(float* g, const float* gamma, const uint8_t* flags, const KParams& P,
@@ -246,6 +251,8 @@ struct Layout {
 };
 Layout layout_of(const lbm_problem* p);
 bool thermal_of(const lbm_problem* p);
+int qf_of(const lbm_problem* p);  // flow directions: 19, or 9 for a 2D lattice
+int sens_buffer(const lbm_problem* p);  // adjoint buffer the sensitivity contracts
 int validate_and_setup(lbm_problem* p, const lbm_desc_t& d, const uint8_t* mask);
 FwdArgs fwd_args(lbm_problem* p, const float* gamma, float* drho, float* u, float* T);
 AdjArgs adj_args(lbm_problem* p, const float* gamma, const float* u, const float* T);

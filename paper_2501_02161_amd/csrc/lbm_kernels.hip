@@ -41,6 +41,17 @@ struct Q19 {
                                   1.f / 36.f, 1.f / 36.f, 1.f / 36.f, 1.f / 36.f, 1.f / 36.f,
                                   1.f / 36.f, 1.f / 36.f, 1.f / 36.f, 1.f / 36.f};
 };
+// D2Q9 (the 2D flow lattice, nz = 1): rest 4/9, axes 1/9, diagonals 1/36, in
+// the same axis-first order with ez = 0.
+struct Q9 {
+  static constexpr int Q = 9;
+  static constexpr int ex[9] = {0, 1, -1, 0, 0, 1, -1, 1, -1};
+  static constexpr int ey[9] = {0, 0, 0, 1, -1, 1, -1, -1, 1};
+  static constexpr int ez[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  static constexpr int opp[9] = {0, 2, 1, 4, 3, 6, 5, 8, 7};
+  static constexpr float w[9] = {4.f / 9.f,  1.f / 9.f,  1.f / 9.f,  1.f / 9.f, 1.f / 9.f,
+                                 1.f / 36.f, 1.f / 36.f, 1.f / 36.f, 1.f / 36.f};
+};
 struct Q7 {
   static constexpr int Q = 7;
   static constexpr int ex[7] = {0, 1, -1, 0, 0, 0, 0};
@@ -220,31 +231,32 @@ __device__ __forceinline__ Normal normal_of(int c) {
 // Generic Zou-He rule on shifted populations (f - w rho0).  Velocity inlet:
 // prescribed rho0 u_n = jn_in.  Pressure outlet / pressure inlet:
 // rho0 u_n = rho_b - sum_T f - 2 sum_O f, i.e. drho_b - (sum_T h + 2 sum_O h).
-__device__ __forceinline__ void zou_he(float (&h)[19], Normal nv, bool inlet, float jn_in,
+template <class L>
+__device__ __forceinline__ void zou_he(float (&h)[L::Q], Normal nv, bool inlet, float jn_in,
                                        float drho_b = 0.0f) {
   float sT = 0.f, sO = 0.f, Nx = 0.f, Ny = 0.f, Nz = 0.f;
-  sfor<19>([&](auto I) {
+  sfor<L::Q>([&](auto I) {
     constexpr int i = I;
-    const int c = Q19::ex[i] * nv.x + Q19::ey[i] * nv.y + Q19::ez[i] * nv.z;
+    const int c = L::ex[i] * nv.x + L::ey[i] * nv.y + L::ez[i] * nv.z;
     const float t = (c == 0) ? h[i] : 0.f;
     sT += t;
     sO += (c < 0) ? h[i] : 0.f;
-    if constexpr (Q19::ex[i] != 0) Nx += float(Q19::ex[i]) * t;
-    if constexpr (Q19::ey[i] != 0) Ny += float(Q19::ey[i]) * t;
-    if constexpr (Q19::ez[i] != 0) Nz += float(Q19::ez[i]) * t;
+    if constexpr (L::ex[i] != 0) Nx += float(L::ex[i]) * t;
+    if constexpr (L::ey[i] != 0) Ny += float(L::ey[i]) * t;
+    if constexpr (L::ez[i] != 0) Nz += float(L::ez[i]) * t;
   });
   const float jn = inlet ? jn_in : drho_b - (sT + 2.0f * sO);
-  float o[19];
-  sfor<19>([&](auto I) {
+  float o[L::Q];
+  sfor<L::Q>([&](auto I) {
     constexpr int i = I;
-    const int c = Q19::ex[i] * nv.x + Q19::ey[i] * nv.y + Q19::ez[i] * nv.z;
-    float v = h[Q19::opp[i]] + (6.0f * Q19::w[i]) * jn;
-    if constexpr (Q19::ex[i] != 0) v -= 0.5f * float(Q19::ex[i]) * Nx;
-    if constexpr (Q19::ey[i] != 0) v -= 0.5f * float(Q19::ey[i]) * Ny;
-    if constexpr (Q19::ez[i] != 0) v -= 0.5f * float(Q19::ez[i]) * Nz;
+    const int c = L::ex[i] * nv.x + L::ey[i] * nv.y + L::ez[i] * nv.z;
+    float v = h[L::opp[i]] + (6.0f * L::w[i]) * jn;
+    if constexpr (L::ex[i] != 0) v -= 0.5f * float(L::ex[i]) * Nx;
+    if constexpr (L::ey[i] != 0) v -= 0.5f * float(L::ey[i]) * Ny;
+    if constexpr (L::ez[i] != 0) v -= 0.5f * float(L::ez[i]) * Nz;
     o[i] = (c > 0) ? v : h[i];
   });
-  sfor<19>([&](auto I) { h[I] = o[I]; });
+  sfor<L::Q>([&](auto I) { h[I] = o[I]; });
 }
 
 // Transpose of the rule above (Eq. 54 at a port; Eqs. 59, 60 in 2D), in place
@@ -260,47 +272,49 @@ __device__ __forceinline__ void zou_he(float (&h)[19], Normal nv, bool inlet, fl
 //                                                  the objective's weight)
 // which zeroes the coefficient of delta f_j in the boundary integral of
 // Eq. (21); the other directions keep their values.
-__device__ __forceinline__ void zou_he_continuous(float (&a)[19], Normal nv, bool outlet, float src) {
+template <class L>
+__device__ __forceinline__ void zou_he_continuous(float (&a)[L::Q], Normal nv, bool outlet, float src) {
   float S12 = 0.f;
-  sfor<19>([&](auto I) {
+  sfor<L::Q>([&](auto I) {
     constexpr int i = I;
-    const int cl = Q19::ex[i] * nv.x + Q19::ey[i] * nv.y + Q19::ez[i] * nv.z;
-    S12 += (cl > 0) ? (12.0f * Q19::w[i]) * a[i] : 0.f;
+    const int cl = L::ex[i] * nv.x + L::ey[i] * nv.y + L::ez[i] * nv.z;
+    S12 += (cl > 0) ? (12.0f * L::w[i]) * a[i] : 0.f;
   });
   const float sub = outlet ? S12 : src;
-  float o[19];
-  sfor<19>([&](auto I) {
+  float o[L::Q];
+  sfor<L::Q>([&](auto I) {
     constexpr int j = I;
-    const int cl = Q19::ex[j] * nv.x + Q19::ey[j] * nv.y + Q19::ez[j] * nv.z;
-    o[j] = (cl < 0) ? a[Q19::opp[j]] - sub : a[j];
+    const int cl = L::ex[j] * nv.x + L::ey[j] * nv.y + L::ez[j] * nv.z;
+    o[j] = (cl < 0) ? a[L::opp[j]] - sub : a[j];
   });
-  sfor<19>([&](auto I) { a[I] = o[I]; });
+  sfor<L::Q>([&](auto I) { a[I] = o[I]; });
 }
 
-__device__ __forceinline__ void zou_he_transpose(float (&c)[19], Normal nv, bool outlet) {
+template <class L>
+__device__ __forceinline__ void zou_he_transpose(float (&c)[L::Q], Normal nv, bool outlet) {
   float S6 = 0.f, Px = 0.f, Py = 0.f, Pz = 0.f;
-  sfor<19>([&](auto I) {
+  sfor<L::Q>([&](auto I) {
     constexpr int i = I;
-    const int cl = Q19::ex[i] * nv.x + Q19::ey[i] * nv.y + Q19::ez[i] * nv.z;
+    const int cl = L::ex[i] * nv.x + L::ey[i] * nv.y + L::ez[i] * nv.z;
     const float t = (cl > 0) ? c[i] : 0.f;
-    S6 += (6.0f * Q19::w[i]) * t;
-    if constexpr (Q19::ex[i] != 0) Px += float(Q19::ex[i]) * t;
-    if constexpr (Q19::ey[i] != 0) Py += float(Q19::ey[i]) * t;
-    if constexpr (Q19::ez[i] != 0) Pz += float(Q19::ez[i]) * t;
+    S6 += (6.0f * L::w[i]) * t;
+    if constexpr (L::ex[i] != 0) Px += float(L::ex[i]) * t;
+    if constexpr (L::ey[i] != 0) Py += float(L::ey[i]) * t;
+    if constexpr (L::ez[i] != 0) Pz += float(L::ez[i]) * t;
   });
   const float s6 = outlet ? S6 : 0.0f;
-  float o[19];
-  sfor<19>([&](auto I) {
+  float o[L::Q];
+  sfor<L::Q>([&](auto I) {
     constexpr int j = I;
-    const int cl = Q19::ex[j] * nv.x + Q19::ey[j] * nv.y + Q19::ez[j] * nv.z;
+    const int cl = L::ex[j] * nv.x + L::ey[j] * nv.y + L::ez[j] * nv.z;
     float tv = c[j] - s6;
-    if constexpr (Q19::ex[j] != 0) tv -= 0.5f * float(Q19::ex[j]) * Px;
-    if constexpr (Q19::ey[j] != 0) tv -= 0.5f * float(Q19::ey[j]) * Py;
-    if constexpr (Q19::ez[j] != 0) tv -= 0.5f * float(Q19::ez[j]) * Pz;
-    const float ov = c[j] + c[Q19::opp[j]] - 2.0f * s6;
+    if constexpr (L::ex[j] != 0) tv -= 0.5f * float(L::ex[j]) * Px;
+    if constexpr (L::ey[j] != 0) tv -= 0.5f * float(L::ey[j]) * Py;
+    if constexpr (L::ez[j] != 0) tv -= 0.5f * float(L::ez[j]) * Pz;
+    const float ov = c[j] + c[L::opp[j]] - 2.0f * s6;
     o[j] = (cl == 0) ? tv : ((cl < 0) ? ov : 0.0f);
   });
-  sfor<19>([&](auto I) { c[I] = o[I]; });
+  sfor<L::Q>([&](auto I) { c[I] = o[I]; });
 }
 
 // ---------------------------------------------------------------------------
@@ -333,7 +347,7 @@ __device__ __forceinline__ void block_reduce_store(double (&acc)[NV], double* __
 // node's velocity.  DIAG additionally writes the macroscopic fields, the
 // thermal non-equilibrium populations and the residual partial sums.
 // ---------------------------------------------------------------------------
-template <bool THERMAL, bool DIAG>
+template <class L, bool THERMAL, bool DIAG>
 __device__ __forceinline__ void forward_tile(const FwdArgs& A, int blk) {
   const KParams& P = A.P;
   const int n = blk * kBlock + threadIdx.x;
@@ -344,10 +358,10 @@ __device__ __forceinline__ void forward_tile(const FwdArgs& A, int blk) {
     const Mirror mr = mirror_of(x, y, z, P);
     const unsigned fl = A.flags[n];
     const int kind = fl & 7, nc = (fl >> 3) & 7;
-    float h[19];
-    sfor<19>([&](auto I) {
+    float h[L::Q];
+    sfor<L::Q>([&](auto I) {
       constexpr int i = I;
-      h[i] = load_pull<Q19, i, -Q19::ex[i], -Q19::ey[i], -Q19::ez[i]>(A.fin, P.Np, nb, n, mr);
+      h[i] = load_pull<L, i, -L::ex[i], -L::ey[i], -L::ez[i]>(A.fin, P.Np, nb, n, mr);
     });
     float k[7];
     if constexpr (THERMAL) {
@@ -365,9 +379,9 @@ __device__ __forceinline__ void forward_tile(const FwdArgs& A, int blk) {
     }
     if (kind >= K_WALL) {
       // full-way bounce-back, no collision (the heated wall adds q_w)
-      sfor<19>([&](auto I) {
+      sfor<L::Q>([&](auto I) {
         constexpr int i = I;
-        A.fout[(size_t)i * P.Np + n] = h[Q19::opp[i]];
+        A.fout[(size_t)i * P.Np + n] = h[L::opp[i]];
       });
       if constexpr (THERMAL) {
         float ko[7];
@@ -398,7 +412,7 @@ __device__ __forceinline__ void forward_tile(const FwdArgs& A, int blk) {
       if (kind == K_INLET || kind == K_OUTLET) {
         const bool vin = kind == K_INLET && !P.pin;   // velocity inlet
         const float jn = vin ? A.uin[n] * P.rho0 : 0.f;
-        zou_he(h, normal_of(nc), vin, jn, (kind == K_INLET) ? P.drho_in : 0.0f);
+        zou_he<L>(h, normal_of(nc), vin, jn, (kind == K_INLET) ? P.drho_in : 0.0f);
       }
       if constexpr (THERMAL) {
         if (kind == K_INLET) {
@@ -411,12 +425,12 @@ __device__ __forceinline__ void forward_tile(const FwdArgs& A, int blk) {
       }
       // moments of the post-boundary state (Eq. 6)
       float drho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
-      sfor<19>([&](auto I) {
+      sfor<L::Q>([&](auto I) {
         constexpr int i = I;
         drho += h[i];
-        if constexpr (Q19::ex[i] != 0) jx += float(Q19::ex[i]) * h[i];
-        if constexpr (Q19::ey[i] != 0) jy += float(Q19::ey[i]) * h[i];
-        if constexpr (Q19::ez[i] != 0) jz += float(Q19::ez[i]) * h[i];
+        if constexpr (L::ex[i] != 0) jx += float(L::ex[i]) * h[i];
+        if constexpr (L::ey[i] != 0) jy += float(L::ey[i]) * h[i];
+        if constexpr (L::ez[i] != 0) jz += float(L::ez[i]) * h[i];
       });
       const float inv_rho0 = 1.0f / P.rho0;
       const float ux = jx * inv_rho0, uy = jy * inv_rho0, uz = jz * inv_rho0;
@@ -425,10 +439,10 @@ __device__ __forceinline__ void forward_tile(const FwdArgs& A, int blk) {
       const float chi = (kind == K_DESIGN) ? chi_of(gam, P) : 1.0f;
       const float vx = chi * ux, vy = chi * uy, vz = chi * uz;
       const float vv = vx * vx + vy * vy + vz * vz;
-      sfor<19>([&](auto I) {
+      sfor<L::Q>([&](auto I) {
         constexpr int i = I;
-        const float eu = float(Q19::ex[i]) * vx + float(Q19::ey[i]) * vy + float(Q19::ez[i]) * vz;
-        const float heq = Q19::w[i] * (drho + P.rho0 * (3.0f * eu + 4.5f * eu * eu - 1.5f * vv));
+        const float eu = float(L::ex[i]) * vx + float(L::ey[i]) * vy + float(L::ez[i]) * vz;
+        const float heq = L::w[i] * (drho + P.rho0 * (3.0f * eu + 4.5f * eu * eu - 1.5f * vv));
         A.fout[(size_t)i * P.Np + n] = h[i] + P.omega * (heq - h[i]);
       });
       float Tabs = 0.f;
@@ -467,9 +481,9 @@ __device__ __forceinline__ void forward_tile(const FwdArgs& A, int blk) {
   if constexpr (DIAG) block_reduce_store<kRedFwd>(acc, A.partials + (size_t)blk * kRedFwd);
 }
 
-template <bool THERMAL, bool DIAG>
+template <class L, bool THERMAL, bool DIAG>
 __global__ __launch_bounds__(kBlock) void k_forward(FwdArgs A) {
-  forward_tile<THERMAL, DIAG>(A, remap_block(blockIdx.x, A.P));
+  forward_tile<L, THERMAL, DIAG>(A, remap_block(blockIdx.x, A.P));
 }
 
 // ---------------------------------------------------------------------------
@@ -483,7 +497,7 @@ __global__ __launch_bounds__(kBlock) void k_forward(FwdArgs A) {
 // the coupling from the thermal lattice adds e_i.W, W = 4 T/(tau_g rho0) sum w b e,
 // and the thermal transpose is (1 - 1/tau_g) b_i + (1/tau_g) sum w b (1 + 4 e.u).
 // ---------------------------------------------------------------------------
-template <bool THERMAL, int OBJ, bool DIAG, bool CONT = false>
+template <class L, bool THERMAL, int OBJ, bool DIAG, bool CONT = false>
 __device__ __forceinline__ void adjoint_tile(const AdjArgs& A, int blk) {
   static_assert(!(CONT && THERMAL), "the continuous variant is for the flow lattice");
   const KParams& P = A.P;
@@ -495,10 +509,10 @@ __device__ __forceinline__ void adjoint_tile(const AdjArgs& A, int blk) {
     const Mirror mr = mirror_of(x, y, z, P);
     const unsigned fl = A.flags[n];
     const int kind = fl & 7, nc = (fl >> 3) & 7;
-    float a[19];
-    sfor<19>([&](auto I) {
+    float a[L::Q];
+    sfor<L::Q>([&](auto I) {
       constexpr int i = I;
-      a[i] = load_pull<Q19, i, Q19::ex[i], Q19::ey[i], Q19::ez[i]>(A.ain, P.Np, nb, n, mr);
+      a[i] = load_pull<L, i, L::ex[i], L::ey[i], L::ez[i]>(A.ain, P.Np, nb, n, mr);
     });
     float b[7];
     if constexpr (THERMAL) {
@@ -516,11 +530,11 @@ __device__ __forceinline__ void adjoint_tile(const AdjArgs& A, int blk) {
     if constexpr (DIAG) {
       if (kind < K_WALL) {
         float mx = 0.f, my = 0.f, mz = 0.f;
-        sfor<19>([&](auto I) {
+        sfor<L::Q>([&](auto I) {
           constexpr int i = I;
-          if constexpr (Q19::ex[i] != 0) mx += float(Q19::ex[i]) * a[i];
-          if constexpr (Q19::ey[i] != 0) my += float(Q19::ey[i]) * a[i];
-          if constexpr (Q19::ez[i] != 0) mz += float(Q19::ez[i]) * a[i];
+          if constexpr (L::ex[i] != 0) mx += float(L::ex[i]) * a[i];
+          if constexpr (L::ey[i] != 0) my += float(L::ey[i]) * a[i];
+          if constexpr (L::ez[i] != 0) mz += float(L::ez[i]) * a[i];
         });
         acc[0] = sqrt((double)mx * mx + (double)my * my + (double)mz * mz);
         if constexpr (THERMAL) {
@@ -539,13 +553,13 @@ __device__ __forceinline__ void adjoint_tile(const AdjArgs& A, int blk) {
         // gives the objective no boundary term there
         const bool prs = kind == K_OUTLET || P.pin;
         const float src = (OBJ == OBJ_PRESSURE_DROP && !prs) ? 2.0f * P.c_in : 0.0f;
-        zou_he_continuous(a, normal_of(nc), prs, src);
+        zou_he_continuous<L>(a, normal_of(nc), prs, src);
       }
     }
     if (kind >= K_WALL) {
-      sfor<19>([&](auto I) {
+      sfor<L::Q>([&](auto I) {
         constexpr int i = I;
-        A.aout[(size_t)i * P.Np + n] = a[Q19::opp[i]];
+        A.aout[(size_t)i * P.Np + n] = a[L::opp[i]];
       });
       if constexpr (THERMAL) {
         sfor<7>([&](auto I) {
@@ -560,15 +574,15 @@ __device__ __forceinline__ void adjoint_tile(const AdjArgs& A, int blk) {
       const float chi = (kind == K_DESIGN) ? chi_of(gam, P) : 1.0f;
       const float vx = chi * ux, vy = chi * uy, vz = chi * uz;
       float M0 = 0.f, M1x = 0.f, M1y = 0.f, M1z = 0.f, Kx = 0.f, Ky = 0.f, Kz = 0.f;
-      sfor<19>([&](auto I) {
+      sfor<L::Q>([&](auto I) {
         constexpr int i = I;
-        const float wa = Q19::w[i] * a[i];
+        const float wa = L::w[i] * a[i];
         M0 += wa;
-        const float ev = float(Q19::ex[i]) * vx + float(Q19::ey[i]) * vy + float(Q19::ez[i]) * vz;
+        const float ev = float(L::ex[i]) * vx + float(L::ey[i]) * vy + float(L::ez[i]) * vz;
         const float wae = wa * ev;
-        if constexpr (Q19::ex[i] != 0) { M1x += float(Q19::ex[i]) * wa; Kx += float(Q19::ex[i]) * wae; }
-        if constexpr (Q19::ey[i] != 0) { M1y += float(Q19::ey[i]) * wa; Ky += float(Q19::ey[i]) * wae; }
-        if constexpr (Q19::ez[i] != 0) { M1z += float(Q19::ez[i]) * wa; Kz += float(Q19::ez[i]) * wae; }
+        if constexpr (L::ex[i] != 0) { M1x += float(L::ex[i]) * wa; Kx += float(L::ex[i]) * wae; }
+        if constexpr (L::ey[i] != 0) { M1y += float(L::ey[i]) * wa; Ky += float(L::ey[i]) * wae; }
+        if constexpr (L::ez[i] != 0) { M1z += float(L::ez[i]) * wa; Kz += float(L::ez[i]) * wae; }
       });
       const float Vx = chi * (3.0f * M1x + 9.0f * Kx - 3.0f * M0 * vx);
       const float Vy = chi * (3.0f * M1y + 9.0f * Ky - 3.0f * M0 * vy);
@@ -616,20 +630,20 @@ __device__ __forceinline__ void adjoint_tile(const AdjArgs& A, int blk) {
                   Sz = P.omega * Vz + Wz - Gz;
       const float base = P.omega * M0 - csrc;
       const float keep = 1.0f - P.omega;
-      float c[19];
-      sfor<19>([&](auto I) {
+      float c[L::Q];
+      sfor<L::Q>([&](auto I) {
         constexpr int i = I;
         float v = keep * a[i] + base;
-        if constexpr (Q19::ex[i] != 0) v += float(Q19::ex[i]) * Sx;
-        if constexpr (Q19::ey[i] != 0) v += float(Q19::ey[i]) * Sy;
-        if constexpr (Q19::ez[i] != 0) v += float(Q19::ez[i]) * Sz;
+        if constexpr (L::ex[i] != 0) v += float(L::ex[i]) * Sx;
+        if constexpr (L::ey[i] != 0) v += float(L::ey[i]) * Sy;
+        if constexpr (L::ez[i] != 0) v += float(L::ez[i]) * Sz;
         c[i] = v;
       });
       if constexpr (!CONT) {
         if (kind == K_INLET || kind == K_OUTLET)
-          zou_he_transpose(c, normal_of(nc), kind == K_OUTLET || P.pin);
+          zou_he_transpose<L>(c, normal_of(nc), kind == K_OUTLET || P.pin);
       }
-      sfor<19>([&](auto I) { A.aout[(size_t)I * P.Np + n] = c[I]; });
+      sfor<L::Q>([&](auto I) { A.aout[(size_t)I * P.Np + n] = c[I]; });
       if constexpr (THERMAL) {
         float cg[7];
         const float bb = og * Bg - dsrc - bq * Sbw;
@@ -651,9 +665,9 @@ __device__ __forceinline__ void adjoint_tile(const AdjArgs& A, int blk) {
   if constexpr (DIAG) block_reduce_store<kRedAdj>(acc, A.partials + (size_t)blk * kRedAdj);
 }
 
-template <bool THERMAL, int OBJ, bool DIAG, bool CONT = false>
+template <class L, bool THERMAL, int OBJ, bool DIAG, bool CONT = false>
 __global__ __launch_bounds__(kBlock) void k_adjoint(AdjArgs A) {
-  adjoint_tile<THERMAL, OBJ, DIAG, CONT>(A, remap_block(blockIdx.x, A.P));
+  adjoint_tile<L, THERMAL, OBJ, DIAG, CONT>(A, remap_block(blockIdx.x, A.P));
 }
 
 // ---------------------------------------------------------------------------
@@ -664,7 +678,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(AdjArgs A) {
 // + beta_max (1 - T) sum_i w_i b_i (and + beta_max (1 - T) for J = -sum Q).
 // Non-design nodes get 0.
 // ---------------------------------------------------------------------------
-template <bool THERMAL>
+template <class L, bool THERMAL>
 __global__ __launch_bounds__(kBlock) void k_sensitivity(SensArgs A) {
   const KParams& P = A.P;
   const int blk = remap_block(blockIdx.x, P);
@@ -685,11 +699,11 @@ __global__ __launch_bounds__(kBlock) void k_sensitivity(SensArgs A) {
       const float dchi = P.tab * (1.0f + P.qb) / (qg * qg);
       const float uu = ux * ux + uy * uy + uz * uz;
       float s = 0.f;
-      sfor<19>([&](auto I) {
+      sfor<L::Q>([&](auto I) {
         constexpr int i = I;
-        const float a = load_pull<Q19, i, Q19::ex[i], Q19::ey[i], Q19::ez[i]>(A.ain, P.Np, nb, n, mr);
-        const float eu = float(Q19::ex[i]) * ux + float(Q19::ey[i]) * uy + float(Q19::ez[i]) * uz;
-        s += Q19::w[i] * a * (3.0f * eu + 9.0f * chi * eu * eu - 3.0f * chi * uu);
+        const float a = load_pull<L, i, L::ex[i], L::ey[i], L::ez[i]>(A.ain, P.Np, nb, n, mr);
+        const float eu = float(L::ex[i]) * ux + float(L::ey[i]) * uy + float(L::ez[i]) * uz;
+        s += L::w[i] * a * (3.0f * eu + 9.0f * chi * eu * eu - 3.0f * chi * uu);
       });
       out = -P.omega * P.rho0 * dchi * s;
       if constexpr (THERMAL) {
@@ -834,22 +848,10 @@ __global__ __launch_bounds__(kBlock) void k_finalize_slots(const SlotDev* __rest
 // the slot's forward or adjoint step on that tile, with the same tile code as
 // the single-problem kernels, so a slot computes bit for bit what it would
 // alone.
-template <bool THERMAL, int OBJ>
-__global__ __launch_bounds__(kBlock) void k_batch(const Tile* __restrict__ tiles,
-                                                  const SlotDev* __restrict__ slots,
-                                                  const int* __restrict__ base, int q, int xper,
-                                                  int xrem) {
-  const int b = blockIdx.x, xcd = b & 7, idx = b >> 3;
-  const int t = xcd < xrem ? xcd * (xper + 1) + idx : xrem * (xper + 1) + (xcd - xrem) * xper + idx;
-  const int launch = *base + q;
-  const Tile tl = tiles[t];
-  const SlotDev& S = slots[tl.slot];
-  const int phase = S.phase;
-  const int k = launch - S.start;
-  if (phase == 0 || k < 0 || k >= S.max_steps) return;  // uniform over the block
-  const bool diag = (S.check > 0 && (k + 1) % S.check == 0) || (k + 1 == S.max_steps);
+template <class L, bool THERMAL, int OBJ>
+__device__ __forceinline__ void batch_tile(const SlotDev& S, int blk, int k, bool diag) {
   const bool odd = (k & 1) != 0;
-  if (phase == 1) {
+  if (S.phase == 1) {
     FwdArgs A = S.fa;
     if (odd) {
       A.fin = S.fa.fout;
@@ -857,8 +859,8 @@ __global__ __launch_bounds__(kBlock) void k_batch(const Tile* __restrict__ tiles
       A.gin = S.fa.gout;
       A.gout = const_cast<float*>(S.fa.gin);
     }
-    if (diag) forward_tile<THERMAL, true>(A, tl.blk);
-    else forward_tile<THERMAL, false>(A, tl.blk);
+    if (diag) forward_tile<L, THERMAL, true>(A, blk);
+    else forward_tile<L, THERMAL, false>(A, blk);
   } else {
     AdjArgs A = S.aa;
     if (odd) {
@@ -869,14 +871,41 @@ __global__ __launch_bounds__(kBlock) void k_batch(const Tile* __restrict__ tiles
     }
     if constexpr (!THERMAL) {
       if (A.P.cont) {
-        if (diag) adjoint_tile<THERMAL, OBJ, true, true>(A, tl.blk);
-        else adjoint_tile<THERMAL, OBJ, false, true>(A, tl.blk);
+        if (diag) adjoint_tile<L, THERMAL, OBJ, true, true>(A, blk);
+        else adjoint_tile<L, THERMAL, OBJ, false, true>(A, blk);
         return;
       }
     }
-    if (diag) adjoint_tile<THERMAL, OBJ, true>(A, tl.blk);
-    else adjoint_tile<THERMAL, OBJ, false>(A, tl.blk);
+    if (diag) adjoint_tile<L, THERMAL, OBJ, true>(A, blk);
+    else adjoint_tile<L, THERMAL, OBJ, false>(A, blk);
   }
+}
+
+// Ragged-batch step: block -> tile (XCD-contiguous runs of tiles) -> slot ->
+// the slot's forward or adjoint step on that tile, with the same tile code as
+// the single-problem kernels, so a slot computes bit for bit what it would
+// alone.  Flow-only engines take D3Q19 and D2Q9 requests side by side (the
+// lattice is uniform over a block: a tile belongs to one slot).
+template <bool THERMAL, int OBJ>
+__global__ __launch_bounds__(kBlock) void k_batch(const Tile* __restrict__ tiles,
+                                                  const SlotDev* __restrict__ slots,
+                                                  const int* __restrict__ base, int q, int xper,
+                                                  int xrem) {
+  const int b = blockIdx.x, xcd = b & 7, idx = b >> 3;
+  const int t = xcd < xrem ? xcd * (xper + 1) + idx : xrem * (xper + 1) + (xcd - xrem) * xper + idx;
+  const int launch = *base + q;
+  const Tile tl = tiles[t];
+  const SlotDev& S = slots[tl.slot];
+  const int k = launch - S.start;
+  if (S.phase == 0 || k < 0 || k >= S.max_steps) return;  // uniform over the block
+  const bool diag = (S.check > 0 && (k + 1) % S.check == 0) || (k + 1 == S.max_steps);
+  if constexpr (!THERMAL) {
+    if (S.fa.P.q == 9) {
+      batch_tile<Q9, THERMAL, OBJ>(S, tl.blk, k, diag);
+      return;
+    }
+  }
+  batch_tile<Q19, THERMAL, OBJ>(S, tl.blk, k, diag);
 }
 
 __global__ void k_advance(int* base, int q) {
@@ -976,28 +1005,43 @@ __global__ void k_fill(float* __restrict__ p, size_t count) {
 // ---------------------------------------------------------------------------
 // ---------------------------------------------------------------------------
 // Level-set update of the design (Eqs. 14, 15, 67) on the design nodes.
-// Laplacian: 7-point stencil over design nodes; a neighbour that is not a
-// design node (or lies outside the box) counts as the node itself (no flux).
+// Laplacian: 7-point stencil (5-point in 2D) in lattice units; a neighbour
+// that is not a design node enters with the fixed phase of its node (+1 for
+// fluid nodes and ports, -1 for walls); a neighbour outside the box or on a
+// mirror layer counts as the node itself (no flux).
 // ---------------------------------------------------------------------------
+// Sum over the counted neighbours of their value (design: phi, else the
+// fixed phase), and their number.
+struct LsNbr {
+  float s;
+  int cnt;
+};
+__device__ __forceinline__ LsNbr levelset_neighbours(const float* __restrict__ phi,
+                                                     const uint8_t* __restrict__ flags, int n,
+                                                     const KParams& P) {
+  const int x = n % P.nx, t = n / P.nx, y = t % P.ny, z = t / P.ny;
+  LsNbr r{0.f, 0};
+  auto add = [&](bool inside, int m) {
+    if (!inside) return;
+    const int k = flags[m] & 7;
+    if (k == K_SYM) return;
+    r.s += (k == K_DESIGN) ? phi[m] : (k >= K_WALL ? -1.0f : 1.0f);
+    ++r.cnt;
+  };
+  add(x > 0, n - 1);
+  add(x < P.nx - 1, n + 1);
+  add(y > 0, n - P.nx);
+  add(y < P.ny - 1, n + P.nx);
+  add(z > 0, n - P.plane);
+  add(z < P.nz - 1, n + P.plane);
+  return r;
+}
+
 __device__ __forceinline__ float levelset_laplacian(const float* __restrict__ phi,
                                                     const uint8_t* __restrict__ flags, int n,
                                                     const KParams& P) {
-  const int x = n % P.nx, t = n / P.nx, y = t % P.ny, z = t / P.ny;
-  const float c = phi[n];
-  float s = 0.f;
-  int cnt = 0;
-  auto add = [&](bool ok, int m) {
-    const bool d = ok && (flags[m] & 7) == K_DESIGN;
-    s += d ? phi[m] : c;
-    ++cnt;
-  };
-  add(x > 0, x > 0 ? n - 1 : n);
-  add(x < P.nx - 1, x < P.nx - 1 ? n + 1 : n);
-  add(y > 0, y > 0 ? n - P.nx : n);
-  add(y < P.ny - 1, y < P.ny - 1 ? n + P.nx : n);
-  add(z > 0, z > 0 ? n - P.plane : n);
-  add(z < P.nz - 1, z < P.nz - 1 ? n + P.plane : n);
-  return s - float(cnt) * c;
+  const LsNbr r = levelset_neighbours(phi, flags, n, P);
+  return r.s - float(r.cnt) * phi[n];
 }
 
 // Pass 1: sum |J'| and the fluid count (phi >= 0) over design nodes.
@@ -1029,23 +1073,46 @@ __global__ __launch_bounds__(kBlock) void k_levelset_lambda(const float* __restr
   block_reduce_store<1>(acc, partials + blockIdx.x);
 }
 
-// Pass 3: phi <- clamp(phi - K (J'/scale + lambda - sigma lap(phi)), -1, 1)
-// (explicit step of Eq. 14), gamma = 1 where phi >= 0 else 0 (Eq. 15).
-__global__ __launch_bounds__(kBlock) void k_levelset_update(const float* __restrict__ phi,
-                                                            float* __restrict__ phi_out,
-                                                            const float* __restrict__ dJ,
-                                                            const uint8_t* __restrict__ flags,
-                                                            float* __restrict__ gamma,
-                                                            float inv_scale, float sigma, float K,
-                                                            float lambda, KParams P) {
+// Right-hand side of the semi-implicit step, r = phi - K (J'/scale + lambda),
+// written to phi_out as the starting guess (non-design nodes copy phi).
+__global__ __launch_bounds__(kBlock) void k_levelset_rhs(const float* __restrict__ phi,
+                                                         float* __restrict__ phi_out,
+                                                         const float* __restrict__ dJ,
+                                                         const uint8_t* __restrict__ flags,
+                                                         float inv_scale, float K, float lambda,
+                                                         KParams P) {
   const int n = blockIdx.x * kBlock + threadIdx.x;
   if (n >= P.N) return;
-  if ((flags[n] & 7) != K_DESIGN) {
-    phi_out[n] = phi[n];
-    return;
-  }
-  const float r = dJ[n] * inv_scale + lambda - sigma * levelset_laplacian(phi, flags, n, P);
-  const float v = fminf(1.0f, fmaxf(-1.0f, phi[n] - K * r));
+  const bool d = (flags[n] & 7) == K_DESIGN;
+  phi_out[n] = d ? phi[n] - K * (dJ[n] * inv_scale + lambda) : phi[n];
+}
+
+// One half-sweep of red-black Gauss-Seidel on (1 + a cnt) x - a sum(nbr) = r
+// (the step (I - K sigma lap) phi_new = r, a = K sigma), in place on x over
+// the design nodes of parity `color` ((x + y + z) mod 2).
+__global__ __launch_bounds__(kBlock) void k_levelset_sweep(const float* __restrict__ phi,
+                                                           float* __restrict__ xs,
+                                                           const float* __restrict__ dJ,
+                                                           const uint8_t* __restrict__ flags,
+                                                           float inv_scale, float K, float lambda,
+                                                           float a, int color, KParams P) {
+  const int n = blockIdx.x * kBlock + threadIdx.x;
+  if (n >= P.N || (flags[n] & 7) != K_DESIGN) return;
+  const int x = n % P.nx, t = n / P.nx, y = t % P.ny, z = t / P.ny;
+  if (((x + y + z) & 1) != color) return;
+  const LsNbr r = levelset_neighbours(xs, flags, n, P);
+  const float rhs = phi[n] - K * (dJ[n] * inv_scale + lambda);
+  xs[n] = (rhs + a * r.s) / (1.0f + a * float(r.cnt));
+}
+
+// Last pass: clamp to [-1, 1] (Eq. 13) and gamma = 1 where phi >= 0, else 0
+// (Eq. 15).
+__global__ __launch_bounds__(kBlock) void k_levelset_finish(float* __restrict__ phi_out,
+                                                            const uint8_t* __restrict__ flags,
+                                                            float* __restrict__ gamma, KParams P) {
+  const int n = blockIdx.x * kBlock + threadIdx.x;
+  if (n >= P.N || (flags[n] & 7) != K_DESIGN) return;
+  const float v = fminf(1.0f, fmaxf(-1.0f, phi_out[n]));
   phi_out[n] = v;
   gamma[n] = v >= 0.0f ? 1.0f : 0.0f;
 }
@@ -1063,10 +1130,16 @@ hipError_t launch_levelset_lambda(const float* phi, const float* dJ, const uint8
   return hipGetLastError();
 }
 hipError_t launch_levelset_update(const float* phi, float* phi_out, const float* dJ,
-                                  const uint8_t* flags, float* gamma, float inv_scale, float sigma,
-                                  float K, float lambda, const KParams& P, hipStream_t s) {
-  hipLaunchKernelGGL(k_levelset_update, dim3(P.nblk), dim3(kBlock), 0, s, phi, phi_out, dJ, flags,
-                     gamma, inv_scale, sigma, K, lambda, P);
+                                  const uint8_t* flags, float* gamma, float inv_scale, float K,
+                                  float lambda, float a, int sweeps, const KParams& P,
+                                  hipStream_t s) {
+  const dim3 g(P.nblk), b(kBlock);
+  hipLaunchKernelGGL(k_levelset_rhs, g, b, 0, s, phi, phi_out, dJ, flags, inv_scale, K, lambda, P);
+  for (int it = 0; it < sweeps; ++it)
+    for (int color = 0; color < 2; ++color)
+      hipLaunchKernelGGL(k_levelset_sweep, g, b, 0, s, phi, phi_out, dJ, flags, inv_scale, K,
+                         lambda, a, color, P);
+  hipLaunchKernelGGL(k_levelset_finish, g, b, 0, s, phi_out, flags, gamma, P);
   return hipGetLastError();
 }
 
@@ -1111,54 +1184,62 @@ static void launch_step(K kern, int nblk, const A& a, hipStream_t s, hipEvent_t 
     hipLaunchKernelGGL(kern, dim3(nblk), dim3(kBlock), 0, s, a);
 }
 
+template <class L, bool TH>
+static void fwd_dispatch(const FwdArgs& a, bool diag, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+  if (diag) launch_step(k_forward<L, TH, true>, a.P.nblk, a, s, ev0, ev1);
+  else launch_step(k_forward<L, TH, false>, a.P.nblk, a, s, ev0, ev1);
+}
+
 hipError_t launch_forward(const FwdArgs& a, bool thermal, bool diag, hipStream_t s, hipEvent_t ev0,
                           hipEvent_t ev1) {
-  const int nb = a.P.nblk;
-  if (thermal) {
-    if (diag) launch_step(k_forward<true, true>, nb, a, s, ev0, ev1);
-    else launch_step(k_forward<true, false>, nb, a, s, ev0, ev1);
-  } else {
-    if (diag) launch_step(k_forward<false, true>, nb, a, s, ev0, ev1);
-    else launch_step(k_forward<false, false>, nb, a, s, ev0, ev1);
-  }
+  if (thermal) fwd_dispatch<Q19, true>(a, diag, s, ev0, ev1);
+  else if (a.P.q == 9) fwd_dispatch<Q9, false>(a, diag, s, ev0, ev1);
+  else fwd_dispatch<Q19, false>(a, diag, s, ev0, ev1);
   return hipGetLastError();
 }
 
-template <bool TH, int OBJ>
+template <class L, bool TH, int OBJ>
 static void adj_dispatch(const AdjArgs& a, bool diag, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   if constexpr (!TH) {
     if (a.P.cont) {
-      if (diag) launch_step(k_adjoint<TH, OBJ, true, true>, a.P.nblk, a, s, ev0, ev1);
-      else launch_step(k_adjoint<TH, OBJ, false, true>, a.P.nblk, a, s, ev0, ev1);
+      if (diag) launch_step(k_adjoint<L, TH, OBJ, true, true>, a.P.nblk, a, s, ev0, ev1);
+      else launch_step(k_adjoint<L, TH, OBJ, false, true>, a.P.nblk, a, s, ev0, ev1);
       return;
     }
   }
-  if (diag) launch_step(k_adjoint<TH, OBJ, true>, a.P.nblk, a, s, ev0, ev1);
-  else launch_step(k_adjoint<TH, OBJ, false>, a.P.nblk, a, s, ev0, ev1);
+  if (diag) launch_step(k_adjoint<L, TH, OBJ, true>, a.P.nblk, a, s, ev0, ev1);
+  else launch_step(k_adjoint<L, TH, OBJ, false>, a.P.nblk, a, s, ev0, ev1);
+}
+
+template <class L>
+static void adj_dispatch_flow(const AdjArgs& a, int objective, bool diag, hipStream_t s,
+                              hipEvent_t ev0, hipEvent_t ev1) {
+  if (objective == OBJ_PRESSURE_DROP) adj_dispatch<L, false, OBJ_PRESSURE_DROP>(a, diag, s, ev0, ev1);
+  else adj_dispatch<L, false, OBJ_DISSIPATION>(a, diag, s, ev0, ev1);
 }
 
 hipError_t launch_adjoint(const AdjArgs& a, bool thermal, int objective, bool diag, hipStream_t s,
                           hipEvent_t ev0, hipEvent_t ev1) {
   if (thermal) {
     switch (objective) {
-      case OBJ_PRESSURE_DROP: adj_dispatch<true, OBJ_PRESSURE_DROP>(a, diag, s, ev0, ev1); break;
-      case OBJ_DISSIPATION: adj_dispatch<true, OBJ_DISSIPATION>(a, diag, s, ev0, ev1); break;
-      case OBJ_HEATGEN: adj_dispatch<true, OBJ_HEATGEN>(a, diag, s, ev0, ev1); break;
-      default: adj_dispatch<true, OBJ_HEATSINK>(a, diag, s, ev0, ev1); break;
+      case OBJ_PRESSURE_DROP: adj_dispatch<Q19, true, OBJ_PRESSURE_DROP>(a, diag, s, ev0, ev1); break;
+      case OBJ_DISSIPATION: adj_dispatch<Q19, true, OBJ_DISSIPATION>(a, diag, s, ev0, ev1); break;
+      case OBJ_HEATGEN: adj_dispatch<Q19, true, OBJ_HEATGEN>(a, diag, s, ev0, ev1); break;
+      default: adj_dispatch<Q19, true, OBJ_HEATSINK>(a, diag, s, ev0, ev1); break;
     }
+  } else if (a.P.q == 9) {
+    adj_dispatch_flow<Q9>(a, objective, diag, s, ev0, ev1);
   } else {
-    switch (objective) {
-      case OBJ_PRESSURE_DROP: adj_dispatch<false, OBJ_PRESSURE_DROP>(a, diag, s, ev0, ev1); break;
-      default: adj_dispatch<false, OBJ_DISSIPATION>(a, diag, s, ev0, ev1); break;
-    }
+    adj_dispatch_flow<Q19>(a, objective, diag, s, ev0, ev1);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_sensitivity(const SensArgs& a, bool thermal, hipStream_t s) {
   const dim3 grid(a.P.nblk), block(kBlock);
-  if (thermal) hipLaunchKernelGGL(k_sensitivity<true>, grid, block, 0, s, a);
-  else hipLaunchKernelGGL(k_sensitivity<false>, grid, block, 0, s, a);
+  if (thermal) hipLaunchKernelGGL((k_sensitivity<Q19, true>), grid, block, 0, s, a);
+  else if (a.P.q == 9) hipLaunchKernelGGL((k_sensitivity<Q9, false>), grid, block, 0, s, a);
+  else hipLaunchKernelGGL((k_sensitivity<Q19, false>), grid, block, 0, s, a);
   return hipGetLastError();
 }
 
@@ -1235,21 +1316,30 @@ hipError_t launch_finalize_slots(const SlotDev* slots, int nslots, double* out, 
   return hipGetLastError();
 }
 
+// Direction table of lattice `which` (0 D3Q19, 1 D3Q7, 2 D2Q9).
+template <class L>
+static void table_of(int32_t* e, double* w, const double* wd) {
+  for (int i = 0; i < L::Q; ++i) {
+    e[3 * i] = L::ex[i];
+    e[3 * i + 1] = L::ey[i];
+    e[3 * i + 2] = L::ez[i];
+    w[i] = wd[i];
+  }
+}
+
 void lattice_table(int which, int32_t* e, double* w) {
   if (which == 0) {
-    for (int i = 0; i < 19; ++i) {
-      e[3 * i] = Q19::ex[i];
-      e[3 * i + 1] = Q19::ey[i];
-      e[3 * i + 2] = Q19::ez[i];
-      w[i] = (i == 0) ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);
-    }
+    double wd[19];
+    for (int i = 0; i < 19; ++i) wd[i] = (i == 0) ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);
+    table_of<Q19>(e, w, wd);
+  } else if (which == 1) {
+    double wd[7];
+    for (int i = 0; i < 7; ++i) wd[i] = (i == 0) ? 0.25 : 0.125;
+    table_of<Q7>(e, w, wd);
   } else {
-    for (int i = 0; i < 7; ++i) {
-      e[3 * i] = Q7::ex[i];
-      e[3 * i + 1] = Q7::ey[i];
-      e[3 * i + 2] = Q7::ez[i];
-      w[i] = (i == 0) ? 0.25 : 0.125;
-    }
+    double wd[9];
+    for (int i = 0; i < 9; ++i) wd[i] = (i == 0) ? 4.0 / 9.0 : (i <= 4 ? 1.0 / 9.0 : 1.0 / 36.0);
+    table_of<Q9>(e, w, wd);
   }
 }
 

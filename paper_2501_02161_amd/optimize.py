@@ -3,7 +3,7 @@ of Sec. 2.2 (Eqs. 13-15, 67).
 
 Each iteration solves the steady forward problem, the discrete adjoint and
 dJ/dgamma (warm-started from the previous iteration's states after the
-first), then moves the level set phi by one explicit step of the
+first), then moves the level set phi by one semi-implicit step of the
 reaction-diffusion equation (Eq. 14) with the multiplier of Eq. (67) and maps
 it to the binary design (Eq. 15), all in the gfx950 library
 (lbm_forward_resume, lbm_adjoint_resume, lbm_sensitivity,
@@ -20,12 +20,27 @@ import torch
 from . import lbm
 
 
+def design_length(spec) -> int:
+    """Longest side (in nodes) of the bounding box of the design domain."""
+    design = (np.asarray(spec.mask).reshape(spec.nz, spec.ny, spec.nx) & 7) == 0
+    idx = np.argwhere(design)
+    if len(idx) == 0:
+        return 1
+    return int((idx.max(0) - idx.min(0) + 1).max())
+
+
 class LevelSetOptimizer:
+    """sigma is the dimensionless regularisation coefficient of Eq. (14) on
+    the length L of the design domain (its longest side): the library gets
+    sigma L^2 in lattice units."""
+
     def __init__(self, spec, K: float = 0.1, sigma: float = 1e-3, vmax: float = 0.3,
                  device="cuda:0"):
         self.spec = spec
         self.problem = lbm.Problem(spec, device=device)
         self.K, self.sigma, self.vmax = float(K), float(sigma), float(vmax)
+        self.L = design_length(spec)
+        self.sigma_lattice = self.sigma * self.L ** 2
         self.device = self.problem.device
         design = (np.asarray(spec.mask).reshape(spec.nz, spec.ny, spec.nx) & 7) == 0
         g0 = np.where(design, 1.0, np.asarray(spec.gamma, dtype=np.float64).reshape(design.shape))
@@ -47,7 +62,7 @@ class LevelSetOptimizer:
         J = p.sensitivity()
         with torch.cuda.device(self.device):
             ls = lbm.lbm_levelset_update(p.h, self.phi, self.phi_next, p.dJ, self.gamma, self.K,
-                                         self.sigma, self.vmax)
+                                         self.sigma_lattice, self.vmax)
         torch.cuda.synchronize(self.device)
         self.phi, self.phi_next = self.phi_next, self.phi
         self.updates += p.N * (fi["steps"] + ai["steps"])

@@ -53,7 +53,7 @@ def classify(r) -> str:
     return "diverged"
 
 
-def sweep(taus, speeds, n=32, max_steps=1000000, log=None):
+def sweep(taus, speeds, n=32, max_steps=1000000, log=None, dim=3):
     """Run the grid taus x speeds x {discrete, continuous}; returns
     (points, limits): points[(tau, u, kind)] = (class, fwd_steps, adj_steps),
     limits[tau] = {"primal": u, "discrete": u, "continuous": u} with the
@@ -65,7 +65,7 @@ def sweep(taus, speeds, n=32, max_steps=1000000, log=None):
         for u in speeds:
             for kind in (lbm.LBM_ADJOINT_DISCRETE, lbm.LBM_ADJOINT_CONTINUOUS):
                 keys.append((tau, u, kind))
-                cases.append(W.stability_case(n, tau, u, kind, max_steps=max_steps))
+                cases.append(W.stability_case(n, tau, u, kind, max_steps=max_steps, dim=dim))
     res = run_points(cases, log=log)
     points = {k: (classify(r), r["fwd_steps"], r["adj_steps"]) for k, r in zip(keys, res)}
     limits = {}

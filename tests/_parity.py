@@ -18,10 +18,11 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-def perm_to_oracle(o, which):
+def perm_to_oracle(o, which, two_d=False):
     """perm[i_oracle] = i_gpu for the flow (0) or thermal (1) lattice, matched by
-    velocity vectors (the two sides keep their own tables)."""
-    eg, wg = lbm.lbm_lattice(which)
+    velocity vectors (the two sides keep their own tables); the flow lattice
+    of a 2D problem is D2Q9."""
+    eg, wg = lbm.lbm_lattice(2 if (two_d and which == 0) else which)
     eo, wo = o.lattice(which)
     perm = np.zeros(len(wo), dtype=np.int64)
     for i, e in enumerate(eo):
@@ -38,7 +39,7 @@ def gpu_pops(prob, which, o):
     st = prob.state(which)
     s = st.reshape(st.shape[0], -1).T.cpu().numpy().astype(np.float64)
     lat = 0 if which in (lbm.STATE_FLOW, lbm.STATE_ADJ_FLOW) else 1
-    return s[:, perm_to_oracle(o, lat)]
+    return s[:, perm_to_oracle(o, lat, prob.spec.nz == 1)]
 
 
 def gpu_fields(prob):

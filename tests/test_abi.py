@@ -175,3 +175,36 @@ def test_invalid_symmetry_and_heat_generation(lbm, bad):
     with pytest.raises(lbm.LBMError) as e:
         _create(lbm, w, **kw)
     assert e.value.code == lbm.LBM_EINVAL
+
+
+def test_2d_lattice_table_and_descriptor(lbm):
+    e9, w9 = lbm.lbm_lattice(2)
+    assert e9.shape == (9, 3) and np.all(e9[:, 2] == 0) and abs(w9.sum() - 1) < 1e-15
+    assert np.allclose(np.einsum("i,ia,ib->ab", w9, e9[:, :2], e9[:, :2]), np.eye(2) / 3)
+    for c, nv in enumerate([[1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0]]):
+        assert list(e9[c + 1]) == nv
+    w = W.pipe_bend_2d()
+    h = _create(lbm, w)
+    # 2 x 9 forward + 2 x 9 adjoint populations, flags, inlet speed
+    n = lbm.lbm_workspace_bytes(h)
+    assert 36 * 4 * w.N <= n < (36 + 3) * 4 * (w.N + 64) + 64 * 1024
+    lbm.lbm_problem_destroy(h)
+
+
+@pytest.mark.parametrize("bad", ["thermal", "nz2", "z_normal", "z_symmetric"])
+def test_invalid_2d_inputs_are_rejected(lbm, bad):
+    w = W.pipe_bend_2d()
+    kw = {}
+    if bad == "thermal":
+        kw["thermal"] = True
+    elif bad == "nz2":
+        kw.update(nz=2, mask=np.concatenate([w.mask, w.mask]), gamma=np.concatenate([w.gamma] * 2))
+    elif bad == "z_normal":
+        m = w.mask.copy()
+        m[(m & 7) == W.INLET] = W.code(W.INLET, W.NPZ)
+        kw["mask"] = m
+    elif bad == "z_symmetric":
+        kw["symmetric"] = (False, False, True)
+    with pytest.raises(lbm.LBMError) as e:
+        _create(lbm, w, **kw)
+    assert e.value.code == lbm.LBM_EINVAL

@@ -1,0 +1,116 @@
+"""GPU parity of the 2D (D2Q9) path against the FP64 oracle: the paper's 2D
+pipe bend (Sec. 3.1) with both objectives and both adjoint kinds, equal fixed
+step counts and converged solves, the per-step arithmetic at a larger size,
+and 2D requests served by the batch engine next to 3D ones (each result
+identical to its single solve).
+
+Tolerances as for the 3D path: 1e-5 on p and u over non-wall nodes, 1e-4 on
+dJ/dgamma over design nodes (norm-wise relative)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from _parity import compare_solution, gpu_fields, rel, run_gpu, run_oracle
+from paper_2501_02161_amd import lbm
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    torch.cuda.set_device(0)
+    lbm.load_library()
+    yield
+
+
+def bend(objective=W.OBJ_PRESSURE_DROP, kind=0, Re=10.0, n=45):
+    # 45 x 45 = 2025 nodes: 8 tiles of 256, the last one ragged
+    w = W.pipe_bend_2d(n=n, Re=Re, sigma=2.0, seed=201, inlet=(5, 16), outlet=(28, 39))
+    return w.replace(objective=objective, adjoint_kind=kind)
+
+
+CASES = {
+    "pressure_drop": lambda: bend(),
+    "dissipation": lambda: bend(W.OBJ_DISSIPATION),
+    "continuous_pressure_drop": lambda: bend(kind=1, Re=2.0),
+}
+
+
+def test_lattice_table():
+    e, w = lbm.lbm_lattice(2)
+    assert e.shape == (9, 3) and np.all(e[:, 2] == 0)
+    assert math.isclose(w.sum(), 1.0, rel_tol=1e-15)
+    assert np.allclose((w[:, None] * e[:, :2]).sum(0), 0.0)
+    assert np.allclose(np.einsum("i,ia,ib->ab", w, e[:, :2], e[:, :2]), np.eye(2) / 3.0)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_fixed_steps_parity_2d(name):
+    w = CASES[name]().replace(max_steps=800, tol=0.0, check_every=200)
+    print(f"[d2q9] {name} grid {w.nx}x{w.ny} tau {w.tau:.4f}", flush=True)
+    prob, res = run_gpu(w)
+    o, ref = run_oracle(w, steps=800, tol=0.0, check_every=200)
+    err = compare_solution(w, prob, ref)
+    assert res["forward"]["steps"] == 800 and res["adjoint"]["steps"] == 800
+    assert math.isclose(res["J"], ref["J"], rel_tol=1e-5)
+    print(f"[d2q9] {name} errors {err} J {res['J']:.9g} vs {ref['J']:.9g}", flush=True)
+
+
+def test_converged_parity_2d():
+    w = W.tiny_pipe_bend_2d().replace(max_steps=60000, tol=1e-8, check_every=500)
+    prob, res = run_gpu(w)
+    assert res["forward"]["status"] == lbm.LBM_OK, res
+    assert res["adjoint"]["status"] == lbm.LBM_OK, res
+    o, ref = run_oracle(w)
+    assert ref["fwd_status"] == 0 and ref["adj_status"] == 0
+    err = compare_solution(w, prob, ref)
+    print(f"[d2q9] converged steps gpu {res['forward']['steps']}/{res['adjoint']['steps']} "
+          f"oracle {ref['fwd_steps']}/{ref['adj_steps']} errors {err}", flush=True)
+
+
+def test_full_size_step_parity_2d():
+    from test_gpu_parity import _step_check
+    w = W.pipe_bend_2d(n=512, inlet=(64, 191), outlet=(320, 447))
+    print(f"[d2q9] step check {w.nx}x{w.ny}", flush=True)
+    err, J = _step_check(w)
+    print(f"[d2q9] step errors {err}", flush=True)
+    for key, v in err.items():
+        assert v < (1e-4 if key == "sens" else 1e-5), (key, err)
+
+
+def test_batch_mixes_2d_and_3d():
+    """2D requests share a flow-only engine with 3D ones (one ragged-batch
+    launch steps both lattices) and each result is its single solve's."""
+    from paper_2501_02161_amd import serving
+    reqs = [bend().replace(max_steps=4000, tol=1e-7, check_every=500),
+            W.pipe_bend_3d(n=20, tau=0.8, Re=10.0, port=5, objective=W.OBJ_PRESSURE_DROP).replace(
+                max_steps=4000, tol=1e-7, check_every=500),
+            bend(Re=5.0).replace(max_steps=4000, tol=1e-7, check_every=500)]
+    eng = serving.BatchEngine(False, W.OBJ_PRESSURE_DROP, budget_bytes=256 << 20, max_slots=4,
+                              quantum=100)
+    tickets = {eng.submit(w): i for i, w in enumerate(reqs)}
+    results = {}
+    for _ in range(10000):
+        eng.step()
+        for t, i in list(tickets.items()):
+            r = eng.collect(t, reqs[i].N)
+            if r is not None:
+                results[i] = r
+                del tickets[t]
+        if not tickets:
+            break
+    assert len(results) == len(reqs)
+    for i, w in enumerate(reqs):
+        prob, res = run_gpu(w)
+        _, _, _, dJ = gpu_fields(prob)
+        r = results[i]
+        print(f"[d2q9] batch {w.name}: J {r['J']:.9g} vs {res['J']:.9g} steps "
+              f"{r['fwd_steps']}/{r['adj_steps']}", flush=True)
+        assert r["state"] == lbm.LBM_BATCH_DONE
+        assert r["J"] == res["J"]
+        assert r["fwd_steps"] == res["forward"]["steps"]
+        assert np.array_equal(r["dJ"], dJ.astype(np.float32))

@@ -26,11 +26,15 @@ def _device():
     yield
 
 
-@pytest.mark.parametrize("sigma", [0.0, 0.05])
+@pytest.mark.parametrize("sigma", [0.0, 2.0, 60.0])
 def test_levelset_update_parity(sigma):
+    """sigma in lattice units: 0 (no diffusion), 2 (K sigma 0.4, a few dozen
+    sweeps) and 60 (K sigma 12, hundreds of sweeps); the design domain
+    touches walls, the inlet and the outlet (fixed phases)."""
     w = W.pipe_bend_3d(n=24, port=6)
     p = lbm.Problem(w, device="cuda:0")
-    design = (w.mask & 7) == W.DESIGN
+    kinds = w.mask & 7
+    design = kinds == W.DESIGN
     rng = np.random.default_rng(11)
     phi = np.where(design, rng.uniform(-1, 1, design.shape), 0.0).astype(np.float32)
     dJ = np.where(design, rng.normal(size=design.shape), 0.0).astype(np.float32)
@@ -41,12 +45,12 @@ def test_levelset_update_parity(sigma):
     info = lbm.lbm_levelset_update(p.h, phi_d, out, dJ_d, g_d, 0.2, sigma, 0.35)
     torch.cuda.synchronize()
     ref_phi, ref_alpha, ref = levelset_update(phi.astype(np.float64), dJ.astype(np.float64),
-                                              design, 0.2, sigma, 0.35)
+                                              kinds, 0.2, sigma, 0.35)
     got = out.cpu().numpy()
     g = g_d.cpu().numpy()
     print(f"[levelset] sigma {sigma}: phi err {rel(got[design], ref_phi[design]):.2e} "
           f"lambda {info['lambda']:.9g} vs {ref['lambda']:.9g}", flush=True)
-    assert rel(got[design], ref_phi[design]) < 1e-6
+    assert rel(got[design], ref_phi[design]) < 1e-5
     assert np.array_equal(got[~design], phi[~design])
     assert info["volume"] == ref["volume"] and abs(info["G"] - ref["G"]) < 1e-15
     assert abs(info["lambda"] - ref["lambda"]) <= 1e-6 * ref["lambda"]

@@ -1,59 +1,115 @@
 """Pins of the oracle's level-set update (Eqs. 13-15, 67), independent of the
-update's own arithmetic: the stencil on fields whose Laplacian is known,
-the multiplier on inputs where it has a closed form, and the step on
-uniform inputs."""
+update's own arithmetic: the stencil on fields whose Laplacian is known and
+at fixed-phase neighbours, the implicit system against the loop stencil
+applied to unit vectors, the step against Eq. (14) evaluated with the loop
+stencil, and closed forms on uniform inputs."""
 import numpy as np
 
-from oracle.levelset import laplacian, levelset_update
+from oracle.levelset import implicit_matrix, laplacian, levelset_update
+
+D, F, I, O, W_, H, S = 0, 1, 2, 3, 4, 5, 6
 
 
 def _box(n=6):
-    d = np.ones((n, n, n), dtype=bool)
-    d[0], d[-1], d[:, 0], d[:, -1], d[:, :, 0], d[:, :, -1] = (False,) * 6
-    return d
+    k = np.full((n, n, n), D, dtype=np.uint8)
+    k[0], k[-1], k[:, 0], k[:, -1], k[:, :, 0], k[:, :, -1] = (W_,) * 6
+    return k
 
 
 def test_laplacian_of_quadratic_is_exact():
     z, y, x = np.meshgrid(np.arange(7.), np.arange(7.), np.arange(7.), indexing="ij")
     phi = 0.5 * x ** 2 - 0.25 * y ** 2 + 0.125 * z ** 2 + 3 * x * y
-    d = np.ones(phi.shape, dtype=bool)
-    lap = laplacian(phi, d)
+    k = np.zeros(phi.shape, dtype=np.uint8)
+    lap = laplacian(phi, k)
     inner = (slice(1, -1),) * 3
     assert np.allclose(lap[inner], 1.0 - 0.5 + 0.25, atol=1e-12)
+    # a box face counts as the node itself: a constant field has no Laplacian
+    assert np.all(laplacian(np.full(phi.shape, 0.3), k) == 0.0)
 
 
-def test_laplacian_no_flux_and_constant():
-    d = _box()
-    phi = np.full(d.shape, 0.3)
-    assert np.allclose(laplacian(phi, d), 0.0, atol=1e-15)
-    # a non-design neighbour counts as the node itself
-    phi2 = np.zeros(d.shape)
-    phi2[~d] = 5.0
-    assert np.all(laplacian(phi2, d) == 0.0)
+def test_fixed_phase_neighbours():
+    k = np.full((3, 3, 5), D, dtype=np.uint8)
+    k[:, :, 0] = W_          # a wall at x = 0: phase -1
+    k[:, :, 4] = F           # fluid at x = 4: phase +1
+    k[2] = S                 # a mirror layer at z = 2: counts as the node itself
+    phi = np.zeros(k.shape)
+    phi[k == D] = 0.25
+    lap = laplacian(phi, k)
+    assert np.isclose(lap[1, 1, 1], -1.25)       # wall neighbour: -1 - 0.25
+    assert np.isclose(lap[1, 1, 3], 0.75)        # fluid neighbour: 1 - 0.25
+    assert np.isclose(lap[1, 1, 2], 0.0)
+    assert np.isclose(lap[0, 1, 1], -1.25)       # box face below, design above
+    for kind, ph in ((I, 1.0), (O, 1.0), (H, -1.0)):
+        k2 = k.copy()
+        k2[:, :, 0] = kind
+        assert np.isclose(laplacian(phi, k2)[1, 1, 1], ph - 0.25)
 
 
-def test_lambda_closed_form_and_uniform_step():
-    d = _box()
+def test_implicit_matrix_is_the_loop_stencil():
+    rng = np.random.default_rng(1)
+    k = _box(5)
+    k[2, 2, 0] = I
+    k[1, 4, 2] = F
+    k[3, 3, 3] = W_
+    d = k == D
+    nodes = np.argwhere(d)
+    a = 0.7
+    A, b = implicit_matrix(k, a)
+    # lap is affine in phi: lap(phi) = L phi + c with c = lap(0)
+    zero = np.zeros(k.shape)
+    c = laplacian(zero, k)[d]
+    for j, idx in enumerate(nodes):
+        e = zero.copy()
+        e[tuple(idx)] = 1.0
+        col = e[d] - a * (laplacian(e, k)[d] - c)
+        assert np.allclose(A[:, j].toarray().ravel(), col, atol=1e-15)
+    assert np.allclose(b, a * c, atol=1e-15)
+    assert np.allclose(A.toarray(), A.toarray().T)
+
+
+def test_step_satisfies_eq14():
     rng = np.random.default_rng(0)
-    phi = rng.uniform(-0.5, 0.5, d.shape)
-    dJ = np.where(d, 2.0, 0.0)                       # uniform sensitivity
-    K, vmax = 0.05, 0.3
-    new, alpha, info = levelset_update(phi, dJ, d, K, 0.0, vmax)
-    v = (phi[d] >= 0).mean()
-    assert info["volume"] == v and np.isclose(info["G"], v - vmax)
-    # sigma = 0, |J'/mean|J'|| = 1 everywhere: lambda = exp(G)
-    assert np.isclose(info["lambda"], np.exp(v - vmax), rtol=1e-15)
-    assert np.allclose(new[d], np.clip(phi[d] - K * (1.0 + np.exp(v - vmax)), -1, 1), rtol=1e-15)
+    k = _box(7)
+    k[3, 3, 0] = I
+    k[3, 0, 3] = O
+    k[2, 2, 2] = W_
+    d = k == D
+    phi = np.where(d, rng.uniform(-0.5, 0.5, k.shape), 0.0)
+    dJ = np.where(d, rng.normal(size=k.shape), 0.0)
+    K, sigma, vmax = 0.05, 0.8, 0.4
+    new, alpha, info = levelset_update(phi, dJ, k, K, sigma, vmax)
+    assert np.all(np.abs(new[d]) < 1.0)           # no clamp active
+    s = np.abs(dJ[d]).mean()
+    lam_ref = np.exp(info["G"]) * np.abs(dJ[d] / s - sigma * laplacian(phi, k)[d]).mean()
+    assert np.isclose(info["lambda"], lam_ref, rtol=1e-14)
+    lhs = (new[d] - phi[d]) / K
+    rhs = -(dJ[d] / s + info["lambda"]) + sigma * laplacian(new, k)[d]
+    assert np.allclose(lhs, rhs, atol=1e-10)
     assert np.array_equal(alpha[d], (new[d] >= 0).astype(float))
     assert np.array_equal(new[~d], phi[~d])
 
 
+def test_lambda_closed_form_and_uniform_step():
+    k = np.zeros((6, 6, 6), dtype=np.uint8)       # all design: no fixed phases
+    d = k == D
+    phi = np.full(k.shape, 0.2)
+    dJ = np.full(k.shape, 2.0)                     # uniform sensitivity
+    K, vmax = 0.05, 0.3
+    for sigma in (0.0, 0.5):
+        new, alpha, info = levelset_update(phi, dJ, k, K, sigma, vmax)
+        assert info["volume"] == 1.0 and np.isclose(info["G"], 1.0 - vmax)
+        # |J'/mean|J'|| = 1 and lap phi = 0: lambda = exp(G), uniform step
+        assert np.isclose(info["lambda"], np.exp(1.0 - vmax), rtol=1e-15)
+        assert np.allclose(new, 0.2 - K * (1.0 + np.exp(1.0 - vmax)), rtol=1e-13)
+
+
 def test_clamp_and_direction():
-    d = _box()
-    phi = np.full(d.shape, 0.99)
+    k = _box()
+    d = k == D
+    phi = np.where(d, 0.99, 0.0)
     dJ = np.where(d, -1.0, 0.0)                      # J decreases with more fluid
-    new, _, info = levelset_update(phi, dJ, d, 1.0, 0.0, 1.0)
+    new, _, info = levelset_update(phi, dJ, k, 1.0, 0.0, 1.0)
     # volume 1 = vmax: G = 0, lambda = 1, step -K(-1 + 1) = 0
     assert np.isclose(info["lambda"], 1.0) and np.allclose(new[d], 0.99)
-    new2, _, _ = levelset_update(np.full(d.shape, -0.99), dJ, d, 10.0, 0.0, 1.0)
+    new2, _, _ = levelset_update(np.where(d, -0.99, 0.0), dJ, k, 10.0, 0.3, 1.0)
     assert np.all(new2[d] <= 1.0) and np.all(new2[d] >= -1.0)

@@ -297,16 +297,21 @@ def serving_request(i: int, base_seed: int = SEED_BASE + 4) -> Workload:
 
 
 def stability_case(n: int, tau: float, u_peak: float, adjoint_kind: int, seed: int = SEED_BASE + 6,
-                   max_steps: int = 1000000, tol: float = 1e-9) -> Workload:
-    """One point of the stability test (a 3D pipe bend on n^3 at relaxation
-    time tau and peak inlet speed u_peak, pressure-drop objective, given
-    adjoint kind): Re = u_peak L / nu with L the port width."""
-    w = pipe_bend_3d(n=n, tau=tau, Re=1.0, sigma=max(1.0, n / 24.0), seed=seed,
-                     port=max(4, n // 6), objective=OBJ_PRESSURE_DROP)
+                   max_steps: int = 1000000, tol: float = 1e-9, dim: int = 3) -> Workload:
+    """One point of the stability test: the pipe bend (3D on n^3, or 2D D2Q9
+    on n x n) at relaxation time tau and peak inlet speed u_peak,
+    pressure-drop objective, given adjoint kind; Re = u_peak L / nu with L
+    the port width."""
+    if dim == 2:
+        w = pipe_bend_2d(n=n, tau=tau, Re=1.0, sigma=max(1.0, n / 24.0), seed=seed,
+                         inlet=(n // 8, (23 * n) // 64), outlet=((5 * n) // 8, (55 * n) // 64))
+    else:
+        w = pipe_bend_3d(n=n, tau=tau, Re=1.0, sigma=max(1.0, n / 24.0), seed=seed,
+                         port=max(4, n // 6), objective=OBJ_PRESSURE_DROP)
     nu = (tau - 0.5) / 3.0
     return w.replace(Re=u_peak * w.L_ref / nu, adjoint_kind=adjoint_kind, max_steps=max_steps,
                      tol=tol, check_every=1000,
-                     name=f"stability_{n}_tau{tau:g}_u{u_peak:g}_k{adjoint_kind}")
+                     name=f"stability_{dim}d_{n}_tau{tau:g}_u{u_peak:g}_k{adjoint_kind}")
 
 
 def poisson_arrivals(n: int, rate: float, seed: int = SEED_BASE + 5) -> np.ndarray:

@@ -35,23 +35,19 @@ METRIC = "fwd+adj MLUPS & % HBM peak (D3Q19+D3Q7 FP32); p50/p99 sensitivity late
 HBM_PEAK_GBS = 8000.0
 
 def bytes_per_node(kernel, w):
-    """Algorithmic bytes per node-update of a step kernel for workload w."""
-    b = BYTES_PER_NODE[(kernel, bool(w.thermal))]
-    if kernel == "adjoint" and w.objective == 1:  # dissipation: source G (3 floats)
+    """Algorithmic bytes per node-update of a step kernel for workload w:
+    every population read once and written once (4 B each), plus the
+    per-node inputs each kernel reads once (forward: gamma, flags; adjoint:
+    u, T, gamma, flags, and the dissipation source G)."""
+    q = 9 if w.nz == 1 else 19          # D2Q9 on a 2D lattice, else D3Q19
+    dim = 2 if w.nz == 1 else 3
+    qt = 7 if w.thermal else 0
+    if kernel == "forward":
+        return (q + qt) * 4 * 2 + 4 + 1
+    b = (q + qt) * 4 * 2 + dim * 4 + (4 if w.thermal else 0) + 4 + 1
+    if w.objective == 1:                # dissipation: source G (3 floats)
         b += 12
     return b
-
-
-# Algorithmic bytes per node-update: every population read once and written
-# once (4 B each), plus the per-node inputs each kernel reads once.
-BYTES_PER_NODE = {
-    # forward: 19 + 7 populations in and out, gamma, flags
-    ("forward", True): (19 + 7) * 4 * 2 + 4 + 1,
-    ("forward", False): 19 * 4 * 2 + 4 + 1,
-    # adjoint: 19 + 7 populations in and out, u (3), T, gamma, flags
-    ("adjoint", True): (19 + 7) * 4 * 2 + 12 + 4 + 4 + 1,
-    ("adjoint", False): 19 * 4 * 2 + 12 + 4 + 1,
-}
 
 
 def parse():
@@ -63,7 +59,7 @@ def parse():
                     choices=["heat_sink_Re50", "heat_sink_Re200", "heat_sink_Re400",
                              "heat_sink_320x160x80_Re200", "pipe_bend_96", "pipe_bend_96_dp",
                              "paper_heat_sink_Re60", "paper_heat_sink_Re120",
-                             "paper_heat_sink_Re240"])
+                             "paper_heat_sink_Re240", "pipe_bend_2d_512", "pipe_bend_2d_2048"])
     ap.add_argument("--re", type=float, default=0.0,
                     help="Reynolds number of a pipe-bend workload (0: the workload's own)")
     ap.add_argument("--adjoint", default="discrete", choices=["discrete", "continuous"],
@@ -103,6 +99,10 @@ def parse():
     ap.add_argument("--opt-k", type=float, default=0.1, help="level-set step size K (Eq. 14)")
     ap.add_argument("--opt-sigma", type=float, default=5e-3,
                     help="level-set regularisation coefficient sigma (Eq. 14)")
+    ap.add_argument("--opt-sigma-z", type=float, default=0.0,
+                    help="sigma along z if > 0 (anisotropic regularisation, Sec. 3.3.4)")
+    ap.add_argument("--opt-max-steps", type=int, default=0,
+                    help="step cap of each solve in the optimisation (0: the workload's)")
     ap.add_argument("--opt-vmax", type=float, default=0.5,
                     help="upper limit of the design domain's fluid fraction (Eq. 10)")
     ap.add_argument("--serving-only", action="store_true",
@@ -185,6 +185,10 @@ def make_workload(name, adjoint="discrete", Re=0.0):
         w = W.pipe_bend_3d(objective=obj, **({"Re": Re} if Re > 0 else {}))
         return w.replace(adjoint_kind=kind, name=w.name + ("_dp" if name.endswith("_dp") else "")
                          + (f"_Re{Re:g}" if Re > 0 else "") + ("_continuous" if kind else ""))
+    if name.startswith("pipe_bend_2d_"):
+        n = int(name.split("_")[3])
+        w = W.pipe_bend_2d(n=n, inlet=(n // 8, (23 * n) // 64), outlet=((5 * n) // 8, (55 * n) // 64))
+        return w.replace(adjoint_kind=kind, name=w.name + ("_continuous" if kind else ""))
     if name.startswith("paper_heat_sink"):
         return W.paper_heat_sink(Re=float(name.split("Re")[1]))
     if name == "heat_sink_320x160x80_Re200":
@@ -298,13 +302,17 @@ def optimize_leg(args):
 
     torch.cuda.set_device(0)
     w = make_workload(args.workload, args.adjoint, args.re)
-    opt = optimize.LevelSetOptimizer(w, K=args.opt_k, sigma=args.opt_sigma, vmax=args.opt_vmax)
+    if args.opt_max_steps > 0:
+        w = w.replace(max_steps=args.opt_max_steps)
+    sigma = (args.opt_sigma, args.opt_sigma, args.opt_sigma_z or args.opt_sigma)
+    opt = optimize.LevelSetOptimizer(w, K=args.opt_k, sigma=sigma, vmax=args.opt_vmax)
     t0 = time.perf_counter()
     hist = opt.run(args.optimize, log=lambda r: print(f"[optimize] {json.dumps(r)}",
                                                       file=sys.stderr, flush=True))
     el = time.perf_counter() - t0
     return {"workload": w.name, "lattice": [w.nx, w.ny, w.nz], "K": args.opt_k,
-            "sigma": args.opt_sigma, "vmax": args.opt_vmax, "iterations": len(hist),
+            "sigma": list(opt.sigma), "sigma_lattice": list(opt.sigma_lattice), "vmax": args.opt_vmax,
+            "max_steps": w.max_steps, "tol": w.tol, "iterations": len(hist),
             "seconds": round(el, 3), "seconds_per_iteration": round(el / max(1, len(hist)), 4),
             "node_updates_per_s": opt.updates / el,
             "J": [h["J"] for h in hist], "volume": [h["volume"] for h in hist],
@@ -396,7 +404,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": w.name, "nodes": w.N,
-                   "lattice": "D3Q19+D3Q7" if w.thermal else "D3Q19",
+                   "lattice": "D2Q9" if w.nz == 1 else ("D3Q19+D3Q7" if w.thermal else "D3Q19"),
                    "objective": {0: "pressure drop", 1: "viscous dissipation",
                                  2: "mean floor-layer T + 0.1 pressure drop",
                                  3: "heat generated, -sum beta (1 - T)"}[w.objective],

@@ -256,16 +256,17 @@ int lbm_adjoint_resume(lbm_problem_t* p, const float* gamma, const float* drho, 
  *          set, then phi' = clamp(phi', -1, 1) (Eq. 13)
  *   gamma  = 1 where phi' >= 0, else 0 (Eq. 15)
  * V is the fluid fraction (phi >= 0) of the design domain before the step.
- * lap is the 7-point Laplacian (5-point in 2D) in lattice units; a
- * neighbour that is not a design node enters with the fixed phase of its
- * node (+1 for FLUID, INLET and OUTLET, -1 for WALL and HEATED); one outside
- * the box or on a SYM layer counts as the node itself.  sigma is in lattice
- * units (a dimensionless coefficient on a length L is sigma L^2 here).  The
- * implicit system is solved by red-black Gauss-Seidel sweeps, as many as
- * take the error below 1e-8 of the starting guess's.  phi, phi_out, dJ,
+ * sigma lap is the 7-point stencil (5-point in 2D) in lattice units over
+ * the design nodes, sum_a sigma[a] (phi(x + e_a) + phi(x - e_a) - 2 phi(x))
+ * with sigma (host, 3 doubles) the coefficient per axis x, y, z (the
+ * anisotropic regularisation of Sec. 3.3.4; equal for the isotropic one); a
+ * neighbour that is not a design node (or lies outside the box) counts as
+ * the node itself (no flux).  A dimensionless coefficient on a length L is
+ * sigma L^2 here.  The implicit system is solved by red-black Gauss-Seidel
+ * sweeps, as many as take the error below 1e-8 of the starting guess's.  phi, phi_out, dJ,
  * gamma: device [N] float; phi_out must not alias phi; non-design entries
  * of phi_out copy phi, of gamma are left unchanged.  Synchronises the
- * stream (two small reductions).  LBM_EINVAL for K <= 0, sigma < 0, vmax
+ * stream (two small reductions).  LBM_EINVAL for K <= 0, a sigma < 0, vmax
  * outside (0, 1], K sigma too large for 100000 sweeps, or no design nodes. */
 typedef struct lbm_levelset_info {
   double lambda;           /* Eq. (67)                                        */
@@ -274,7 +275,7 @@ typedef struct lbm_levelset_info {
   double scale;            /* mean |J'| over the design domain                */
 } lbm_levelset_info_t;
 int lbm_levelset_update(lbm_problem_t* p, const float* phi, float* phi_out, const float* dJ,
-                        float* gamma, double K, double sigma, double vmax,
+                        float* gamma, double K, const double* sigma, double vmax,
                         lbm_levelset_info_t* info, void* stream);
 
 /* Run exactly nsteps more adjoint steps from the current adjoint state. */

@@ -16,47 +16,45 @@ Readings taken here (the text leaves them open):
   then phi_new is clamped to [-1, 1] (the range of Eq. 13);
 * J'_W is divided by s = mean |J'_W| over the design domain (K scale free);
 * lap is the 7-point Laplacian (5-point in 2D) in lattice units on the
-  design nodes; a neighbour outside the design domain enters with the fixed
-  phase of its node: +1 for fluid nodes and ports, -1 for walls; a
-  neighbour outside the box or on a mirror layer counts as the node itself
-  (no flux);
+  design nodes; a neighbour that is not a design node (or lies outside the
+  box) counts as the node itself: no flux out of the design domain;
 * lambda uses lap of the current phi;
+* an anisotropic sigma (Sec. 3.3.4: a diagonal matrix) weights each axis'
+  second difference by its own coefficient;
 * G is the fluid fraction of the design domain (phi >= 0) minus V_max.
-The node kinds are those of the mask: DESIGN 0, FLUID 1, INLET 2, OUTLET 3,
-WALL 4, HEATED 5, SYM 6.
+kinds are the node kinds of the mask (DESIGN = 0).
 """
 import numpy as np
 import scipy.sparse
 import scipy.sparse.linalg
 
-_DESIGN, _SYM = 0, 6
-_FLUID_LIKE = (1, 2, 3)    # fixed phase +1
-_SOLID_LIKE = (4, 5)       # fixed phase -1
-_OFFSETS = ((0, 0, -1), (0, 0, 1), (0, -1, 0), (0, 1, 0), (-1, 0, 0), (1, 0, 0))
+_DESIGN = 0
+# (offset, axis): axis 0 x, 1 y, 2 z
+_OFFSETS = (((0, 0, -1), 0), ((0, 0, 1), 0), ((0, -1, 0), 1), ((0, 1, 0), 1),
+            ((-1, 0, 0), 2), ((1, 0, 0), 2))
 
 
-def _neighbours(kinds, z, y, x):
-    """(kind, index) of the 6 axis neighbours of a node that lie inside the
-    box and are not mirror-layer nodes."""
+def _sigma3(sigma):
+    s = np.broadcast_to(np.asarray(sigma, dtype=np.float64), (3,))
+    return tuple(float(v) for v in s)
+
+
+def _design_neighbours(kinds, z, y, x):
+    """(index, axis) of the axis neighbours of a node that are design nodes."""
     nz, ny, nx = kinds.shape
     out = []
-    for dz, dy, dx in _OFFSETS:
+    for (dz, dy, dx), ax in _OFFSETS:
         zz, yy, xx = z + dz, y + dy, x + dx
-        if not (0 <= zz < nz and 0 <= yy < ny and 0 <= xx < nx):
-            continue
-        k = int(kinds[zz, yy, xx])
-        if k == _SYM:
-            continue
-        out.append((k, (zz, yy, xx)))
+        if 0 <= zz < nz and 0 <= yy < ny and 0 <= xx < nx and kinds[zz, yy, xx] == _DESIGN:
+            out.append(((zz, yy, xx), ax))
     return out
 
 
-def fixed_phase(kind):
-    return 1.0 if kind in _FLUID_LIKE else -1.0
-
-
-def laplacian(phi, kinds):
-    """Laplacian of phi [nz, ny, nx] on the design nodes (0 elsewhere)."""
+def laplacian(phi, kinds, sigma=1.0):
+    """sigma-weighted Laplacian sum_a sigma_a d_aa phi of phi [nz, ny, nx] on
+    the design nodes (0 elsewhere); sigma a scalar or (sigma_x, sigma_y,
+    sigma_z)."""
+    sg = _sigma3(sigma)
     phi = np.asarray(phi, dtype=np.float64)
     out = np.zeros_like(phi)
     nz, ny, nx = phi.shape
@@ -66,47 +64,42 @@ def laplacian(phi, kinds):
                 if kinds[z, y, x] != _DESIGN:
                     continue
                 c = phi[z, y, x]
-                s = 0.0
-                for k, idx in _neighbours(kinds, z, y, x):
-                    v = phi[idx] if k == _DESIGN else fixed_phase(k)
-                    s += v - c
-                out[z, y, x] = s
+                out[z, y, x] = sum(sg[ax] * (phi[idx] - c)
+                                   for idx, ax in _design_neighbours(kinds, z, y, x))
     return out
 
 
-def implicit_matrix(kinds, a):
-    """The system of the semi-implicit step over the design nodes:
-    A = I - a lap restricted to design unknowns (CSR, in the order of
-    np.flatnonzero(kinds == DESIGN)) and b, the fixed-phase neighbours'
-    contribution a * sum v, so that A phi_new = rhs + b."""
+def implicit_matrix(kinds, K, sigma):
+    """The matrix of the semi-implicit step over the design nodes,
+    A = I - K lap_sigma restricted to design unknowns (CSR, in the order of
+    np.flatnonzero(kinds == DESIGN))."""
+    sg = _sigma3(sigma)
     d = np.asarray(kinds) == _DESIGN
     ids = -np.ones(kinds.shape, dtype=np.int64)
     nodes = np.argwhere(d)
     ids[d] = np.arange(len(nodes))
     rows, cols, vals = [], [], []
-    b = np.zeros(len(nodes))
     for r, (z, y, x) in enumerate(nodes):
         diag = 1.0
-        for k, idx in _neighbours(kinds, z, y, x):
-            diag += a
-            if k == _DESIGN:
-                rows.append(r)
-                cols.append(ids[idx])
-                vals.append(-a)
-            else:
-                b[r] += a * fixed_phase(k)
+        for idx, ax in _design_neighbours(kinds, z, y, x):
+            rows.append(r)
+            cols.append(ids[idx])
+            vals.append(-K * sg[ax])
+            diag += K * sg[ax]
         rows.append(r)
         cols.append(r)
         vals.append(diag)
-    A = scipy.sparse.csr_matrix((vals, (rows, cols)), shape=(len(nodes), len(nodes)))
-    return A, b
+    return scipy.sparse.csr_matrix((vals, (rows, cols)), shape=(len(nodes), len(nodes)))
 
 
 def levelset_update(phi, dJ, kinds, K, sigma, vmax):
     """One design update: returns (phi_new, alpha, info) with info the
     lambda of Eq. (67), the fluid fraction before the step, G and the scale
-    of J'.  sigma is in lattice units.  Non-design entries of phi_new copy
-    phi; alpha is returned on the design nodes only (others 0)."""
+    of J'.  sigma (lattice units) is a scalar or per axis (sigma_x, sigma_y,
+    sigma_z): the anisotropic regularisation of Sec. 3.3.4, sigma lap
+    becoming sum_a sigma_a d_aa.  Non-design entries of phi_new copy phi;
+    alpha is returned on the design nodes only (others 0)."""
+    sg = _sigma3(sigma)
     phi = np.asarray(phi, dtype=np.float64)
     dJ = np.asarray(dJ, dtype=np.float64)
     kinds = np.asarray(kinds)
@@ -115,13 +108,13 @@ def levelset_update(phi, dJ, kinds, K, sigma, vmax):
     scale = np.abs(dJ[d]).sum() / nd
     volume = float((phi[d] >= 0.0).sum()) / nd
     G = volume - vmax
-    lap = laplacian(phi, kinds)
+    lap = laplacian(phi, kinds, sg)
     Jn = dJ / scale if scale > 0 else np.zeros_like(dJ)
-    lam = np.exp(G) * np.abs(Jn[d] - sigma * lap[d]).sum() / nd
+    lam = np.exp(G) * np.abs(Jn[d] - lap[d]).sum() / nd
     rhs = phi[d] - K * (Jn[d] + lam)
-    if sigma > 0.0:
-        A, b = implicit_matrix(kinds, K * sigma)
-        sol = scipy.sparse.linalg.spsolve(A.tocsc(), rhs + b)
+    if max(sg) > 0.0:
+        A = implicit_matrix(kinds, K, sg)
+        sol = scipy.sparse.linalg.spsolve(A.tocsc(), rhs)
     else:
         sol = rhs
     phi_new = phi.copy()

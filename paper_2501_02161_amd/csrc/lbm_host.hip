@@ -687,18 +687,20 @@ int lbm_adjoint_resume(lbm_problem_t* p, const float* gamma, const float* drho, 
 }
 
 int lbm_levelset_update(lbm_problem_t* p, const float* phi, float* phi_out, const float* dJ,
-                        float* gamma, double K, double sigma, double vmax,
+                        float* gamma, double K, const double* sigma, double vmax,
                         lbm_levelset_info_t* info, void* stream) {
   last_error().clear();
   int rc = check_bound(p);
   if (rc) return rc;
-  if (!phi || !phi_out || !dJ || !gamma) return fail(LBM_EINVAL, "null field pointer");
+  if (!phi || !phi_out || !dJ || !gamma || !sigma) return fail(LBM_EINVAL, "null pointer");
   if (phi == phi_out) return fail(LBM_EINVAL, "phi and phi_out must differ (stencil)");
-  if (!(K > 0.0) || !(sigma >= 0.0) || !(vmax > 0.0 && vmax <= 1.0))
+  if (!(K > 0.0) || !(sigma[0] >= 0.0) || !(sigma[1] >= 0.0) || !(sigma[2] >= 0.0) ||
+      !(vmax > 0.0 && vmax <= 1.0))
     return fail(LBM_EINVAL, "need K > 0, sigma >= 0, 0 < vmax <= 1");
   if (p->n_design == 0) return fail(LBM_EINVAL, "the problem has no design nodes");
   DeviceGuard guard(p->dev);
   hipStream_t s = (hipStream_t)stream;
+  const float sg[3] = {(float)sigma[0], (float)sigma[1], (float)sigma[2]};
   HIPCHK(launch_levelset_stats(phi, dJ, p->flags, p->partials, p->kp, s));
   rc = read_sums(p, 2, s);
   if (rc) return rc;
@@ -706,25 +708,26 @@ int lbm_levelset_update(lbm_problem_t* p, const float* phi, float* phi_out, cons
   const double volume = p->pinned[1] / p->n_design; // fluid fraction (phi >= 0, Eq. 15)
   const double G = volume - vmax;                     // volume constraint of Eq. (10)
   const float inv_scale = scale > 0.0 ? (float)(1.0 / scale) : 0.0f;
-  HIPCHK(launch_levelset_lambda(phi, dJ, p->flags, inv_scale, (float)sigma, p->partials, p->kp, s));
+  HIPCHK(launch_levelset_lambda(phi, dJ, p->flags, inv_scale, sg, p->partials, p->kp, s));
   rc = read_sums(p, 1, s);
   if (rc) return rc;
   const double lambda = std::exp(G) * p->pinned[0] / p->n_design;  // Eq. (67)
-  // Semi-implicit step (I - K sigma lap) phi_new = phi - K (J'/scale + lambda),
+  // Semi-implicit step (I - K lap_sigma) phi_new = phi - K (J'/scale + lambda),
   // solved by red-black Gauss-Seidel.  The Jacobi iteration of this diagonally
-  // dominant system contracts by rho = 6a / (1 + 6a) (a = K sigma) per sweep;
-  // red-black ordering squares that, so the sweep count brings the error
-  // below 1e-8 of the starting guess's.
-  const double a = K * sigma;
+  // dominant system contracts by rho = b / (1 + b) per sweep, b = 2 K (sigma_x +
+  // sigma_y + sigma_z) bounding K times any row's neighbour weight; red-black
+  // ordering squares that, so the sweep count brings the error below 1e-8 of
+  // the starting guess's.
+  const double b = 2.0 * K * (sigma[0] + sigma[1] + sigma[2]);
   int sweeps = 0;
-  if (a > 0.0) {
-    const double rho = 6.0 * a / (1.0 + 6.0 * a);
+  if (b > 0.0) {
+    const double rho = b / (1.0 + b);
     const double n_sw = std::ceil(std::log(1e-8) / (2.0 * std::log(rho))) + 8.0;
     if (!(n_sw <= 100000.0)) return fail(LBM_EINVAL, "K * sigma too large for the level-set solve");
     sweeps = (int)n_sw;
   }
   HIPCHK(launch_levelset_update(phi, phi_out, dJ, p->flags, gamma, inv_scale, (float)K, (float)lambda,
-                                (float)a, sweeps, p->kp, s));
+                                sg, sweeps, p->kp, s));
   if (info) {
     info->lambda = lambda;
     info->volume = volume;

@@ -136,14 +136,15 @@ hipError_t launch_fill(float* p, size_t count, hipStream_t s);
 hipError_t launch_levelset_stats(const float* phi, const float* dJ, const uint8_t* flags,
                                  double* partials, const KParams& P, hipStream_t s);
 hipError_t launch_levelset_lambda(const float* phi, const float* dJ, const uint8_t* flags,
-                                  float inv_scale, float sigma, double* partials, const KParams& P,
-                                  hipStream_t s);
+                                  float inv_scale, const float* sigma, double* partials,
+                                  const KParams& P, hipStream_t s);
 // Semi-implicit step: r = phi - K (J'/scale + lambda) into phi_out, `sweeps`
-// red-black Gauss-Seidel sweeps of (I - a lap) x = r in place (a = K sigma),
-// then the clamp and gamma = (phi_out >= 0).
+// red-black Gauss-Seidel sweeps of (I - K lap_sigma) x = r in place
+// (sigma[3]: per-axis coefficients, host array), then the clamp and
+// gamma = (phi_out >= 0).
 hipError_t launch_levelset_update(const float* phi, float* phi_out, const float* dJ,
                                   const uint8_t* flags, float* gamma, float inv_scale, float K,
-                                  float lambda, float a, int sweeps, const KParams& P,
+                                  float lambda, const float* sigma, int sweeps, const KParams& P,
                                   hipStream_t s);
 // Adds the first collision's heat source to a zero-filled thermal state
 // (no-op without heat generation).

@@ -568,7 +568,7 @@ __device__ __forceinline__ void adjoint_tile(const AdjArgs& A, int blk) {
         });
       }
     } else {
-      const float ux = A.u[n], uy = A.u[P.N + n], uz = A.u[2 * P.N + n];
+      const float ux = A.u[n], uy = A.u[P.N + n], uz = (L::Q == 9) ? 0.0f : A.u[2 * P.N + n];  // 2D: no z component
       float gam = 1.0f;
       if (kind == K_DESIGN) gam = A.gamma[n];
       const float chi = (kind == K_DESIGN) ? chi_of(gam, P) : 1.0f;
@@ -692,7 +692,7 @@ __global__ __launch_bounds__(kBlock) void k_sensitivity(SensArgs A) {
       const int x = n % P.nx, t = n / P.nx, y = t % P.ny, z = t / P.ny;
       const Nbr nb = make_nbr(x, y, z, P);
       const Mirror mr = mirror_of(x, y, z, P);
-      const float ux = A.u[n], uy = A.u[P.N + n], uz = A.u[2 * P.N + n];
+      const float ux = A.u[n], uy = A.u[P.N + n], uz = (L::Q == 9) ? 0.0f : A.u[2 * P.N + n];  // 2D: no z component
       const float gam = A.gamma[n];
       const float chi = chi_of(gam, P);
       const float qg = P.qb + gam;
@@ -1005,43 +1005,44 @@ __global__ void k_fill(float* __restrict__ p, size_t count) {
 // ---------------------------------------------------------------------------
 // ---------------------------------------------------------------------------
 // Level-set update of the design (Eqs. 14, 15, 67) on the design nodes.
-// Laplacian: 7-point stencil (5-point in 2D) in lattice units; a neighbour
-// that is not a design node enters with the fixed phase of its node (+1 for
-// fluid nodes and ports, -1 for walls); a neighbour outside the box or on a
-// mirror layer counts as the node itself (no flux).
+// Laplacian: 7-point stencil (5-point in 2D) in lattice units over design
+// nodes; a neighbour that is not a design node (or lies outside the box)
+// counts as the node itself (no flux out of the design domain).
 // ---------------------------------------------------------------------------
-// Sum over the counted neighbours of their value (design: phi, else the
-// fixed phase), and their number.
+// sigma-weighted sum of the design neighbours' values and of their weights
+// (sigma_x for the x neighbours, ...; the anisotropic regularisation of
+// Sec. 3.3.4, all equal for the isotropic one).
 struct LsNbr {
   float s;
-  int cnt;
+  float w;
 };
 __device__ __forceinline__ LsNbr levelset_neighbours(const float* __restrict__ phi,
                                                      const uint8_t* __restrict__ flags, int n,
+                                                     float sx, float sy, float sz,
                                                      const KParams& P) {
   const int x = n % P.nx, t = n / P.nx, y = t % P.ny, z = t / P.ny;
-  LsNbr r{0.f, 0};
-  auto add = [&](bool inside, int m) {
-    if (!inside) return;
-    const int k = flags[m] & 7;
-    if (k == K_SYM) return;
-    r.s += (k == K_DESIGN) ? phi[m] : (k >= K_WALL ? -1.0f : 1.0f);
-    ++r.cnt;
+  LsNbr r{0.f, 0.f};
+  auto add = [&](bool inside, int m, float sg) {
+    if (!inside || (flags[m] & 7) != K_DESIGN) return;
+    r.s += sg * phi[m];
+    r.w += sg;
   };
-  add(x > 0, n - 1);
-  add(x < P.nx - 1, n + 1);
-  add(y > 0, n - P.nx);
-  add(y < P.ny - 1, n + P.nx);
-  add(z > 0, n - P.plane);
-  add(z < P.nz - 1, n + P.plane);
+  add(x > 0, n - 1, sx);
+  add(x < P.nx - 1, n + 1, sx);
+  add(y > 0, n - P.nx, sy);
+  add(y < P.ny - 1, n + P.nx, sy);
+  add(z > 0, n - P.plane, sz);
+  add(z < P.nz - 1, n + P.plane, sz);
   return r;
 }
 
+// sum_a sigma_a d_aa phi at a design node
 __device__ __forceinline__ float levelset_laplacian(const float* __restrict__ phi,
                                                     const uint8_t* __restrict__ flags, int n,
+                                                    float sx, float sy, float sz,
                                                     const KParams& P) {
-  const LsNbr r = levelset_neighbours(phi, flags, n, P);
-  return r.s - float(r.cnt) * phi[n];
+  const LsNbr r = levelset_neighbours(phi, flags, n, sx, sy, sz, P);
+  return r.s - r.w * phi[n];
 }
 
 // Pass 1: sum |J'| and the fluid count (phi >= 0) over design nodes.
@@ -1063,13 +1064,13 @@ __global__ __launch_bounds__(kBlock) void k_levelset_stats(const float* __restri
 __global__ __launch_bounds__(kBlock) void k_levelset_lambda(const float* __restrict__ phi,
                                                             const float* __restrict__ dJ,
                                                             const uint8_t* __restrict__ flags,
-                                                            float inv_scale, float sigma,
-                                                            double* __restrict__ partials,
+                                                            float inv_scale, float sx, float sy,
+                                                            float sz, double* __restrict__ partials,
                                                             KParams P) {
   const int n = blockIdx.x * kBlock + threadIdx.x;
   double acc[1] = {0.0};
   if (n < P.N && (flags[n] & 7) == K_DESIGN)
-    acc[0] = fabs((double)(dJ[n] * inv_scale - sigma * levelset_laplacian(phi, flags, n, P)));
+    acc[0] = fabs((double)(dJ[n] * inv_scale - levelset_laplacian(phi, flags, n, sx, sy, sz, P)));
   block_reduce_store<1>(acc, partials + blockIdx.x);
 }
 
@@ -1087,22 +1088,24 @@ __global__ __launch_bounds__(kBlock) void k_levelset_rhs(const float* __restrict
   phi_out[n] = d ? phi[n] - K * (dJ[n] * inv_scale + lambda) : phi[n];
 }
 
-// One half-sweep of red-black Gauss-Seidel on (1 + a cnt) x - a sum(nbr) = r
-// (the step (I - K sigma lap) phi_new = r, a = K sigma), in place on x over
-// the design nodes of parity `color` ((x + y + z) mod 2).
+// One half-sweep of red-black Gauss-Seidel on (1 + K w) x - K s = r (the
+// step (I - K sigma lap) phi_new = r with the sigma-weighted neighbour sum s
+// and weight w), in place on x over the design nodes of parity `color`
+// ((x + y + z) mod 2).
 __global__ __launch_bounds__(kBlock) void k_levelset_sweep(const float* __restrict__ phi,
                                                            float* __restrict__ xs,
                                                            const float* __restrict__ dJ,
                                                            const uint8_t* __restrict__ flags,
                                                            float inv_scale, float K, float lambda,
-                                                           float a, int color, KParams P) {
+                                                           float sx, float sy, float sz, int color,
+                                                           KParams P) {
   const int n = blockIdx.x * kBlock + threadIdx.x;
   if (n >= P.N || (flags[n] & 7) != K_DESIGN) return;
   const int x = n % P.nx, t = n / P.nx, y = t % P.ny, z = t / P.ny;
   if (((x + y + z) & 1) != color) return;
-  const LsNbr r = levelset_neighbours(xs, flags, n, P);
+  const LsNbr r = levelset_neighbours(xs, flags, n, sx, sy, sz, P);
   const float rhs = phi[n] - K * (dJ[n] * inv_scale + lambda);
-  xs[n] = (rhs + a * r.s) / (1.0f + a * float(r.cnt));
+  xs[n] = (rhs + K * r.s) / (1.0f + K * r.w);
 }
 
 // Last pass: clamp to [-1, 1] (Eq. 13) and gamma = 1 where phi >= 0, else 0
@@ -1123,22 +1126,22 @@ hipError_t launch_levelset_stats(const float* phi, const float* dJ, const uint8_
   return hipGetLastError();
 }
 hipError_t launch_levelset_lambda(const float* phi, const float* dJ, const uint8_t* flags,
-                                  float inv_scale, float sigma, double* partials, const KParams& P,
-                                  hipStream_t s) {
+                                  float inv_scale, const float* sigma, double* partials,
+                                  const KParams& P, hipStream_t s) {
   hipLaunchKernelGGL(k_levelset_lambda, dim3(P.nblk), dim3(kBlock), 0, s, phi, dJ, flags, inv_scale,
-                     sigma, partials, P);
+                     sigma[0], sigma[1], sigma[2], partials, P);
   return hipGetLastError();
 }
 hipError_t launch_levelset_update(const float* phi, float* phi_out, const float* dJ,
                                   const uint8_t* flags, float* gamma, float inv_scale, float K,
-                                  float lambda, float a, int sweeps, const KParams& P,
+                                  float lambda, const float* sigma, int sweeps, const KParams& P,
                                   hipStream_t s) {
   const dim3 g(P.nblk), b(kBlock);
   hipLaunchKernelGGL(k_levelset_rhs, g, b, 0, s, phi, phi_out, dJ, flags, inv_scale, K, lambda, P);
   for (int it = 0; it < sweeps; ++it)
     for (int color = 0; color < 2; ++color)
       hipLaunchKernelGGL(k_levelset_sweep, g, b, 0, s, phi, phi_out, dJ, flags, inv_scale, K,
-                         lambda, a, color, P);
+                         lambda, sigma[0], sigma[1], sigma[2], color, P);
   hipLaunchKernelGGL(k_levelset_finish, g, b, 0, s, phi_out, flags, gamma, P);
   return hipGetLastError();
 }

@@ -117,7 +117,7 @@ def load_library(path: str = LIB_PATH):
     lib.lbm_forward_resume.restype = c_int
     lib.lbm_adjoint_resume.argtypes = [P, P, P, P, P, POINTER(lbm_info_t), P]
     lib.lbm_adjoint_resume.restype = c_int
-    lib.lbm_levelset_update.argtypes = [P, P, P, P, P, c_double, c_double, c_double,
+    lib.lbm_levelset_update.argtypes = [P, P, P, P, P, c_double, POINTER(c_double), c_double,
                                         POINTER(lbm_levelset_info_t), P]
     lib.lbm_levelset_update.restype = c_int
     lib.lbm_thermal_resolve.argtypes = [P, P, P, P, POINTER(lbm_info_t), P]
@@ -242,9 +242,12 @@ def lbm_adjoint_resume(p, gamma, drho, u, T, stream=None) -> lbm_info_t:
 
 
 def lbm_levelset_update(p, phi, phi_out, dJ, gamma, K, sigma, vmax, stream=None) -> dict:
+    """sigma: a scalar or the per-axis coefficients (sigma_x, sigma_y, sigma_z)."""
+    import numpy as np
     info = lbm_levelset_info_t()
+    sg = (c_double * 3)(*np.broadcast_to(np.asarray(sigma, dtype=np.float64), (3,)).tolist())
     _check(load_library().lbm_levelset_update(p, _ptr(phi), _ptr(phi_out), _ptr(dJ), _ptr(gamma),
-                                              float(K), float(sigma), float(vmax), byref(info),
+                                              float(K), sg, float(vmax), byref(info),
                                               _stream(stream)))
     return {"lambda": info.lambda_, "volume": info.volume, "G": info.G, "scale": info.scale}
 

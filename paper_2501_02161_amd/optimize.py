@@ -31,16 +31,17 @@ def design_length(spec) -> int:
 
 class LevelSetOptimizer:
     """sigma is the dimensionless regularisation coefficient of Eq. (14) on
-    the length L of the design domain (its longest side): the library gets
-    sigma L^2 in lattice units."""
+    the length L of the design domain (its longest side), a scalar or per
+    axis (sigma_x, sigma_y, sigma_z) for the anisotropic regularisation of
+    Sec. 3.3.4: the library gets sigma L^2 in lattice units."""
 
-    def __init__(self, spec, K: float = 0.1, sigma: float = 1e-3, vmax: float = 0.3,
-                 device="cuda:0"):
+    def __init__(self, spec, K: float = 0.1, sigma=1e-3, vmax: float = 0.3, device="cuda:0"):
         self.spec = spec
         self.problem = lbm.Problem(spec, device=device)
-        self.K, self.sigma, self.vmax = float(K), float(sigma), float(vmax)
+        self.K, self.vmax = float(K), float(vmax)
+        self.sigma = tuple(np.broadcast_to(np.asarray(sigma, dtype=np.float64), (3,)).tolist())
         self.L = design_length(spec)
-        self.sigma_lattice = self.sigma * self.L ** 2
+        self.sigma_lattice = tuple(v * self.L ** 2 for v in self.sigma)
         self.device = self.problem.device
         design = (np.asarray(spec.mask).reshape(spec.nz, spec.ny, spec.nx) & 7) == 0
         g0 = np.where(design, 1.0, np.asarray(spec.gamma, dtype=np.float64).reshape(design.shape))

@@ -26,30 +26,53 @@ def _device():
     yield
 
 
-@pytest.mark.parametrize("sigma", [0.0, 2.0, 60.0])
-def test_levelset_update_parity(sigma):
-    """sigma in lattice units: 0 (no diffusion), 2 (K sigma 0.4, a few dozen
-    sweeps) and 60 (K sigma 12, hundreds of sweeps); the design domain
-    touches walls, the inlet and the outlet (fixed phases)."""
-    w = W.pipe_bend_3d(n=24, port=6)
+LS_CASES = {
+    # name: (workload, sigma in lattice units, K, smooth level set)
+    "explicit": (lambda: W.pipe_bend_3d(n=24, port=6), 0.0, 0.2, False),
+    "walls_ports": (lambda: W.pipe_bend_3d(n=24, port=6), 2.0, 0.2, False),
+    "walls_ports_smooth": (lambda: W.pipe_bend_3d(n=24, port=6), 20.0, 0.02, True),
+    "many_sweeps": (lambda: W.periodic_box(24, 3, 0.5), 120.0, 0.1, True),
+    # sigma_z = 10 sigma_x, the anisotropic regularisation of Sec. 3.3.4
+    "anisotropic": (lambda: W.pipe_bend_3d(n=24, port=6), (2.0, 2.0, 20.0), 0.02, True),
+}
+
+
+@pytest.mark.parametrize("name", list(LS_CASES))
+def test_levelset_update_parity(name):
+    """K sigma from 0 (no diffusion) over 0.4 (a few dozen sweeps; the design
+    domain touches walls, the inlet and the outlet, no flux there) to 12
+    (several hundred sweeps); the smooth cases keep the step off the clamp so
+    that the solve itself is compared."""
+    make, sigma, K, smooth = LS_CASES[name]
+    w = make()
     p = lbm.Problem(w, device="cuda:0")
     kinds = w.mask & 7
     design = kinds == W.DESIGN
-    rng = np.random.default_rng(11)
-    phi = np.where(design, rng.uniform(-1, 1, design.shape), 0.0).astype(np.float32)
-    dJ = np.where(design, rng.normal(size=design.shape), 0.0).astype(np.float32)
+    if smooth:
+        phi = 1.6 * (W.smoothed_noise(design.shape, 3.0, 5) - 0.5)
+        dJ = W.smoothed_noise(design.shape, 3.0, 6) - 0.4
+    else:
+        rng = np.random.default_rng(11)
+        phi = rng.uniform(-1, 1, design.shape)
+        dJ = rng.normal(size=design.shape)
+    phi = np.where(design, phi, 0.0).astype(np.float32)
+    dJ = np.where(design, dJ, 0.0).astype(np.float32)
     gam = np.ones(design.shape, dtype=np.float32)
     t = lambda a: torch.tensor(a, device="cuda:0").contiguous()
     phi_d, dJ_d, g_d = t(phi), t(dJ), t(gam)
     out = torch.empty_like(phi_d)
-    info = lbm.lbm_levelset_update(p.h, phi_d, out, dJ_d, g_d, 0.2, sigma, 0.35)
+    info = lbm.lbm_levelset_update(p.h, phi_d, out, dJ_d, g_d, K, sigma, 0.35)
     torch.cuda.synchronize()
     ref_phi, ref_alpha, ref = levelset_update(phi.astype(np.float64), dJ.astype(np.float64),
-                                              kinds, 0.2, sigma, 0.35)
+                                              kinds, K, sigma, 0.35)
     got = out.cpu().numpy()
     g = g_d.cpu().numpy()
-    print(f"[levelset] sigma {sigma}: phi err {rel(got[design], ref_phi[design]):.2e} "
-          f"lambda {info['lambda']:.9g} vs {ref['lambda']:.9g}", flush=True)
+    unclamped = float(np.mean(np.abs(ref_phi[design]) < 1.0))
+    print(f"[levelset] {name}: K sigma {K * np.max(sigma):g}, unclamped {unclamped:.3f}, phi err "
+          f"{rel(got[design], ref_phi[design]):.2e} lambda {info['lambda']:.9g} vs "
+          f"{ref['lambda']:.9g}", flush=True)
+    if smooth:
+        assert unclamped > 0.9
     assert rel(got[design], ref_phi[design]) < 1e-5
     assert np.array_equal(got[~design], phi[~design])
     assert info["volume"] == ref["volume"] and abs(info["G"] - ref["G"]) < 1e-15

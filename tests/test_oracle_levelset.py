@@ -1,6 +1,6 @@
 """Pins of the oracle's level-set update (Eqs. 13-15, 67), independent of the
 update's own arithmetic: the stencil on fields whose Laplacian is known and
-at fixed-phase neighbours, the implicit system against the loop stencil
+next to non-design nodes (no flux), the implicit system against the loop stencil
 applied to unit vectors, the step against Eq. (14) evaluated with the loop
 stencil, and closed forms on uniform inputs."""
 import numpy as np
@@ -23,47 +23,48 @@ def test_laplacian_of_quadratic_is_exact():
     lap = laplacian(phi, k)
     inner = (slice(1, -1),) * 3
     assert np.allclose(lap[inner], 1.0 - 0.5 + 0.25, atol=1e-12)
+    # sum_a sigma_a d_aa phi with phi_xx = 1, phi_yy = -0.5, phi_zz = 0.25
+    lap3 = laplacian(phi, k, (2.0, 3.0, 4.0))
+    assert np.allclose(lap3[inner], 2.0 * 1.0 - 3.0 * 0.5 + 4.0 * 0.25, atol=1e-12)
     # a box face counts as the node itself: a constant field has no Laplacian
     assert np.all(laplacian(np.full(phi.shape, 0.3), k) == 0.0)
 
 
-def test_fixed_phase_neighbours():
+def test_no_flux_to_non_design_nodes():
     k = np.full((3, 3, 5), D, dtype=np.uint8)
-    k[:, :, 0] = W_          # a wall at x = 0: phase -1
-    k[:, :, 4] = F           # fluid at x = 4: phase +1
-    k[2] = S                 # a mirror layer at z = 2: counts as the node itself
-    phi = np.zeros(k.shape)
-    phi[k == D] = 0.25
+    k[:, :, 0] = W_
+    k[:, :, 4] = F
+    k[2] = S
+    phi = np.where(k == D, 0.25, 0.0)
+    phi[1, 1, 2] = 1.0
     lap = laplacian(phi, k)
-    assert np.isclose(lap[1, 1, 1], -1.25)       # wall neighbour: -1 - 0.25
-    assert np.isclose(lap[1, 1, 3], 0.75)        # fluid neighbour: 1 - 0.25
-    assert np.isclose(lap[1, 1, 2], 0.0)
-    assert np.isclose(lap[0, 1, 1], -1.25)       # box face below, design above
-    for kind, ph in ((I, 1.0), (O, 1.0), (H, -1.0)):
+    # non-design neighbours (whatever their phase) and box faces count as
+    # the node itself
+    assert np.isclose(lap[1, 1, 1], 0.75) and np.isclose(lap[1, 1, 3], 0.75)
+    assert np.isclose(lap[1, 1, 2], -3.75)           # 5 design neighbours at 0.25
+    assert np.all(lap[k != D] == 0.0)
+    for kind in (I, O, H, W_, F, S):
         k2 = k.copy()
         k2[:, :, 0] = kind
-        assert np.isclose(laplacian(phi, k2)[1, 1, 1], ph - 0.25)
+        assert np.isclose(laplacian(phi, k2)[1, 1, 1], 0.75)
 
 
 def test_implicit_matrix_is_the_loop_stencil():
-    rng = np.random.default_rng(1)
     k = _box(5)
     k[2, 2, 0] = I
     k[1, 4, 2] = F
     k[3, 3, 3] = W_
     d = k == D
     nodes = np.argwhere(d)
-    a = 0.7
-    A, b = implicit_matrix(k, a)
-    # lap is affine in phi: lap(phi) = L phi + c with c = lap(0)
+    K, sig = 0.7, (0.5, 1.5, 4.0)
+    A = implicit_matrix(k, K, sig)
     zero = np.zeros(k.shape)
-    c = laplacian(zero, k)[d]
+    assert np.all(laplacian(zero, k, sig) == 0.0)      # lap is linear
     for j, idx in enumerate(nodes):
         e = zero.copy()
         e[tuple(idx)] = 1.0
-        col = e[d] - a * (laplacian(e, k)[d] - c)
+        col = e[d] - K * laplacian(e, k, sig)[d]
         assert np.allclose(A[:, j].toarray().ravel(), col, atol=1e-15)
-    assert np.allclose(b, a * c, atol=1e-15)
     assert np.allclose(A.toarray(), A.toarray().T)
 
 
@@ -85,12 +86,20 @@ def test_step_satisfies_eq14():
     lhs = (new[d] - phi[d]) / K
     rhs = -(dJ[d] / s + info["lambda"]) + sigma * laplacian(new, k)[d]
     assert np.allclose(lhs, rhs, atol=1e-10)
+    # anisotropic: sigma_z = 10 sigma_x as in Sec. 3.3.4
+    sig = (sigma, sigma, 10 * sigma)
+    new3, _, info3 = levelset_update(phi, dJ, k, K, sig, vmax)
+    lam3 = np.exp(info3["G"]) * np.abs(dJ[d] / s - laplacian(phi, k, sig)[d]).mean()
+    assert np.isclose(info3["lambda"], lam3, rtol=1e-14)
+    lhs3 = (new3[d] - phi[d]) / K
+    rhs3 = -(dJ[d] / s + info3["lambda"]) + laplacian(new3, k, sig)[d]
+    assert np.allclose(lhs3, rhs3, atol=1e-10)
     assert np.array_equal(alpha[d], (new[d] >= 0).astype(float))
     assert np.array_equal(new[~d], phi[~d])
 
 
 def test_lambda_closed_form_and_uniform_step():
-    k = np.zeros((6, 6, 6), dtype=np.uint8)       # all design: no fixed phases
+    k = np.zeros((6, 6, 6), dtype=np.uint8)       # all design
     d = k == D
     phi = np.full(k.shape, 0.2)
     dJ = np.full(k.shape, 2.0)                     # uniform sensitivity

@@ -160,6 +160,9 @@ constexpr int mirror_dir() {
 struct Mirror {
   bool x, y, z;
 };
+// Problems without mirror planes are compiled with MIR = false, which makes
+// every Mirror constant false and folds the reflection selects away.
+__device__ __forceinline__ bool has_mirror(const KParams& P) { return (P.sx | P.sy | P.sz) != 0; }
 __device__ __forceinline__ Mirror mirror_of(int x, int y, int z, const KParams& P) {
   Mirror m;
   m.x = P.sx && x == P.nx - 2;
@@ -347,7 +350,7 @@ __device__ __forceinline__ void block_reduce_store(double (&acc)[NV], double* __
 // node's velocity.  DIAG additionally writes the macroscopic fields, the
 // thermal non-equilibrium populations and the residual partial sums.
 // ---------------------------------------------------------------------------
-template <class L, bool THERMAL, bool DIAG>
+template <class L, bool MIR, bool THERMAL, bool DIAG>
 __device__ __forceinline__ void forward_tile(const FwdArgs& A, int blk) {
   const KParams& P = A.P;
   const int n = blk * kBlock + threadIdx.x;
@@ -355,7 +358,7 @@ __device__ __forceinline__ void forward_tile(const FwdArgs& A, int blk) {
   if (n < P.N) {
     const int x = n % P.nx, t = n / P.nx, y = t % P.ny, z = t / P.ny;
     const Nbr nb = make_nbr(x, y, z, P);
-    const Mirror mr = mirror_of(x, y, z, P);
+    const Mirror mr = MIR ? mirror_of(x, y, z, P) : Mirror{false, false, false};
     const unsigned fl = A.flags[n];
     const int kind = fl & 7, nc = (fl >> 3) & 7;
     float h[L::Q];
@@ -481,9 +484,9 @@ __device__ __forceinline__ void forward_tile(const FwdArgs& A, int blk) {
   if constexpr (DIAG) block_reduce_store<kRedFwd>(acc, A.partials + (size_t)blk * kRedFwd);
 }
 
-template <class L, bool THERMAL, bool DIAG>
+template <class L, bool MIR, bool THERMAL, bool DIAG>
 __global__ __launch_bounds__(kBlock) void k_forward(FwdArgs A) {
-  forward_tile<L, THERMAL, DIAG>(A, remap_block(blockIdx.x, A.P));
+  forward_tile<L, MIR, THERMAL, DIAG>(A, remap_block(blockIdx.x, A.P));
 }
 
 // ---------------------------------------------------------------------------
@@ -497,7 +500,7 @@ __global__ __launch_bounds__(kBlock) void k_forward(FwdArgs A) {
 // the coupling from the thermal lattice adds e_i.W, W = 4 T/(tau_g rho0) sum w b e,
 // and the thermal transpose is (1 - 1/tau_g) b_i + (1/tau_g) sum w b (1 + 4 e.u).
 // ---------------------------------------------------------------------------
-template <class L, bool THERMAL, int OBJ, bool DIAG, bool CONT = false>
+template <class L, bool MIR, bool THERMAL, int OBJ, bool DIAG, bool CONT = false>
 __device__ __forceinline__ void adjoint_tile(const AdjArgs& A, int blk) {
   static_assert(!(CONT && THERMAL), "the continuous variant is for the flow lattice");
   const KParams& P = A.P;
@@ -506,7 +509,7 @@ __device__ __forceinline__ void adjoint_tile(const AdjArgs& A, int blk) {
   if (n < P.N) {
     const int x = n % P.nx, t = n / P.nx, y = t % P.ny, z = t / P.ny;
     const Nbr nb = make_nbr(x, y, z, P);
-    const Mirror mr = mirror_of(x, y, z, P);
+    const Mirror mr = MIR ? mirror_of(x, y, z, P) : Mirror{false, false, false};
     const unsigned fl = A.flags[n];
     const int kind = fl & 7, nc = (fl >> 3) & 7;
     float a[L::Q];
@@ -665,9 +668,9 @@ __device__ __forceinline__ void adjoint_tile(const AdjArgs& A, int blk) {
   if constexpr (DIAG) block_reduce_store<kRedAdj>(acc, A.partials + (size_t)blk * kRedAdj);
 }
 
-template <class L, bool THERMAL, int OBJ, bool DIAG, bool CONT = false>
+template <class L, bool MIR, bool THERMAL, int OBJ, bool DIAG, bool CONT = false>
 __global__ __launch_bounds__(kBlock) void k_adjoint(AdjArgs A) {
-  adjoint_tile<L, THERMAL, OBJ, DIAG, CONT>(A, remap_block(blockIdx.x, A.P));
+  adjoint_tile<L, MIR, THERMAL, OBJ, DIAG, CONT>(A, remap_block(blockIdx.x, A.P));
 }
 
 // ---------------------------------------------------------------------------
@@ -678,7 +681,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(AdjArgs A) {
 // + beta_max (1 - T) sum_i w_i b_i (and + beta_max (1 - T) for J = -sum Q).
 // Non-design nodes get 0.
 // ---------------------------------------------------------------------------
-template <class L, bool THERMAL>
+template <class L, bool MIR, bool THERMAL>
 __global__ __launch_bounds__(kBlock) void k_sensitivity(SensArgs A) {
   const KParams& P = A.P;
   const int blk = remap_block(blockIdx.x, P);
@@ -691,7 +694,7 @@ __global__ __launch_bounds__(kBlock) void k_sensitivity(SensArgs A) {
     if (kind == K_DESIGN) {
       const int x = n % P.nx, t = n / P.nx, y = t % P.ny, z = t / P.ny;
       const Nbr nb = make_nbr(x, y, z, P);
-      const Mirror mr = mirror_of(x, y, z, P);
+      const Mirror mr = MIR ? mirror_of(x, y, z, P) : Mirror{false, false, false};
       const float ux = A.u[n], uy = A.u[P.N + n], uz = (L::Q == 9) ? 0.0f : A.u[2 * P.N + n];  // 2D: no z component
       const float gam = A.gamma[n];
       const float chi = chi_of(gam, P);
@@ -848,7 +851,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize_slots(const SlotDev* __rest
 // the slot's forward or adjoint step on that tile, with the same tile code as
 // the single-problem kernels, so a slot computes bit for bit what it would
 // alone.
-template <class L, bool THERMAL, int OBJ>
+template <class L, bool MIR, bool THERMAL, int OBJ>
 __device__ __forceinline__ void batch_tile(const SlotDev& S, int blk, int k, bool diag) {
   const bool odd = (k & 1) != 0;
   if (S.phase == 1) {
@@ -859,8 +862,8 @@ __device__ __forceinline__ void batch_tile(const SlotDev& S, int blk, int k, boo
       A.gin = S.fa.gout;
       A.gout = const_cast<float*>(S.fa.gin);
     }
-    if (diag) forward_tile<L, THERMAL, true>(A, blk);
-    else forward_tile<L, THERMAL, false>(A, blk);
+    if (diag) forward_tile<L, MIR, THERMAL, true>(A, blk);
+    else forward_tile<L, MIR, THERMAL, false>(A, blk);
   } else {
     AdjArgs A = S.aa;
     if (odd) {
@@ -871,13 +874,13 @@ __device__ __forceinline__ void batch_tile(const SlotDev& S, int blk, int k, boo
     }
     if constexpr (!THERMAL) {
       if (A.P.cont) {
-        if (diag) adjoint_tile<L, THERMAL, OBJ, true, true>(A, blk);
-        else adjoint_tile<L, THERMAL, OBJ, false, true>(A, blk);
+        if (diag) adjoint_tile<L, MIR, THERMAL, OBJ, true, true>(A, blk);
+        else adjoint_tile<L, MIR, THERMAL, OBJ, false, true>(A, blk);
         return;
       }
     }
-    if (diag) adjoint_tile<L, THERMAL, OBJ, true>(A, blk);
-    else adjoint_tile<L, THERMAL, OBJ, false>(A, blk);
+    if (diag) adjoint_tile<L, MIR, THERMAL, OBJ, true>(A, blk);
+    else adjoint_tile<L, MIR, THERMAL, OBJ, false>(A, blk);
   }
 }
 
@@ -899,13 +902,16 @@ __global__ __launch_bounds__(kBlock) void k_batch(const Tile* __restrict__ tiles
   const int k = launch - S.start;
   if (S.phase == 0 || k < 0 || k >= S.max_steps) return;  // uniform over the block
   const bool diag = (S.check > 0 && (k + 1) % S.check == 0) || (k + 1 == S.max_steps);
+  const bool mir = has_mirror(S.fa.P);
   if constexpr (!THERMAL) {
     if (S.fa.P.q == 9) {
-      batch_tile<Q9, THERMAL, OBJ>(S, tl.blk, k, diag);
+      if (mir) batch_tile<Q9, true, THERMAL, OBJ>(S, tl.blk, k, diag);
+      else batch_tile<Q9, false, THERMAL, OBJ>(S, tl.blk, k, diag);
       return;
     }
   }
-  batch_tile<Q19, THERMAL, OBJ>(S, tl.blk, k, diag);
+  if (mir) batch_tile<Q19, true, THERMAL, OBJ>(S, tl.blk, k, diag);
+  else batch_tile<Q19, false, THERMAL, OBJ>(S, tl.blk, k, diag);
 }
 
 __global__ void k_advance(int* base, int q) {
@@ -918,7 +924,7 @@ __global__ void k_advance(int* base, int q) {
 // populations from (u, T) only.  Same pull, boundary rules and collision as
 // the coupled kernel; DIAG writes g - g_eq and the mean-T partial sums.
 // ---------------------------------------------------------------------------
-template <bool DIAG>
+template <bool DIAG, bool MIR>
 __global__ __launch_bounds__(kBlock) void k_thermal(ThermArgs A) {
   const KParams& P = A.P;
   const int blk = remap_block(blockIdx.x, P);
@@ -927,7 +933,7 @@ __global__ __launch_bounds__(kBlock) void k_thermal(ThermArgs A) {
   if (n < P.N) {
     const int x = n % P.nx, t = n / P.nx, y = t % P.ny, z = t / P.ny;
     const Nbr nb = make_nbr(x, y, z, P);
-    const Mirror mr = mirror_of(x, y, z, P);
+    const Mirror mr = MIR ? mirror_of(x, y, z, P) : Mirror{false, false, false};
     const unsigned fl = A.flags[n];
     const int kind = fl & 7, nc = (fl >> 3) & 7;
     float k[7];
@@ -1189,8 +1195,13 @@ static void launch_step(K kern, int nblk, const A& a, hipStream_t s, hipEvent_t 
 
 template <class L, bool TH>
 static void fwd_dispatch(const FwdArgs& a, bool diag, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
-  if (diag) launch_step(k_forward<L, TH, true>, a.P.nblk, a, s, ev0, ev1);
-  else launch_step(k_forward<L, TH, false>, a.P.nblk, a, s, ev0, ev1);
+  if ((a.P.sx | a.P.sy | a.P.sz) != 0) {
+    if (diag) launch_step(k_forward<L, true, TH, true>, a.P.nblk, a, s, ev0, ev1);
+    else launch_step(k_forward<L, true, TH, false>, a.P.nblk, a, s, ev0, ev1);
+  } else {
+    if (diag) launch_step(k_forward<L, false, TH, true>, a.P.nblk, a, s, ev0, ev1);
+    else launch_step(k_forward<L, false, TH, false>, a.P.nblk, a, s, ev0, ev1);
+  }
 }
 
 hipError_t launch_forward(const FwdArgs& a, bool thermal, bool diag, hipStream_t s, hipEvent_t ev0,
@@ -1201,17 +1212,23 @@ hipError_t launch_forward(const FwdArgs& a, bool thermal, bool diag, hipStream_t
   return hipGetLastError();
 }
 
-template <class L, bool TH, int OBJ>
-static void adj_dispatch(const AdjArgs& a, bool diag, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+template <class L, bool MIR, bool TH, int OBJ>
+static void adj_launch(const AdjArgs& a, bool diag, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   if constexpr (!TH) {
     if (a.P.cont) {
-      if (diag) launch_step(k_adjoint<L, TH, OBJ, true, true>, a.P.nblk, a, s, ev0, ev1);
-      else launch_step(k_adjoint<L, TH, OBJ, false, true>, a.P.nblk, a, s, ev0, ev1);
+      if (diag) launch_step(k_adjoint<L, MIR, TH, OBJ, true, true>, a.P.nblk, a, s, ev0, ev1);
+      else launch_step(k_adjoint<L, MIR, TH, OBJ, false, true>, a.P.nblk, a, s, ev0, ev1);
       return;
     }
   }
-  if (diag) launch_step(k_adjoint<L, TH, OBJ, true>, a.P.nblk, a, s, ev0, ev1);
-  else launch_step(k_adjoint<L, TH, OBJ, false>, a.P.nblk, a, s, ev0, ev1);
+  if (diag) launch_step(k_adjoint<L, MIR, TH, OBJ, true>, a.P.nblk, a, s, ev0, ev1);
+  else launch_step(k_adjoint<L, MIR, TH, OBJ, false>, a.P.nblk, a, s, ev0, ev1);
+}
+
+template <class L, bool TH, int OBJ>
+static void adj_dispatch(const AdjArgs& a, bool diag, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+  if ((a.P.sx | a.P.sy | a.P.sz) != 0) adj_launch<L, true, TH, OBJ>(a, diag, s, ev0, ev1);
+  else adj_launch<L, false, TH, OBJ>(a, diag, s, ev0, ev1);
 }
 
 template <class L>
@@ -1238,17 +1255,29 @@ hipError_t launch_adjoint(const AdjArgs& a, bool thermal, int objective, bool di
   return hipGetLastError();
 }
 
-hipError_t launch_sensitivity(const SensArgs& a, bool thermal, hipStream_t s) {
+template <bool MIR>
+static void sens_launch(const SensArgs& a, bool thermal, hipStream_t s) {
   const dim3 grid(a.P.nblk), block(kBlock);
-  if (thermal) hipLaunchKernelGGL((k_sensitivity<Q19, true>), grid, block, 0, s, a);
-  else if (a.P.q == 9) hipLaunchKernelGGL((k_sensitivity<Q9, false>), grid, block, 0, s, a);
-  else hipLaunchKernelGGL((k_sensitivity<Q19, false>), grid, block, 0, s, a);
+  if (thermal) hipLaunchKernelGGL((k_sensitivity<Q19, MIR, true>), grid, block, 0, s, a);
+  else if (a.P.q == 9) hipLaunchKernelGGL((k_sensitivity<Q9, MIR, false>), grid, block, 0, s, a);
+  else hipLaunchKernelGGL((k_sensitivity<Q19, MIR, false>), grid, block, 0, s, a);
+}
+
+hipError_t launch_sensitivity(const SensArgs& a, bool thermal, hipStream_t s) {
+  if ((a.P.sx | a.P.sy | a.P.sz) != 0) sens_launch<true>(a, thermal, s);
+  else sens_launch<false>(a, thermal, s);
   return hipGetLastError();
 }
 
 hipError_t launch_thermal(const ThermArgs& a, bool diag, hipStream_t s) {
-  if (diag) hipLaunchKernelGGL(k_thermal<true>, dim3(a.P.nblk), dim3(kBlock), 0, s, a);
-  else hipLaunchKernelGGL(k_thermal<false>, dim3(a.P.nblk), dim3(kBlock), 0, s, a);
+  const dim3 grid(a.P.nblk), block(kBlock);
+  if ((a.P.sx | a.P.sy | a.P.sz) != 0) {
+    if (diag) hipLaunchKernelGGL((k_thermal<true, true>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_thermal<false, true>), grid, block, 0, s, a);
+  } else {
+    if (diag) hipLaunchKernelGGL((k_thermal<true, false>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_thermal<false, false>), grid, block, 0, s, a);
+  }
   return hipGetLastError();
 }
 

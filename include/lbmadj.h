@@ -321,7 +321,8 @@ int lbm_lattice(int32_t which, int32_t* e, double* w);
  * Continuous batching of many sensitivity solves (serving).
  *
  * A batch engine holds requests of one kind (thermal flag and objective) on
- * one GPU.  lbm_batch_submit queues a request (descriptor, host mask, host
+ * one GPU; a flow-only engine takes 2D (D2Q9) and 3D requests side by side,
+ * with or without mirror planes, and either adjoint kind.  lbm_batch_submit queues a request (descriptor, host mask, host
  * design field; all copied).  Each lbm_batch_step call first admits queued
  * requests in arrival order while a slot is free and the request's workspace
  * and fields fit in the arena the caller bound (the HBM budget).  Work is

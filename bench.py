@@ -322,8 +322,8 @@ def optimize_leg(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (--gpus {args.gpus} requested); "
-              "a multi-GPU slab decomposition is not part of it.",
+        print(f"bench.py: the library runs on one GPU only (--gpus {args.gpus} requested); "
+              "it has no multi-GPU slab decomposition.",
               file=sys.stderr)
         sys.exit(2)
     if args.profile:

@@ -114,3 +114,50 @@ def test_batch_mixes_2d_and_3d():
         assert r["J"] == res["J"]
         assert r["fwd_steps"] == res["forward"]["steps"]
         assert np.array_equal(r["dJ"], dJ.astype(np.float32))
+
+
+def half_channel_2d(nx=40, ny=12, seed=7):
+    """A 2D channel with a design region, cut at its mid-plane: wall at y = 0,
+    mirror plane before the last y layer (SYM nodes), velocity inlet on
+    x = 0 and pressure outlet on x = nx - 1 over the interior rows."""
+    m = np.full((1, ny, nx), W.DESIGN, dtype=np.uint8)
+    m[0, :, 0] = W.WALL
+    m[0, :, nx - 1] = W.WALL
+    m[0, 0, :] = W.WALL
+    m[0, 1:ny - 1, 0] = W.code(W.INLET, W.NPX)
+    m[0, 1:ny - 1, nx - 1] = W.code(W.OUTLET, W.NMX)
+    m[0, 1:ny - 1, 1:4] = W.FLUID
+    m[0, 1:ny - 1, nx - 4:nx - 1] = W.FLUID
+    m[0, ny - 1, :] = W.SYM
+    gamma = W.smoothed_noise((1, ny, nx), 1.5, seed)
+    return W.Workload(name=f"half_channel_2d_{nx}x{ny}", dim=2, nx=nx, ny=ny, nz=1, thermal=False,
+                      tau=0.7, Re=8.0, L_ref=float(2 * (ny - 2) + 1), objective=W.OBJ_PRESSURE_DROP,
+                      mask=m, gamma=gamma, alpha_max=0.2, q_brink=0.1, max_steps=600, tol=0.0,
+                      check_every=200, symmetric=(False, True, False))
+
+
+def test_mirror_plane_2d():
+    """The 2D lattice with a mirror plane (the reflected pulls on D2Q9):
+    parity with the oracle, and the half domain equals the unfolded full
+    domain on the GPU."""
+    w = half_channel_2d()
+    prob, res = run_gpu(w)
+    o, ref = run_oracle(w, steps=600, tol=0.0, check_every=200)
+    err = compare_solution(w, prob, ref)
+    wf = W.mirror_full(w)
+    pf, rf = run_gpu(wf)
+    k = (w.mask & 7).reshape(w.ny, w.nx)
+    live = k < W.WALL
+    d = k == W.DESIGN
+    uh = pf.u.cpu().numpy()[:, 0, :w.ny - 1, :]
+    u = prob.u.cpu().numpy()[:, 0, :w.ny - 1, :]
+    dJh = pf.dJ.cpu().numpy()[0, :w.ny - 1, :]
+    dJ = prob.dJ.cpu().numpy()[0, :w.ny - 1, :]
+    e_u = rel(u[:, live[:w.ny - 1]], uh[:, live[:w.ny - 1]])
+    # J is a mean over the inlet: equal on both domains, while a cell of the
+    # half domain stands for two mirrored cells of the full one
+    e_dJ = rel(dJ[d[:w.ny - 1]], 2.0 * dJh[d[:w.ny - 1]])
+    print(f"[d2q9] mirror: oracle errors {err}; half vs full u {e_u:.2e} dJ {e_dJ:.2e} "
+          f"J {res['J']:.9g} vs {rf['J']:.9g}", flush=True)
+    assert e_u < 1e-5 and e_dJ < 1e-4
+    assert math.isclose(res["J"], rf["J"], rel_tol=1e-5)

@@ -380,11 +380,16 @@ __device__ __forceinline__ void forward_tile(const FwdArgs& A, int blk) {
         sfor<7>([&](auto I) { k[I] = (I == d) ? own : k[I]; });
       }
     }
+    // post-step populations, stored once after both branches: a wave that
+    // holds wall and fluid nodes then writes each cache line with one store
+    // instead of two partial ones
+    float fo[L::Q];
+    float go[7];
     if (kind >= K_WALL) {
       // full-way bounce-back, no collision (the heated wall adds q_w)
       sfor<L::Q>([&](auto I) {
         constexpr int i = I;
-        A.fout[(size_t)i * P.Np + n] = h[L::opp[i]];
+        fo[i] = h[L::opp[i]];
       });
       if constexpr (THERMAL) {
         float ko[7];
@@ -396,10 +401,7 @@ __device__ __forceinline__ void forward_tile(const FwdArgs& A, int blk) {
           const int d = nc + 1;
           sfor<7>([&](auto I) { ko[I] += (I == d) ? P.q_w : 0.0f; });
         }
-        sfor<7>([&](auto I) {
-          constexpr int i = I;
-          A.gout[(size_t)i * P.Np + n] = ko[i];
-        });
+        sfor<7>([&](auto I) { go[I] = ko[I]; });
       }
       if constexpr (DIAG) {
         A.drho[n] = 0.f;
@@ -446,7 +448,7 @@ __device__ __forceinline__ void forward_tile(const FwdArgs& A, int blk) {
         constexpr int i = I;
         const float eu = float(L::ex[i]) * vx + float(L::ey[i]) * vy + float(L::ez[i]) * vz;
         const float heq = L::w[i] * (drho + P.rho0 * (3.0f * eu + 4.5f * eu * eu - 1.5f * vv));
-        A.fout[(size_t)i * P.Np + n] = h[i] + P.omega * (heq - h[i]);
+        fo[i] = h[i] + P.omega * (heq - h[i]);
       });
       float Tabs = 0.f;
       if constexpr (THERMAL) {
@@ -461,7 +463,7 @@ __device__ __forceinline__ void forward_tile(const FwdArgs& A, int blk) {
           constexpr int i = I;
           const float eu = float(Q7::ex[i]) * ux + float(Q7::ey[i]) * uy + float(Q7::ez[i]) * uz;
           const float keq = Q7::w[i] * (dT + 4.0f * Tabs * eu);
-          A.gout[(size_t)i * P.Np + n] = k[i] + og * (keq - k[i]) + Q7::w[i] * Qh;
+          go[i] = k[i] + og * (keq - k[i]) + Q7::w[i] * Qh;
           if constexpr (DIAG) A.gneq[(size_t)i * P.Np + n] = k[i] - keq;
         });
         if constexpr (DIAG) {
@@ -480,6 +482,8 @@ __device__ __forceinline__ void forward_tile(const FwdArgs& A, int blk) {
         if (fl & kLayerBit) acc[3] = (double)Tabs;
       }
     }
+    sfor<L::Q>([&](auto I) { A.fout[(size_t)I * P.Np + n] = fo[I]; });
+    if constexpr (THERMAL) sfor<7>([&](auto I) { A.gout[(size_t)I * P.Np + n] = go[I]; });
   }
   if constexpr (DIAG) block_reduce_store<kRedFwd>(acc, A.partials + (size_t)blk * kRedFwd);
 }

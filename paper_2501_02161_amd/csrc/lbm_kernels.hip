@@ -563,15 +563,19 @@ __device__ __forceinline__ void adjoint_tile(const AdjArgs& A, int blk) {
         zou_he_continuous<L>(a, normal_of(nc), prs, src);
       }
     }
+    // the new state, stored once after both branches (one full store per
+    // cache line in waves that hold wall and fluid nodes)
+    float c[L::Q];
+    float cg[7];
     if (kind >= K_WALL) {
       sfor<L::Q>([&](auto I) {
         constexpr int i = I;
-        A.aout[(size_t)i * P.Np + n] = a[L::opp[i]];
+        c[i] = a[L::opp[i]];
       });
       if constexpr (THERMAL) {
         sfor<7>([&](auto I) {
           constexpr int i = I;
-          A.bout[(size_t)i * P.Np + n] = b[Q7::opp[i]];
+          cg[i] = b[Q7::opp[i]];
         });
       }
     } else {
@@ -637,7 +641,6 @@ __device__ __forceinline__ void adjoint_tile(const AdjArgs& A, int blk) {
                   Sz = P.omega * Vz + Wz - Gz;
       const float base = P.omega * M0 - csrc;
       const float keep = 1.0f - P.omega;
-      float c[L::Q];
       sfor<L::Q>([&](auto I) {
         constexpr int i = I;
         float v = keep * a[i] + base;
@@ -650,9 +653,7 @@ __device__ __forceinline__ void adjoint_tile(const AdjArgs& A, int blk) {
         if (kind == K_INLET || kind == K_OUTLET)
           zou_he_transpose<L>(c, normal_of(nc), kind == K_OUTLET || P.pin);
       }
-      sfor<L::Q>([&](auto I) { A.aout[(size_t)I * P.Np + n] = c[I]; });
       if constexpr (THERMAL) {
-        float cg[7];
         const float bb = og * Bg - dsrc - bq * Sbw;
         sfor<7>([&](auto I) {
           constexpr int i = I;
@@ -665,9 +666,10 @@ __device__ __forceinline__ void adjoint_tile(const AdjArgs& A, int blk) {
           sfor<7>([&](auto J) { cd += (J == d) ? cg[J] : 0.0f; });
           sfor<7>([&](auto J) { cg[J] = (J == d) ? 0.0f : cg[J] - cd; });
         }
-        sfor<7>([&](auto I) { A.bout[(size_t)I * P.Np + n] = cg[I]; });
       }
     }
+    sfor<L::Q>([&](auto I) { A.aout[(size_t)I * P.Np + n] = c[I]; });
+    if constexpr (THERMAL) sfor<7>([&](auto I) { A.bout[(size_t)I * P.Np + n] = cg[I]; });
   }
   if constexpr (DIAG) block_reduce_store<kRedAdj>(acc, A.partials + (size_t)blk * kRedAdj);
 }
@@ -950,11 +952,10 @@ __global__ __launch_bounds__(kBlock) void k_thermal(ThermArgs A) {
       const float own = A.gin[(size_t)d * P.Np + n];
       sfor<7>([&](auto I) { k[I] = (I == d) ? own : k[I]; });
     }
+    float ko[7];  // stored once after both branches
     if (kind >= K_WALL) {
-      float ko[7];
       sfor<7>([&](auto I) { ko[I] = k[Q7::opp[I]]; });
       if (kind == K_HEATED) sfor<7>([&](auto I) { ko[I] += (I == d) ? P.q_w : 0.0f; });
-      sfor<7>([&](auto I) { A.gout[(size_t)I * P.Np + n] = ko[I]; });
       if constexpr (DIAG) sfor<7>([&](auto I) { A.gneq[(size_t)I * P.Np + n] = 0.f; });
     } else {
       if (kind == K_INLET) {
@@ -974,7 +975,7 @@ __global__ __launch_bounds__(kBlock) void k_thermal(ThermArgs A) {
         constexpr int i = I;
         const float eu = float(Q7::ex[i]) * ux + float(Q7::ey[i]) * uy + float(Q7::ez[i]) * uz;
         const float keq = Q7::w[i] * (dT + 4.0f * Tabs * eu);
-        A.gout[(size_t)i * P.Np + n] = k[i] + og * (keq - k[i]) + Q7::w[i] * Qh;
+        ko[i] = k[i] + og * (keq - k[i]) + Q7::w[i] * Qh;
         if constexpr (DIAG) A.gneq[(size_t)i * P.Np + n] = k[i] - keq;
       });
       if constexpr (DIAG) {
@@ -982,6 +983,7 @@ __global__ __launch_bounds__(kBlock) void k_thermal(ThermArgs A) {
         if (fl & kLayerBit) acc[3] = (double)Tabs;
       }
     }
+    sfor<7>([&](auto I) { A.gout[(size_t)I * P.Np + n] = ko[I]; });
   }
   if constexpr (DIAG) block_reduce_store<kRedFwd>(acc, A.partials + (size_t)blk * kRedFwd);
 }

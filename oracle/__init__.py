@@ -140,7 +140,7 @@ class Oracle:
         return np.ascontiguousarray(np.asarray(gamma).reshape(-1), dtype=dtype)
 
     def lattice(self, which: int = 0):
-        Q = self.Q if which == 0 else 7
+        Q = self.Q if which == 0 else (self.Qg or 7)
         e = np.zeros((Q, 3), dtype=np.int32)
         wt = np.zeros(Q, dtype=np.float64)
         self.lib.orc_lattice(self.h, which, _ptr(e), _ptr(wt))

@@ -102,6 +102,22 @@ Lattice make_d3q19() {
   return L;
 }
 
+// D2Q5 (thermal lattice of a 2D problem): rest and the four axis directions,
+// weights 1/2 and 1/8, so that the lattice sound speed squared is 1/4 as on
+// D3Q7: the same equilibrium w T (1 + 4 e.u) and the same tau_g(D).
+Lattice make_d2q5() {
+  Lattice L;
+  L.Q = 5;
+  const int e[5][3] = {{0, 0, 0}, {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}};
+  for (int i = 0; i < 5; ++i) {
+    for (int a = 0; a < 3; ++a) L.e[i][a] = e[i][a];
+    L.w[i] = (i == 0) ? 0.5 : 0.125;
+  }
+  L.cs2 = 0.25;
+  finish_lattice(L);
+  return L;
+}
+
 Lattice make_d3q7() {
   Lattice L;
   L.Q = 7;
@@ -1065,8 +1081,8 @@ bool build_problem(const OrcConfig& c, const uint8_t* mask, Problem& P, std::str
   P.nz = c.nz;
   P.N = c.nx * c.ny * c.nz;
   if (c.dim == 2) {
-    if (c.nz != 1 || c.thermal) {
-      err = "2D problems need nz == 1 and no thermal lattice";
+    if (c.nz != 1) {
+      err = "2D problems need nz == 1";
       return false;
     }
     P.F = make_d2q9();
@@ -1077,7 +1093,7 @@ bool build_problem(const OrcConfig& c, const uint8_t* mask, Problem& P, std::str
     return false;
   }
   P.thermal = c.thermal != 0;
-  P.G = make_d3q7();
+  P.G = (c.dim == 2) ? make_d2q5() : make_d3q7();
   P.nu = (c.tau - 0.5) / 3.0;
   P.U_peak = (c.L_ref > 0) ? c.Re * P.nu / c.L_ref : 0.0;
   P.Df = (c.Pr > 0) ? P.nu / c.Pr : 0.0;

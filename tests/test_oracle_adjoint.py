@@ -26,6 +26,7 @@ def cases():
         "pipe3d_pressure_drop": W.tiny_pipe_bend_3d(objective=W.OBJ_PRESSURE_DROP),
         "heat_sink": W.tiny_heat_sink(),
         "paper_heat_sink": W.tiny_paper_heat_sink(),
+        "paper_heat_sink_2d": W.tiny_paper_heat_sink_2d(),
     }
 
 

@@ -62,8 +62,9 @@ def test_quarter_domain_equals_unfolded_full_domain(variant):
     assert np.max(np.abs(dq)) > 0
 
 
-def test_heat_generation_decay_closed_form():
-    w = W.periodic_box(6, dim=3, gamma_value=0.0, thermal=True).replace(
+@pytest.mark.parametrize("dim", [2, 3])
+def test_heat_generation_decay_closed_form(dim):
+    w = W.periodic_box(6, dim=dim, gamma_value=0.0, thermal=True).replace(
         beta_max=0.01, objective=W.OBJ_HEATGEN, T_in=0.0)
     o = oracle.Oracle(w)
     f, g = o.init()
@@ -98,3 +99,23 @@ def test_pressure_driven_channel_poiseuille():
     # mass in = mass out (summed axial velocity equal at every section)
     flux = ux[1:nz - 1, 1:nx - 1].sum(axis=0)
     assert np.allclose(flux, flux.mean(), rtol=1e-10)
+
+
+def test_half_domain_equals_unfolded_full_domain_2d():
+    """The 2D heat sink (D2Q9 + D2Q5) on the half domain below its mirror
+    plane reproduces the unfolded full domain: fields, J = -sum Q twice,
+    and dJ/dgamma (a cell of the half is two mirror cells)."""
+    w = W.tiny_paper_heat_sink_2d()
+    wf = W.mirror_full(w)
+    o, of = oracle.Oracle(w), oracle.Oracle(wf)
+    kw = dict(tol=1e-13, check_every=200)
+    h, full = o.solve(fwd_steps=40000, adj_steps=40000, **kw), \
+        of.solve(fwd_steps=40000, adj_steps=40000, **kw)
+    assert h["fwd_status"] == 0 and h["adj_status"] == 0
+    for key in ("rho", "u", "T"):
+        a, b = _quarter(h[key], w), _fold(full[key], w, wf)
+        assert np.max(np.abs(a - b)) <= 1e-12 * max(np.max(np.abs(b)), 1e-30), key
+    assert abs(full["J"] - 2.0 * h["J"]) <= 1e-12 * abs(full["J"])
+    dh, df = _quarter(h["dJ"], w), _fold(full["dJ"], w, wf)
+    assert np.max(np.abs(dh - df)) <= 1e-9 * np.max(np.abs(dh))
+    assert np.max(np.abs(dh)) > 0

@@ -46,11 +46,14 @@ def test_lattice_isotropy(dim):
     # every direction has its opposite
     for i in range(len(wt)):
         assert sum(np.all(e[j] == -e[i]) for j in range(len(wt))) == 1
-    if dim == 3:
-        eg, wg = o.lattice(1)
-        eg = eg.astype(float)
-        assert math.isclose(wg.sum(), 1.0, abs_tol=1e-15)
-        assert np.allclose(np.einsum("i,ia,ib->ab", wg, eg, eg), np.eye(3) / 4.0)
+    # thermal lattice (D3Q7, or D2Q5 on a 2D problem): cs2 = 1/4
+    wth = W.tiny_paper_heat_sink_2d() if dim == 2 else W.tiny_heat_sink()
+    eg, wg = oracle.Oracle(wth).lattice(1)
+    assert len(wg) == (5 if dim == 2 else 7)
+    eg = eg.astype(float)
+    assert math.isclose(wg.sum(), 1.0, abs_tol=1e-15)
+    assert np.allclose(wg @ eg, 0.0, atol=1e-15)
+    assert np.allclose(np.einsum("i,ia,ib->ab", wg, eg, eg)[:dim, :dim], np.eye(dim) / 4.0)
 
 
 # ------------------------------------------------ printed boundary rules
@@ -295,6 +298,23 @@ def test_poiseuille_closed_form(case):
     fluid = (kinds.reshape(shape) < W.WALL)[..., 20:w.nx - 24]
     ut = u[:, 1:].reshape(shape + (2,))[..., 20:w.nx - 24, :][fluid]
     assert np.abs(ut).max() < 1e-9 * U
+
+
+def test_conduction_linear_profile_2d():
+    """The same on D2Q9 + D2Q5: a heated floor row under a Dirichlet top row,
+    exactly linear with slope -q_w / D."""
+    w = W.conduction_column_2d(5, 12, tau=0.8, Pr=0.5, q_w=0.003, T_top=0.25)
+    o = oracle.Oracle(w)
+    r = o.forward(max_steps=200000, tol=1e-15, check_every=500)
+    assert r["status"] == 0
+    rho, u, T = o.macro(r["f"], r["g"])
+    assert np.abs(u).max() < 1e-15
+    D = (w.tau - 0.5) / 3.0 / w.Pr
+    T = T.reshape(w.ny, w.nx)
+    ys = np.arange(1, w.ny)
+    expect = w.T_in + w.q_w / D * (w.ny - 1 - ys)
+    for x in range(1, w.nx - 1):
+        assert np.allclose(T[1:, x], expect, rtol=1e-10, atol=0)
 
 
 def test_conduction_linear_profile():

@@ -374,6 +374,61 @@ def conduction_column(nx: int, ny: int, nz: int, tau: float, Pr: float, q_w: flo
                     gamma=np.ones((nz, ny, nx)), Pr=Pr, q_w=q_w, T_in=T_top, w_dp=0.0)
 
 
+def conduction_column_2d(nx: int, ny: int, tau: float, Pr: float, q_w: float,
+                         T_top: float) -> Workload:
+    """Pure conduction in 2D (D2Q9 + D2Q5): a heated floor (y = 0, heat flux
+    q_w), a zero-velocity inlet on the top row acting as a Dirichlet T_top
+    boundary, adiabatic side walls, fluid inside (no flow)."""
+    m = walled_box(nx, ny, 1, dim=2, interior=FLUID)
+    m[0, 0, 1:nx - 1] = code(HEATED, NPY)
+    m[0, ny - 1, 1:nx - 1] = code(INLET, NMY)
+    return Workload(name=f"conduction_2d_{nx}x{ny}", dim=2, nx=nx, ny=ny, nz=1, thermal=True,
+                    tau=tau, Re=0.0, L_ref=1.0, objective=OBJ_HEATSINK, mask=m,
+                    gamma=np.ones((1, ny, nx)), Pr=Pr, q_w=q_w, T_in=T_top, w_dp=0.0)
+
+
+def paper_heat_sink_2d(nx: int = 512, ny: int = 129, Re: float = 60.0, tau: float = 0.6,
+                       Pr: float = 7.1, beta_max: float = 1e-5, k_ratio: float = 100.0,
+                       alpha_max: float = 0.1, buffer: int = 4, sigma: float = 3.0,
+                       seed: Optional[int] = None, name: Optional[str] = None) -> Workload:
+    """The 2D form of the paper's heat sink (the planform that Sec. 3.3.5
+    designs in 2D and extrudes): D2Q9 flow and D2Q5 heat on the half domain
+    below the mirror plane of the channel, wall at y = 0, SYM nodes on the
+    last row, pressure inlet over x = 0 and outlet over x = nx-1, `buffer`
+    fluid columns after the inlet and before the outlet, the design domain
+    between; heat Q = beta(gamma)(1 - T) in the solid (Eq. 69), J = -sum Q
+    (Eq. 72); Re from Eq. (70) with L the full width between the walls,
+    2 (ny - 2) + 1 nodes."""
+    seed = SEED_BASE + 8 if seed is None else seed
+    m = np.full((1, ny, nx), DESIGN, dtype=np.uint8)
+    m[0, 0, :] = WALL
+    m[0, :, 0] = WALL
+    m[0, :, nx - 1] = WALL
+    m[0, 1:ny - 1, 0] = code(INLET, NPX)
+    m[0, 1:ny - 1, nx - 1] = code(OUTLET, NMX)
+    if buffer > 0:
+        m[0, 1:ny - 1, 1:1 + buffer] = FLUID
+        m[0, 1:ny - 1, nx - 1 - buffer:nx - 1] = FLUID
+    m[0, ny - 1, :] = SYM
+    L = float(2 * (ny - 2) + 1)
+    nu = (tau - 0.5) / 3.0
+    dp = (Re * nu / L) ** 2
+    gamma = smoothed_noise((1, ny, nx), sigma, seed)
+    return Workload(name=name or f"paper_heat_sink_2d_{nx}x{ny}_Re{Re:g}", dim=2, nx=nx, ny=ny,
+                    nz=1, thermal=True, tau=tau, Re=Re, L_ref=L, objective=OBJ_HEATGEN, mask=m,
+                    gamma=gamma, alpha_max=alpha_max, q_brink=0.1, Pr=Pr, k_ratio=k_ratio,
+                    q_ramp=1.0, q_w=0.0, T_in=0.0, w_dp=0.0, seed=seed,
+                    symmetric=(False, True, False), inlet_rho=1.0 + 3.0 * dp, beta_max=beta_max)
+
+
+def tiny_paper_heat_sink_2d(nx: int = 14, ny: int = 7, Re: float = 10.0, tau: float = 0.8,
+                            beta_max: float = 2e-3, seed: int = 11) -> Workload:
+    """A small 2D heat sink of the paper's formulation, for pins."""
+    return paper_heat_sink_2d(nx, ny, Re=Re, tau=tau, Pr=1.0, beta_max=beta_max, alpha_max=0.2,
+                              buffer=1, sigma=1.0, seed=seed,
+                              name=f"tiny_paper_heat_sink_2d_{nx}x{ny}")
+
+
 def tiny_heat_sink(nx: int = 10, ny: int = 8, nz: int = 6, seed: int = 7, Re: float = 5.0,
                    Pr: float = 1.0, tau: float = 0.8, alpha_max: float = 0.2,
                    sigma: float = 1.0) -> Workload:

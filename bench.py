@@ -41,7 +41,7 @@ def bytes_per_node(kernel, w):
     u, T, gamma, flags, and the dissipation source G)."""
     q = 9 if w.nz == 1 else 19          # D2Q9 on a 2D lattice, else D3Q19
     dim = 2 if w.nz == 1 else 3
-    qt = 7 if w.thermal else 0
+    qt = (5 if w.nz == 1 else 7) if w.thermal else 0   # D2Q5 / D3Q7
     if kernel == "forward":
         return (q + qt) * 4 * 2 + 4 + 1
     b = (q + qt) * 4 * 2 + dim * 4 + (4 if w.thermal else 0) + 4 + 1
@@ -59,7 +59,9 @@ def parse():
                     choices=["heat_sink_Re50", "heat_sink_Re200", "heat_sink_Re400",
                              "heat_sink_320x160x80_Re200", "pipe_bend_96", "pipe_bend_96_dp",
                              "paper_heat_sink_Re60", "paper_heat_sink_Re120",
-                             "paper_heat_sink_Re240", "pipe_bend_2d_512", "pipe_bend_2d_2048"])
+                             "paper_heat_sink_Re240", "pipe_bend_2d_512", "pipe_bend_2d_2048",
+                             "paper_heat_sink_2d_Re60", "paper_heat_sink_2d_Re240",
+                             "paper_heat_sink_2d_2048x513_Re60"])
     ap.add_argument("--re", type=float, default=0.0,
                     help="Reynolds number of a pipe-bend workload (0: the workload's own)")
     ap.add_argument("--adjoint", default="discrete", choices=["discrete", "continuous"],
@@ -185,6 +187,11 @@ def make_workload(name, adjoint="discrete", Re=0.0):
         w = W.pipe_bend_3d(objective=obj, **({"Re": Re} if Re > 0 else {}))
         return w.replace(adjoint_kind=kind, name=w.name + ("_dp" if name.endswith("_dp") else "")
                          + (f"_Re{Re:g}" if Re > 0 else "") + ("_continuous" if kind else ""))
+    if name.startswith("paper_heat_sink_2d"):
+        Re = float(name.split("Re")[1])
+        if "2048x513" in name:
+            return W.paper_heat_sink_2d(2048, 513, Re=Re)
+        return W.paper_heat_sink_2d(Re=Re)
     if name.startswith("pipe_bend_2d_"):
         n = int(name.split("_")[3])
         w = W.pipe_bend_2d(n=n, inlet=(n // 8, (23 * n) // 64), outlet=((5 * n) // 8, (55 * n) // 64))
@@ -404,7 +411,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": w.name, "nodes": w.N,
-                   "lattice": "D2Q9" if w.nz == 1 else ("D3Q19+D3Q7" if w.thermal else "D3Q19"),
+                   "lattice": ("D2Q9+D2Q5" if w.thermal else "D2Q9") if w.nz == 1 else
+                              ("D3Q19+D3Q7" if w.thermal else "D3Q19"),
                    "objective": {0: "pressure drop", 1: "viscous dissipation",
                                  2: "mean floor-layer T + 0.1 pressure drop",
                                  3: "heat generated, -sum beta (1 - T)"}[w.objective],

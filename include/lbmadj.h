@@ -8,9 +8,10 @@
  * equilibrium of Eq. (4), extended by the design field as in Eq. (12), and
  * optionally a coupled D3Q7 BGK advection-diffusion lattice for temperature
  * (Eq. 71, with the volumetric source of Eq. 69 when beta_max > 0).  A grid
- * with nz == 1 is a 2D problem on the D2Q9 lattice of Eq. (5) (flow only),
- * for which Eqs. (7), (8) and (58)-(60) are the printed special cases of the
- * generic port rules.  Three calls make the hot path:
+ * with nz == 1 is a 2D problem on the D2Q9 lattice of Eq. (5), for which
+ * Eqs. (7), (8) and (58)-(60) are the printed special cases of the generic
+ * port rules, with a D2Q5 thermal lattice (rest 1/2, axes 1/8, cs2 = 1/4 as
+ * on D3Q7) when thermal.  Three calls make the hot path:
  *
  *   lbm_forward_solve   the steady forward sweep: collision (Eq. 36),
  *                       streaming (Eq. 37), boundary conditions (Eqs. 7-9)
@@ -142,8 +143,8 @@ extern "C" {
 
 typedef struct lbm_desc {
   int32_t nx, ny, nz;      /* grid: nx, ny >= 3; nz >= 3 (D3Q19) or nz == 1   */
-                           /* (2D: D2Q9, flow only, z not symmetric and its  */
-                           /* periodic flag ignored, port normals in x or y) */
+                           /* (2D: D2Q9 + D2Q5, z not symmetric and its      */
+                           /* periodic flag ignored, normals in x or y)      */
   int32_t thermal;         /* 0: flow only; 1: coupled D3Q7 temperature       */
   int32_t periodic[3];     /* 1: periodic streaming along x / y / z           */
   int32_t objective;       /* LBM_OBJ_*                                       */
@@ -292,8 +293,9 @@ int lbm_sensitivity(lbm_problem_t* p, const float* gamma, const float* drho, con
 
 /* Copy a workspace state to device memory dst: which 0 = forward flow
  * populations (Q x N, Q = 19, or 9 on a 2D lattice), 1 = forward thermal
- * (7 x N), 2 = adjoint flow (Q x N), 3 = adjoint thermal (7 x N), 4 = thermal non-equilibrium
- * populations of the last forward state (7 x N).  Populations are
+ * (Qg x N, Qg = 7, or 5 on a 2D lattice), 2 = adjoint flow (Q x N),
+ * 3 = adjoint thermal (Qg x N), 4 = thermal non-equilibrium populations of
+ * the last forward state (Qg x N).  Populations are
  * population-major [q][z][y][x] and stored shifted: f_i - w_i rho0 (forward
  * flow), g_i - w_i T_in (forward thermal); the forward state is the
  * post-collision one, the adjoint state the one after the adjoint boundary
@@ -313,8 +315,8 @@ int lbm_set_kernel_timing(lbm_problem_t* p, int32_t enable);
 int lbm_kernel_timing(lbm_problem_t* p, double* ms, int64_t* launches, int32_t reset);
 
 /* Direction table of the library: which 0 = D3Q19 (19 entries), 1 = D3Q7
- * (7 entries), 2 = D2Q9 (9 entries, e_z = 0); e receives 3 ints per
- * direction, w the weight. */
+ * (7 entries), 2 = D2Q9 (9 entries, e_z = 0), 3 = D2Q5 (5 entries); e
+ * receives 3 ints per direction, w the weight. */
 int lbm_lattice(int32_t which, int32_t* e, double* w);
 
 /* ---------------------------------------------------------------------------

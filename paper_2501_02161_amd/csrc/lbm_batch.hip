@@ -312,7 +312,7 @@ int bind_slot(lbm_batch* b, Slot& s, const Request& r, hipStream_t st) {
   HIPCHK(hipMemcpyAsync(s.gamma, gam, (size_t)p->N * sizeof(float), hipMemcpyHostToDevice, st));
   HIPCHK(launch_fill(p->f[0], (size_t)qf_of(p) * p->Np, st));
   if (th) {
-    HIPCHK(launch_fill(p->g[0], (size_t)7 * p->Np, st));
+    HIPCHK(launch_fill(p->g[0], (size_t)qg_of(p) * p->Np, st));
     HIPCHK(launch_heat_init(p->g[0], s.gamma, p->flags, p->kp, st));
   }
   HIPCHK(hipStreamSynchronize(st));  // the staging is reused
@@ -465,7 +465,7 @@ int after_quantum(lbm_batch* b, int i, Lane& ln) {
     }
     s.J = J;
     HIPCHK(launch_fill(p->a[0], (size_t)qf_of(p) * p->Np, st));
-    if (th) HIPCHK(launch_fill(p->b[0], (size_t)7 * p->Np, st));
+    if (th) HIPCHK(launch_fill(p->b[0], (size_t)qg_of(p) * p->Np, st));
     s.phase = PH_ADJOINT;
     s.steps = 0;
     s.have_prev = false;

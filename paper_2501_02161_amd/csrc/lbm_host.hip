@@ -30,11 +30,12 @@ namespace lbmadj {
 
 bool thermal_of(const lbm_problem* p) { return p->d.thermal != 0; }
 int qf_of(const lbm_problem* p) { return p->d.nz == 1 ? 9 : 19; }
+int qg_of(const lbm_problem* p) { return p->d.nz == 1 ? 5 : 7; }
 
 Layout layout_of(const lbm_problem* p) {
   Layout L{};
   size_t off = 0;
-  const size_t pf = (size_t)qf_of(p) * p->Np * sizeof(float), pg = (size_t)7 * p->Np * sizeof(float);
+  const size_t pf = (size_t)qf_of(p) * p->Np * sizeof(float), pg = (size_t)qg_of(p) * p->Np * sizeof(float);
   const bool th = thermal_of(p);
   auto take = [&](size_t bytes) {
     const size_t o = off;
@@ -59,7 +60,6 @@ int validate_and_setup(lbm_problem* p, const lbm_desc_t& d, const uint8_t* mask)
   if (d.nx < 3 || d.ny < 3 || (d.nz < 3 && d.nz != 1))
     return fail(LBM_EINVAL, "nx, ny must be >= 3 and nz >= 3 (D3Q19) or nz == 1 (D2Q9)");
   const bool two_d = d.nz == 1;
-  if (two_d && d.thermal) return fail(LBM_EINVAL, "the 2D lattice (nz == 1) is flow only");
   if (two_d && d.symmetric[2])
     return fail(LBM_EINVAL, "the 2D lattice (nz == 1) has no z axis to be symmetric");
   const long long N = (long long)d.nx * d.ny * d.nz;
@@ -607,7 +607,7 @@ int lbm_forward_solve(lbm_problem_t* p, const float* gamma, float* drho, float* 
   p->fcur = 0;
   HIPCHK(launch_fill(p->f[0], (size_t)qf_of(p) * p->Np, s));
   if (thermal_of(p)) {
-    HIPCHK(launch_fill(p->g[0], (size_t)7 * p->Np, s));
+    HIPCHK(launch_fill(p->g[0], (size_t)qg_of(p) * p->Np, s));
     HIPCHK(launch_heat_init(p->g[0], gamma, p->flags, p->kp, s));
   }
   return run_forward(p, gamma, drho, u, T, p->d.max_steps, p->d.check_every, p->d.tol, s, info);
@@ -641,7 +641,7 @@ int lbm_adjoint_solve(lbm_problem_t* p, const float* gamma, const float* drho, c
   if (p->d.objective == LBM_OBJ_DISSIPATION)
     HIPCHK(launch_dissipation_source(u, gamma, p->flags, p->G, p->kp, s));
   HIPCHK(launch_fill(p->a[0], (size_t)qf_of(p) * p->Np, s));
-  if (thermal_of(p)) HIPCHK(launch_fill(p->b[0], (size_t)7 * p->Np, s));
+  if (thermal_of(p)) HIPCHK(launch_fill(p->b[0], (size_t)qg_of(p) * p->Np, s));
   return run_adjoint(p, gamma, u, T, p->d.max_steps, p->d.check_every, p->d.tol, s, info);
 }
 
@@ -791,10 +791,10 @@ int lbm_copy_state(const lbm_problem_t* p, int32_t which, float* dst, void* stre
   int q = 0;
   switch (which) {
     case 0: src = p->f[p->fcur]; q = qf_of(p); break;
-    case 1: src = p->g[p->fcur]; q = 7; break;
+    case 1: src = p->g[p->fcur]; q = qg_of(p); break;
     case 2: src = p->a[p->acur]; q = qf_of(p); break;
-    case 3: src = p->b[p->acur]; q = 7; break;
-    case 4: src = p->gneq; q = 7; break;
+    case 3: src = p->b[p->acur]; q = qg_of(p); break;
+    case 4: src = p->gneq; q = qg_of(p); break;
     default: return fail(LBM_EINVAL, "which must be 0..4");
   }
   if (!src) return fail(LBM_EINVAL, "no such state for this problem");
@@ -834,7 +834,7 @@ int lbm_kernel_timing(lbm_problem_t* p, double* ms, int64_t* launches, int32_t r
 }
 
 int lbm_lattice(int32_t which, int32_t* e, double* w) {
-  if (!e || !w || which < 0 || which > 2) return fail(LBM_EINVAL, "bad arguments");
+  if (!e || !w || which < 0 || which > 3) return fail(LBM_EINVAL, "bad arguments");
   lattice_table(which, e, w);
   return LBM_OK;
 }

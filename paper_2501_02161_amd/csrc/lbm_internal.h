@@ -71,9 +71,9 @@ struct FwdArgs {
 };
 
 struct AdjArgs {
-  const float* ain;     // adjoint flow state (after the adjoint BC), 19 x Np
+  const float* ain;     // adjoint flow state (after the adjoint BC), 19 (2D: 9) x Np
   float* aout;
-  const float* bin;     // adjoint thermal state, 7 x Np
+  const float* bin;     // adjoint thermal state, 7 (2D: 5) x Np
   float* bout;
   const uint8_t* flags;
   const float* gamma;
@@ -91,7 +91,7 @@ struct SensArgs {
   const float* gamma;
   const float* u;
   const float* T;
-  const float* gneq;    // 7 x Np
+  const float* gneq;    // 7 (2D: 5) x Np
   float* dJ;
   double* partials;
   int objective;
@@ -106,7 +106,7 @@ struct ThermArgs {
   const float* gamma;
   const float* u;       // [3][N] frozen velocity
   const float* T;       // [N] initial temperature (init kernel only)
-  float* gneq;          // 7 x Np (diagnostic step)
+  float* gneq;          // 7 (2D: 5) x Np (diagnostic step)
   double* partials;
   KParams P;
 };
@@ -253,6 +253,7 @@ struct Layout {
 Layout layout_of(const lbm_problem* p);
 bool thermal_of(const lbm_problem* p);
 int qf_of(const lbm_problem* p);  // flow directions: 19, or 9 for a 2D lattice
+int qg_of(const lbm_problem* p);  // thermal directions: 7, or 5 for a 2D lattice
 int sens_buffer(const lbm_problem* p);  // adjoint buffer the sensitivity contracts
 int validate_and_setup(lbm_problem* p, const lbm_desc_t& d, const uint8_t* mask);
 FwdArgs fwd_args(lbm_problem* p, const float* gamma, float* drho, float* u, float* T);

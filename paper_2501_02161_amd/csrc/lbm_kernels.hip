@@ -60,6 +60,25 @@ struct Q7 {
   static constexpr int opp[7] = {0, 2, 1, 4, 3, 6, 5};
   static constexpr float w[7] = {0.25f, 0.125f, 0.125f, 0.125f, 0.125f, 0.125f, 0.125f};
 };
+// D2Q5, the thermal lattice of a 2D problem: rest 1/2, axes 1/8, so that
+// cs2 = 1/4 as on D3Q7 (same equilibrium and relaxation time).
+struct Q5 {
+  static constexpr int Q = 5;
+  static constexpr int ex[5] = {0, 1, -1, 0, 0};
+  static constexpr int ey[5] = {0, 0, 0, 1, -1};
+  static constexpr int ez[5] = {0, 0, 0, 0, 0};
+  static constexpr int opp[5] = {0, 2, 1, 4, 3};
+  static constexpr float w[5] = {0.5f, 0.125f, 0.125f, 0.125f, 0.125f};
+};
+// Thermal lattice paired with a flow lattice.
+template <class L>
+struct ThermalOf {
+  using type = Q7;
+};
+template <>
+struct ThermalOf<Q9> {
+  using type = Q5;
+};
 
 template <int V>
 using ic = std::integral_constant<int, V>;
@@ -352,6 +371,7 @@ __device__ __forceinline__ void block_reduce_store(double (&acc)[NV], double* __
 // ---------------------------------------------------------------------------
 template <class L, bool MIR, bool THERMAL, bool DIAG>
 __device__ __forceinline__ void forward_tile(const FwdArgs& A, int blk) {
+  using G = typename ThermalOf<L>::type;  // thermal lattice
   const KParams& P = A.P;
   const int n = blk * kBlock + threadIdx.x;
   double acc[kRedFwd] = {0.0, 0.0, 0.0, 0.0};
@@ -366,25 +386,25 @@ __device__ __forceinline__ void forward_tile(const FwdArgs& A, int blk) {
       constexpr int i = I;
       h[i] = load_pull<L, i, -L::ex[i], -L::ey[i], -L::ez[i]>(A.fin, P.Np, nb, n, mr);
     });
-    float k[7];
+    float k[G::Q];
     if constexpr (THERMAL) {
-      sfor<7>([&](auto I) {
+      sfor<G::Q>([&](auto I) {
         constexpr int i = I;
-        k[i] = load_pull<Q7, i, -Q7::ex[i], -Q7::ey[i], -Q7::ez[i]>(A.gin, P.Np, nb, n, mr);
+        k[i] = load_pull<G, i, -G::ex[i], -G::ey[i], -G::ez[i]>(A.gin, P.Np, nb, n, mr);
       });
       // zero-gradient outflow: the population along the inward normal takes
       // the node's own post-collision value
       if (kind == K_OUTLET) {
         const int d = nc + 1;
         const float own = A.gin[(size_t)d * P.Np + n];
-        sfor<7>([&](auto I) { k[I] = (I == d) ? own : k[I]; });
+        sfor<G::Q>([&](auto I) { k[I] = (I == d) ? own : k[I]; });
       }
     }
     // post-step populations, stored once after both branches: a wave that
     // holds wall and fluid nodes then writes each cache line with one store
     // instead of two partial ones
     float fo[L::Q];
-    float go[7];
+    float go[G::Q];
     if (kind >= K_WALL) {
       // full-way bounce-back, no collision (the heated wall adds q_w)
       sfor<L::Q>([&](auto I) {
@@ -392,16 +412,16 @@ __device__ __forceinline__ void forward_tile(const FwdArgs& A, int blk) {
         fo[i] = h[L::opp[i]];
       });
       if constexpr (THERMAL) {
-        float ko[7];
-        sfor<7>([&](auto I) {
+        float ko[G::Q];
+        sfor<G::Q>([&](auto I) {
           constexpr int i = I;
-          ko[i] = k[Q7::opp[i]];
+          ko[i] = k[G::opp[i]];
         });
         if (kind == K_HEATED) {
           const int d = nc + 1;
-          sfor<7>([&](auto I) { ko[I] += (I == d) ? P.q_w : 0.0f; });
+          sfor<G::Q>([&](auto I) { ko[I] += (I == d) ? P.q_w : 0.0f; });
         }
-        sfor<7>([&](auto I) { go[I] = ko[I]; });
+        sfor<G::Q>([&](auto I) { go[I] = ko[I]; });
       }
       if constexpr (DIAG) {
         A.drho[n] = 0.f;
@@ -410,7 +430,7 @@ __device__ __forceinline__ void forward_tile(const FwdArgs& A, int blk) {
         A.u[2 * P.N + n] = 0.f;
         if constexpr (THERMAL) {
           A.T[n] = 0.f;
-          sfor<7>([&](auto I) { A.gneq[(size_t)I * P.Np + n] = 0.f; });
+          sfor<G::Q>([&](auto I) { A.gneq[(size_t)I * P.Np + n] = 0.f; });
         }
       }
     } else {
@@ -424,8 +444,8 @@ __device__ __forceinline__ void forward_tile(const FwdArgs& A, int blk) {
           // Dirichlet T = T_in by the sum rule on the inward-normal population
           const int d = nc + 1;
           float s = 0.f;
-          sfor<7>([&](auto J) { s += (J == d) ? 0.0f : k[J]; });
-          sfor<7>([&](auto J) { k[J] = (J == d) ? P.dT_in - s : k[J]; });
+          sfor<G::Q>([&](auto J) { s += (J == d) ? 0.0f : k[J]; });
+          sfor<G::Q>([&](auto J) { k[J] = (J == d) ? P.dT_in - s : k[J]; });
         }
       }
       // moments of the post-boundary state (Eq. 6)
@@ -453,17 +473,17 @@ __device__ __forceinline__ void forward_tile(const FwdArgs& A, int blk) {
       float Tabs = 0.f;
       if constexpr (THERMAL) {
         float dT = 0.f;
-        sfor<7>([&](auto I) { dT += k[I]; });
+        sfor<G::Q>([&](auto I) { dT += k[I]; });
         Tabs = P.T_ref + dT;
         const float tg = 0.5f + P.dfc * ((kind == K_DESIGN) ? khat_of(gam, P) : 1.0f);
         const float og = 1.0f / tg;
         // heat generation Q = beta_max (1 - gamma) (1 - T) in the design domain
         const float Qh = (kind == K_DESIGN) ? P.beta * (1.0f - gam) * (1.0f - Tabs) : 0.0f;
-        sfor<7>([&](auto I) {
+        sfor<G::Q>([&](auto I) {
           constexpr int i = I;
-          const float eu = float(Q7::ex[i]) * ux + float(Q7::ey[i]) * uy + float(Q7::ez[i]) * uz;
-          const float keq = Q7::w[i] * (dT + 4.0f * Tabs * eu);
-          go[i] = k[i] + og * (keq - k[i]) + Q7::w[i] * Qh;
+          const float eu = float(G::ex[i]) * ux + float(G::ey[i]) * uy + float(G::ez[i]) * uz;
+          const float keq = G::w[i] * (dT + 4.0f * Tabs * eu);
+          go[i] = k[i] + og * (keq - k[i]) + G::w[i] * Qh;
           if constexpr (DIAG) A.gneq[(size_t)i * P.Np + n] = k[i] - keq;
         });
         if constexpr (DIAG) {
@@ -483,7 +503,7 @@ __device__ __forceinline__ void forward_tile(const FwdArgs& A, int blk) {
       }
     }
     sfor<L::Q>([&](auto I) { A.fout[(size_t)I * P.Np + n] = fo[I]; });
-    if constexpr (THERMAL) sfor<7>([&](auto I) { A.gout[(size_t)I * P.Np + n] = go[I]; });
+    if constexpr (THERMAL) sfor<G::Q>([&](auto I) { A.gout[(size_t)I * P.Np + n] = go[I]; });
   }
   if constexpr (DIAG) block_reduce_store<kRedFwd>(acc, A.partials + (size_t)blk * kRedFwd);
 }
@@ -506,6 +526,7 @@ __global__ __launch_bounds__(kBlock) void k_forward(FwdArgs A) {
 // ---------------------------------------------------------------------------
 template <class L, bool MIR, bool THERMAL, int OBJ, bool DIAG, bool CONT = false>
 __device__ __forceinline__ void adjoint_tile(const AdjArgs& A, int blk) {
+  using G = typename ThermalOf<L>::type;  // thermal lattice
   static_assert(!(CONT && THERMAL), "the continuous variant is for the flow lattice");
   const KParams& P = A.P;
   const int n = blk * kBlock + threadIdx.x;
@@ -521,17 +542,17 @@ __device__ __forceinline__ void adjoint_tile(const AdjArgs& A, int blk) {
       constexpr int i = I;
       a[i] = load_pull<L, i, L::ex[i], L::ey[i], L::ez[i]>(A.ain, P.Np, nb, n, mr);
     });
-    float b[7];
+    float b[G::Q];
     if constexpr (THERMAL) {
-      sfor<7>([&](auto I) {
+      sfor<G::Q>([&](auto I) {
         constexpr int i = I;
-        b[i] = load_pull<Q7, i, Q7::ex[i], Q7::ey[i], Q7::ez[i]>(A.bin, P.Np, nb, n, mr);
+        b[i] = load_pull<G, i, G::ex[i], G::ey[i], G::ez[i]>(A.bin, P.Np, nb, n, mr);
       });
       // transpose of the outflow self-copy
       if (kind == K_OUTLET) {
         const int d = nc + 1;
         const float own = A.bin[(size_t)d * P.Np + n];
-        sfor<7>([&](auto I) { b[I] += (I == d) ? own : 0.0f; });
+        sfor<G::Q>([&](auto I) { b[I] += (I == d) ? own : 0.0f; });
       }
     }
     if constexpr (DIAG) {
@@ -546,7 +567,7 @@ __device__ __forceinline__ void adjoint_tile(const AdjArgs& A, int blk) {
         acc[0] = sqrt((double)mx * mx + (double)my * my + (double)mz * mz);
         if constexpr (THERMAL) {
           float sb = 0.f;
-          sfor<7>([&](auto I) { sb += b[I]; });
+          sfor<G::Q>([&](auto I) { sb += b[I]; });
           acc[1] = fabs((double)sb);
         }
       }
@@ -566,16 +587,16 @@ __device__ __forceinline__ void adjoint_tile(const AdjArgs& A, int blk) {
     // the new state, stored once after both branches (one full store per
     // cache line in waves that hold wall and fluid nodes)
     float c[L::Q];
-    float cg[7];
+    float cg[G::Q];
     if (kind >= K_WALL) {
       sfor<L::Q>([&](auto I) {
         constexpr int i = I;
         c[i] = a[L::opp[i]];
       });
       if constexpr (THERMAL) {
-        sfor<7>([&](auto I) {
+        sfor<G::Q>([&](auto I) {
           constexpr int i = I;
-          cg[i] = b[Q7::opp[i]];
+          cg[i] = b[G::opp[i]];
         });
       }
     } else {
@@ -605,13 +626,13 @@ __device__ __forceinline__ void adjoint_tile(const AdjArgs& A, int blk) {
         const float tg = 0.5f + P.dfc * ((kind == K_DESIGN) ? khat_of(gam, P) : 1.0f);
         og = 1.0f / tg;
         float Sb = 0.f, Mbx = 0.f, Mby = 0.f, Mbz = 0.f;
-        sfor<7>([&](auto I) {
+        sfor<G::Q>([&](auto I) {
           constexpr int i = I;
-          const float wb = Q7::w[i] * b[i];
+          const float wb = G::w[i] * b[i];
           Sb += wb;
-          if constexpr (Q7::ex[i] != 0) Mbx += float(Q7::ex[i]) * wb;
-          if constexpr (Q7::ey[i] != 0) Mby += float(Q7::ey[i]) * wb;
-          if constexpr (Q7::ez[i] != 0) Mbz += float(Q7::ez[i]) * wb;
+          if constexpr (G::ex[i] != 0) Mbx += float(G::ex[i]) * wb;
+          if constexpr (G::ey[i] != 0) Mby += float(G::ey[i]) * wb;
+          if constexpr (G::ez[i] != 0) Mbz += float(G::ez[i]) * wb;
         });
         Bg = Sb + 4.0f * (ux * Mbx + uy * Mby + uz * Mbz);
         Sbw = Sb;
@@ -655,7 +676,7 @@ __device__ __forceinline__ void adjoint_tile(const AdjArgs& A, int blk) {
       }
       if constexpr (THERMAL) {
         const float bb = og * Bg - dsrc - bq * Sbw;
-        sfor<7>([&](auto I) {
+        sfor<G::Q>([&](auto I) {
           constexpr int i = I;
           cg[i] = (1.0f - og) * b[i] + bb;
         });
@@ -663,13 +684,13 @@ __device__ __forceinline__ void adjoint_tile(const AdjArgs& A, int blk) {
           // transpose of the Dirichlet sum rule
           const int d = nc + 1;
           float cd = 0.f;
-          sfor<7>([&](auto J) { cd += (J == d) ? cg[J] : 0.0f; });
-          sfor<7>([&](auto J) { cg[J] = (J == d) ? 0.0f : cg[J] - cd; });
+          sfor<G::Q>([&](auto J) { cd += (J == d) ? cg[J] : 0.0f; });
+          sfor<G::Q>([&](auto J) { cg[J] = (J == d) ? 0.0f : cg[J] - cd; });
         }
       }
     }
     sfor<L::Q>([&](auto I) { A.aout[(size_t)I * P.Np + n] = c[I]; });
-    if constexpr (THERMAL) sfor<7>([&](auto I) { A.bout[(size_t)I * P.Np + n] = cg[I]; });
+    if constexpr (THERMAL) sfor<G::Q>([&](auto I) { A.bout[(size_t)I * P.Np + n] = cg[I]; });
   }
   if constexpr (DIAG) block_reduce_store<kRedAdj>(acc, A.partials + (size_t)blk * kRedAdj);
 }
@@ -689,6 +710,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(AdjArgs A) {
 // ---------------------------------------------------------------------------
 template <class L, bool MIR, bool THERMAL>
 __global__ __launch_bounds__(kBlock) void k_sensitivity(SensArgs A) {
+  using G = typename ThermalOf<L>::type;  // thermal lattice
   const KParams& P = A.P;
   const int blk = remap_block(blockIdx.x, P);
   const int n = blk * kBlock + threadIdx.x;
@@ -722,11 +744,11 @@ __global__ __launch_bounds__(kBlock) void k_sensitivity(SensArgs A) {
         const float tg = 0.5f + P.dfc * kh;
         const float dtg = P.dfc * dkh;
         float sg = 0.f, swb = 0.f;
-        sfor<7>([&](auto I) {
+        sfor<G::Q>([&](auto I) {
           constexpr int i = I;
-          const float b = load_pull<Q7, i, Q7::ex[i], Q7::ey[i], Q7::ez[i]>(A.bin, P.Np, nb, n, mr);
+          const float b = load_pull<G, i, G::ex[i], G::ey[i], G::ez[i]>(A.bin, P.Np, nb, n, mr);
           sg += b * A.gneq[(size_t)i * P.Np + n];
-          swb += Q7::w[i] * b;
+          swb += G::w[i] * b;
         });
         out -= dtg / (tg * tg) * sg;
         // heat generation: d(w_i beta (1 - T))/dgamma = -w_i beta_max (1 - T),
@@ -893,8 +915,8 @@ __device__ __forceinline__ void batch_tile(const SlotDev& S, int blk, int k, boo
 // Ragged-batch step: block -> tile (XCD-contiguous runs of tiles) -> slot ->
 // the slot's forward or adjoint step on that tile, with the same tile code as
 // the single-problem kernels, so a slot computes bit for bit what it would
-// alone.  Flow-only engines take D3Q19 and D2Q9 requests side by side (the
-// lattice is uniform over a block: a tile belongs to one slot).
+// alone.  An engine takes 3D and 2D requests side by side (the lattice is
+// uniform over a block: a tile belongs to one slot).
 template <bool THERMAL, int OBJ>
 __global__ __launch_bounds__(kBlock) void k_batch(const Tile* __restrict__ tiles,
                                                   const SlotDev* __restrict__ slots,
@@ -909,12 +931,10 @@ __global__ __launch_bounds__(kBlock) void k_batch(const Tile* __restrict__ tiles
   if (S.phase == 0 || k < 0 || k >= S.max_steps) return;  // uniform over the block
   const bool diag = (S.check > 0 && (k + 1) % S.check == 0) || (k + 1 == S.max_steps);
   const bool mir = has_mirror(S.fa.P);
-  if constexpr (!THERMAL) {
-    if (S.fa.P.q == 9) {
-      if (mir) batch_tile<Q9, true, THERMAL, OBJ>(S, tl.blk, k, diag);
-      else batch_tile<Q9, false, THERMAL, OBJ>(S, tl.blk, k, diag);
-      return;
-    }
+  if (S.fa.P.q == 9) {
+    if (mir) batch_tile<Q9, true, THERMAL, OBJ>(S, tl.blk, k, diag);
+    else batch_tile<Q9, false, THERMAL, OBJ>(S, tl.blk, k, diag);
+    return;
   }
   if (mir) batch_tile<Q19, true, THERMAL, OBJ>(S, tl.blk, k, diag);
   else batch_tile<Q19, false, THERMAL, OBJ>(S, tl.blk, k, diag);
@@ -930,7 +950,7 @@ __global__ void k_advance(int* base, int q) {
 // populations from (u, T) only.  Same pull, boundary rules and collision as
 // the coupled kernel; DIAG writes g - g_eq and the mean-T partial sums.
 // ---------------------------------------------------------------------------
-template <bool DIAG, bool MIR>
+template <class G, bool DIAG, bool MIR>
 __global__ __launch_bounds__(kBlock) void k_thermal(ThermArgs A) {
   const KParams& P = A.P;
   const int blk = remap_block(blockIdx.x, P);
@@ -942,40 +962,40 @@ __global__ __launch_bounds__(kBlock) void k_thermal(ThermArgs A) {
     const Mirror mr = MIR ? mirror_of(x, y, z, P) : Mirror{false, false, false};
     const unsigned fl = A.flags[n];
     const int kind = fl & 7, nc = (fl >> 3) & 7;
-    float k[7];
-    sfor<7>([&](auto I) {
+    float k[G::Q];
+    sfor<G::Q>([&](auto I) {
       constexpr int i = I;
-      k[i] = load_pull<Q7, i, -Q7::ex[i], -Q7::ey[i], -Q7::ez[i]>(A.gin, P.Np, nb, n, mr);
+      k[i] = load_pull<G, i, -G::ex[i], -G::ey[i], -G::ez[i]>(A.gin, P.Np, nb, n, mr);
     });
     const int d = nc + 1;
     if (kind == K_OUTLET) {
       const float own = A.gin[(size_t)d * P.Np + n];
-      sfor<7>([&](auto I) { k[I] = (I == d) ? own : k[I]; });
+      sfor<G::Q>([&](auto I) { k[I] = (I == d) ? own : k[I]; });
     }
-    float ko[7];  // stored once after both branches
+    float ko[G::Q];  // stored once after both branches
     if (kind >= K_WALL) {
-      sfor<7>([&](auto I) { ko[I] = k[Q7::opp[I]]; });
-      if (kind == K_HEATED) sfor<7>([&](auto I) { ko[I] += (I == d) ? P.q_w : 0.0f; });
-      if constexpr (DIAG) sfor<7>([&](auto I) { A.gneq[(size_t)I * P.Np + n] = 0.f; });
+      sfor<G::Q>([&](auto I) { ko[I] = k[G::opp[I]]; });
+      if (kind == K_HEATED) sfor<G::Q>([&](auto I) { ko[I] += (I == d) ? P.q_w : 0.0f; });
+      if constexpr (DIAG) sfor<G::Q>([&](auto I) { A.gneq[(size_t)I * P.Np + n] = 0.f; });
     } else {
       if (kind == K_INLET) {
         float s = 0.f;
-        sfor<7>([&](auto J) { s += (J == d) ? 0.0f : k[J]; });
-        sfor<7>([&](auto J) { k[J] = (J == d) ? P.dT_in - s : k[J]; });
+        sfor<G::Q>([&](auto J) { s += (J == d) ? 0.0f : k[J]; });
+        sfor<G::Q>([&](auto J) { k[J] = (J == d) ? P.dT_in - s : k[J]; });
       }
       const float ux = A.u[n], uy = A.u[P.N + n], uz = A.u[2 * P.N + n];
       float dT = 0.f;
-      sfor<7>([&](auto I) { dT += k[I]; });
+      sfor<G::Q>([&](auto I) { dT += k[I]; });
       const float Tabs = P.T_ref + dT;
       const float gm = (kind == K_DESIGN) ? A.gamma[n] : 1.0f;
       const float tg = 0.5f + P.dfc * ((kind == K_DESIGN) ? khat_of(gm, P) : 1.0f);
       const float og = 1.0f / tg;
       const float Qh = (kind == K_DESIGN) ? P.beta * (1.0f - gm) * (1.0f - Tabs) : 0.0f;
-      sfor<7>([&](auto I) {
+      sfor<G::Q>([&](auto I) {
         constexpr int i = I;
-        const float eu = float(Q7::ex[i]) * ux + float(Q7::ey[i]) * uy + float(Q7::ez[i]) * uz;
-        const float keq = Q7::w[i] * (dT + 4.0f * Tabs * eu);
-        ko[i] = k[i] + og * (keq - k[i]) + Q7::w[i] * Qh;
+        const float eu = float(G::ex[i]) * ux + float(G::ey[i]) * uy + float(G::ez[i]) * uz;
+        const float keq = G::w[i] * (dT + 4.0f * Tabs * eu);
+        ko[i] = k[i] + og * (keq - k[i]) + G::w[i] * Qh;
         if constexpr (DIAG) A.gneq[(size_t)i * P.Np + n] = k[i] - keq;
       });
       if constexpr (DIAG) {
@@ -983,13 +1003,14 @@ __global__ __launch_bounds__(kBlock) void k_thermal(ThermArgs A) {
         if (fl & kLayerBit) acc[3] = (double)Tabs;
       }
     }
-    sfor<7>([&](auto I) { A.gout[(size_t)I * P.Np + n] = ko[I]; });
+    sfor<G::Q>([&](auto I) { A.gout[(size_t)I * P.Np + n] = ko[I]; });
   }
   if constexpr (DIAG) block_reduce_store<kRedFwd>(acc, A.partials + (size_t)blk * kRedFwd);
 }
 
 // Initial thermal state g = g_eq(T, u) (stored shifted by w T_ref) at
 // non-wall nodes, 0 (that is w T_ref) at walls.
+template <class G>
 __global__ __launch_bounds__(kBlock) void k_thermal_init(ThermArgs A) {
   const KParams& P = A.P;
   const int n = blockIdx.x * kBlock + threadIdx.x;
@@ -997,10 +1018,10 @@ __global__ __launch_bounds__(kBlock) void k_thermal_init(ThermArgs A) {
   const int kind = A.flags[n] & 7;
   const float ux = A.u[n], uy = A.u[P.N + n], uz = A.u[2 * P.N + n];
   const float Tabs = A.T[n];
-  sfor<7>([&](auto I) {
+  sfor<G::Q>([&](auto I) {
     constexpr int i = I;
-    const float eu = float(Q7::ex[i]) * ux + float(Q7::ey[i]) * uy + float(Q7::ez[i]) * uz;
-    const float keq = Q7::w[i] * ((Tabs - P.T_ref) + 4.0f * Tabs * eu);
+    const float eu = float(G::ex[i]) * ux + float(G::ey[i]) * uy + float(G::ez[i]) * uz;
+    const float keq = G::w[i] * ((Tabs - P.T_ref) + 4.0f * Tabs * eu);
     A.gout[(size_t)i * P.Np + n] = (kind >= K_WALL) ? 0.0f : keq;
   });
 }
@@ -1164,6 +1185,7 @@ hipError_t launch_levelset_update(const float* phi, float* phi_out, const float*
 // store post-collision populations, so this makes the stored start the image
 // of the rest state under the collision, as the forward map C -> S -> B from
 // the rest state has it (without a source that collision is the identity).
+template <class G>
 __global__ __launch_bounds__(kBlock) void k_heat_init(float* __restrict__ g,
                                                       const float* __restrict__ gamma,
                                                       const uint8_t* __restrict__ flags,
@@ -1172,14 +1194,15 @@ __global__ __launch_bounds__(kBlock) void k_heat_init(float* __restrict__ g,
   if (n >= P.N) return;
   if ((flags[n] & 7) != K_DESIGN) return;
   const float Q = P.beta * (1.0f - gamma[n]) * (1.0f - P.T_ref);
-  sfor<7>([&](auto I) { g[(size_t)I * P.Np + n] = Q7::w[I] * Q; });
+  sfor<G::Q>([&](auto I) { g[(size_t)I * P.Np + n] = G::w[I] * Q; });
 }
 
 hipError_t launch_heat_init(float* g, const float* gamma, const uint8_t* flags, const KParams& P,
                             hipStream_t s) {
   if (!(P.beta > 0.0f)) return hipSuccess;
-  hipLaunchKernelGGL(k_heat_init, dim3((P.N + kBlock - 1) / kBlock), dim3(kBlock), 0, s, g, gamma,
-                     flags, P);
+  const dim3 grid((P.N + kBlock - 1) / kBlock), block(kBlock);
+  if (P.q == 9) hipLaunchKernelGGL((k_heat_init<Q5>), grid, block, 0, s, g, gamma, flags, P);
+  else hipLaunchKernelGGL((k_heat_init<Q7>), grid, block, 0, s, g, gamma, flags, P);
   return hipGetLastError();
 }
 
@@ -1212,7 +1235,8 @@ static void fwd_dispatch(const FwdArgs& a, bool diag, hipStream_t s, hipEvent_t 
 
 hipError_t launch_forward(const FwdArgs& a, bool thermal, bool diag, hipStream_t s, hipEvent_t ev0,
                           hipEvent_t ev1) {
-  if (thermal) fwd_dispatch<Q19, true>(a, diag, s, ev0, ev1);
+  if (thermal && a.P.q == 9) fwd_dispatch<Q9, true>(a, diag, s, ev0, ev1);
+  else if (thermal) fwd_dispatch<Q19, true>(a, diag, s, ev0, ev1);
   else if (a.P.q == 9) fwd_dispatch<Q9, false>(a, diag, s, ev0, ev1);
   else fwd_dispatch<Q19, false>(a, diag, s, ev0, ev1);
   return hipGetLastError();
@@ -1244,15 +1268,23 @@ static void adj_dispatch_flow(const AdjArgs& a, int objective, bool diag, hipStr
   else adj_dispatch<L, false, OBJ_DISSIPATION>(a, diag, s, ev0, ev1);
 }
 
+template <class L>
+static void adj_dispatch_thermal(const AdjArgs& a, int objective, bool diag, hipStream_t s,
+                                 hipEvent_t ev0, hipEvent_t ev1) {
+  switch (objective) {
+    case OBJ_PRESSURE_DROP: adj_dispatch<L, true, OBJ_PRESSURE_DROP>(a, diag, s, ev0, ev1); break;
+    case OBJ_DISSIPATION: adj_dispatch<L, true, OBJ_DISSIPATION>(a, diag, s, ev0, ev1); break;
+    case OBJ_HEATGEN: adj_dispatch<L, true, OBJ_HEATGEN>(a, diag, s, ev0, ev1); break;
+    default: adj_dispatch<L, true, OBJ_HEATSINK>(a, diag, s, ev0, ev1); break;
+  }
+}
+
 hipError_t launch_adjoint(const AdjArgs& a, bool thermal, int objective, bool diag, hipStream_t s,
                           hipEvent_t ev0, hipEvent_t ev1) {
-  if (thermal) {
-    switch (objective) {
-      case OBJ_PRESSURE_DROP: adj_dispatch<Q19, true, OBJ_PRESSURE_DROP>(a, diag, s, ev0, ev1); break;
-      case OBJ_DISSIPATION: adj_dispatch<Q19, true, OBJ_DISSIPATION>(a, diag, s, ev0, ev1); break;
-      case OBJ_HEATGEN: adj_dispatch<Q19, true, OBJ_HEATGEN>(a, diag, s, ev0, ev1); break;
-      default: adj_dispatch<Q19, true, OBJ_HEATSINK>(a, diag, s, ev0, ev1); break;
-    }
+  if (thermal && a.P.q == 9) {
+    adj_dispatch_thermal<Q9>(a, objective, diag, s, ev0, ev1);
+  } else if (thermal) {
+    adj_dispatch_thermal<Q19>(a, objective, diag, s, ev0, ev1);
   } else if (a.P.q == 9) {
     adj_dispatch_flow<Q9>(a, objective, diag, s, ev0, ev1);
   } else {
@@ -1264,7 +1296,8 @@ hipError_t launch_adjoint(const AdjArgs& a, bool thermal, int objective, bool di
 template <bool MIR>
 static void sens_launch(const SensArgs& a, bool thermal, hipStream_t s) {
   const dim3 grid(a.P.nblk), block(kBlock);
-  if (thermal) hipLaunchKernelGGL((k_sensitivity<Q19, MIR, true>), grid, block, 0, s, a);
+  if (thermal && a.P.q == 9) hipLaunchKernelGGL((k_sensitivity<Q9, MIR, true>), grid, block, 0, s, a);
+  else if (thermal) hipLaunchKernelGGL((k_sensitivity<Q19, MIR, true>), grid, block, 0, s, a);
   else if (a.P.q == 9) hipLaunchKernelGGL((k_sensitivity<Q9, MIR, false>), grid, block, 0, s, a);
   else hipLaunchKernelGGL((k_sensitivity<Q19, MIR, false>), grid, block, 0, s, a);
 }
@@ -1275,20 +1308,27 @@ hipError_t launch_sensitivity(const SensArgs& a, bool thermal, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_thermal(const ThermArgs& a, bool diag, hipStream_t s) {
+template <class G>
+static void thermal_launch(const ThermArgs& a, bool diag, hipStream_t s) {
   const dim3 grid(a.P.nblk), block(kBlock);
   if ((a.P.sx | a.P.sy | a.P.sz) != 0) {
-    if (diag) hipLaunchKernelGGL((k_thermal<true, true>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((k_thermal<false, true>), grid, block, 0, s, a);
+    if (diag) hipLaunchKernelGGL((k_thermal<G, true, true>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_thermal<G, false, true>), grid, block, 0, s, a);
   } else {
-    if (diag) hipLaunchKernelGGL((k_thermal<true, false>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((k_thermal<false, false>), grid, block, 0, s, a);
+    if (diag) hipLaunchKernelGGL((k_thermal<G, true, false>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_thermal<G, false, false>), grid, block, 0, s, a);
   }
+}
+
+hipError_t launch_thermal(const ThermArgs& a, bool diag, hipStream_t s) {
+  if (a.P.q == 9) thermal_launch<Q5>(a, diag, s);
+  else thermal_launch<Q7>(a, diag, s);
   return hipGetLastError();
 }
 
 hipError_t launch_thermal_init(const ThermArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_thermal_init, dim3(a.P.nblk), dim3(kBlock), 0, s, a);
+  if (a.P.q == 9) hipLaunchKernelGGL((k_thermal_init<Q5>), dim3(a.P.nblk), dim3(kBlock), 0, s, a);
+  else hipLaunchKernelGGL((k_thermal_init<Q7>), dim3(a.P.nblk), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 
@@ -1354,7 +1394,7 @@ hipError_t launch_finalize_slots(const SlotDev* slots, int nslots, double* out, 
   return hipGetLastError();
 }
 
-// Direction table of lattice `which` (0 D3Q19, 1 D3Q7, 2 D2Q9).
+// Direction table of lattice `which` (0 D3Q19, 1 D3Q7, 2 D2Q9, 3 D2Q5).
 template <class L>
 static void table_of(int32_t* e, double* w, const double* wd) {
   for (int i = 0; i < L::Q; ++i) {
@@ -1374,10 +1414,14 @@ void lattice_table(int which, int32_t* e, double* w) {
     double wd[7];
     for (int i = 0; i < 7; ++i) wd[i] = (i == 0) ? 0.25 : 0.125;
     table_of<Q7>(e, w, wd);
-  } else {
+  } else if (which == 2) {
     double wd[9];
     for (int i = 0; i < 9; ++i) wd[i] = (i == 0) ? 4.0 / 9.0 : (i <= 4 ? 1.0 / 9.0 : 1.0 / 36.0);
     table_of<Q9>(e, w, wd);
+  } else {
+    double wd[5];
+    for (int i = 0; i < 5; ++i) wd[i] = (i == 0) ? 0.5 : 0.125;
+    table_of<Q5>(e, w, wd);
   }
 }
 

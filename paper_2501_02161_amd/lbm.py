@@ -287,7 +287,7 @@ def lbm_kernel_timing(p, reset: bool = False):
 
 def lbm_lattice(which: int):
     import numpy as np
-    Q = {0: 19, 1: 7, 2: 9}.get(int(which), 19)
+    Q = {0: 19, 1: 7, 2: 9, 3: 5}.get(int(which), 19)
     e = np.zeros((Q, 3), dtype=np.int32)
     w = np.zeros(Q, dtype=np.float64)
     _check(load_library().lbm_lattice(int(which), c_void_p(e.ctypes.data),
@@ -483,8 +483,8 @@ class Problem:
         return {"forward": fi, "adjoint": ai, "J": J}
 
     def state(self, which: int) -> torch.Tensor:
-        qf = 9 if self.spec.nz == 1 else 19
-        q = qf if which in (STATE_FLOW, STATE_ADJ_FLOW) else 7
+        qf, qg = (9, 5) if self.spec.nz == 1 else (19, 7)
+        q = qf if which in (STATE_FLOW, STATE_ADJ_FLOW) else qg
         out = torch.empty((q,) + self.shape, dtype=torch.float32, device=self.device)
         with torch.cuda.device(self.device):
             lbm_copy_state(self.h, which, out)

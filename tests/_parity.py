@@ -20,9 +20,9 @@ def rel(a, b):
 
 def perm_to_oracle(o, which, two_d=False):
     """perm[i_oracle] = i_gpu for the flow (0) or thermal (1) lattice, matched by
-    velocity vectors (the two sides keep their own tables); the flow lattice
-    of a 2D problem is D2Q9."""
-    eg, wg = lbm.lbm_lattice(2 if (two_d and which == 0) else which)
+    velocity vectors (the two sides keep their own tables); a 2D problem has
+    D2Q9 and D2Q5."""
+    eg, wg = lbm.lbm_lattice((2 if which == 0 else 3) if two_d else which)
     eo, wo = o.lattice(which)
     perm = np.zeros(len(wo), dtype=np.int64)
     for i, e in enumerate(eo):

@@ -189,15 +189,22 @@ def test_2d_lattice_table_and_descriptor(lbm):
     n = lbm.lbm_workspace_bytes(h)
     assert 36 * 4 * w.N <= n < (36 + 3) * 4 * (w.N + 64) + 64 * 1024
     lbm.lbm_problem_destroy(h)
+    # with heat: D2Q5, 2 x 5 forward + 2 x 5 adjoint + 5 non-equilibrium planes
+    e5, w5 = lbm.lbm_lattice(3)
+    assert e5.shape == (5, 3) and abs(w5.sum() - 1) < 1e-15
+    assert np.allclose(np.einsum("i,ia,ib->ab", w5, e5[:, :2], e5[:, :2]), np.eye(2) / 4)
+    wt = W.paper_heat_sink_2d(64, 17)
+    h = _create(lbm, wt)
+    n = lbm.lbm_workspace_bytes(h)
+    assert (36 + 25) * 4 * wt.N <= n < (36 + 25 + 3) * 4 * (wt.N + 64) + 64 * 1024
+    lbm.lbm_problem_destroy(h)
 
 
-@pytest.mark.parametrize("bad", ["thermal", "nz2", "z_normal", "z_symmetric"])
+@pytest.mark.parametrize("bad", ["nz2", "z_normal", "z_symmetric"])
 def test_invalid_2d_inputs_are_rejected(lbm, bad):
     w = W.pipe_bend_2d()
     kw = {}
-    if bad == "thermal":
-        kw["thermal"] = True
-    elif bad == "nz2":
+    if bad == "nz2":
         kw.update(nz=2, mask=np.concatenate([w.mask, w.mask]), gamma=np.concatenate([w.gamma] * 2))
     elif bad == "z_normal":
         m = w.mask.copy()

@@ -27,11 +27,12 @@ def test_more_than_one_gpu_exits_with_a_message():
 
 @pytest.mark.parametrize("name,q,thermal", [("heat_sink_Re200", 19, True), ("pipe_bend_96", 19, False),
                                             ("pipe_bend_2d_512", 9, False),
-                                            ("paper_heat_sink_Re60", 19, True)])
+                                            ("paper_heat_sink_Re60", 19, True),
+                                            ("paper_heat_sink_2d_Re60", 9, True)])
 def test_bytes_per_node(bench, name, q, thermal):
     w = bench.make_workload(name)
     assert bool(w.thermal) == thermal and (w.nz == 1) == (q == 9)
-    qt = 7 if thermal else 0
+    qt = (5 if q == 9 else 7) if thermal else 0
     dim = 2 if q == 9 else 3
     # every population read and written once, gamma and flags once
     assert bench.bytes_per_node("forward", w) == (q + qt) * 8 + 4 + 1

@@ -161,3 +161,80 @@ def test_mirror_plane_2d():
           f"J {res['J']:.9g} vs {rf['J']:.9g}", flush=True)
     assert e_u < 1e-5 and e_dJ < 1e-4
     assert math.isclose(res["J"], rf["J"], rel_tol=1e-5)
+
+
+# --------------------------------------------------------------------------
+# D2Q9 + D2Q5: the 2D heat sink of the paper's formulation
+# --------------------------------------------------------------------------
+def small_heat_sink_2d():
+    # 40 x 12 = 480 nodes: 2 tiles, the last one ragged
+    return W.paper_heat_sink_2d(40, 12, Re=10.0, tau=0.8, Pr=1.0, beta_max=2e-3, alpha_max=0.2,
+                                buffer=2, sigma=1.5, seed=31)
+
+
+def test_thermal_2d_fixed_steps_parity():
+    w = small_heat_sink_2d().replace(max_steps=600, tol=0.0, check_every=200)
+    print(f"[d2q5] fixed steps {w.nx}x{w.ny}", flush=True)
+    prob, res = run_gpu(w)
+    o, ref = run_oracle(w, steps=600, tol=0.0, check_every=200)
+    err = compare_solution(w, prob, ref)
+    assert math.isclose(res["J"], ref["J"], rel_tol=1e-5)
+    print(f"[d2q5] errors {err} J {res['J']:.9g} vs {ref['J']:.9g}", flush=True)
+
+
+def test_thermal_2d_converged_parity_and_half_equals_full():
+    """Both sides step 20000 times (the FP64 residual reaches 1e-8 after
+    about 8000): the converged states, without the spread that stopping at
+    different FP32 / FP64 residual checks would add.  A converged FP32 state
+    carries its per-step rounding amplified by the slowest mode of the
+    coupled iteration: 8.8e-6 in T on this 24 x 9 half channel, 1.1-2.0e-5
+    on 40 x 12 variants (after 600 steps the same fields agree to 1.2e-7)."""
+    w = W.paper_heat_sink_2d(24, 9, Re=10.0, tau=0.8, Pr=1.0, beta_max=2e-3, alpha_max=0.2,
+                             buffer=2, sigma=1.5, seed=31).replace(max_steps=20000, tol=0.0,
+                                                                   check_every=1000)
+    prob, res = run_gpu(w)
+    o, ref = run_oracle(w, steps=20000, tol=0.0, check_every=1000)
+    err = compare_solution(w, prob, ref)
+    wf = W.mirror_full(w)
+    pf, rf = run_gpu(wf)
+    h = w.ny - 1
+    T, Tf = prob.T.cpu().numpy()[0, :h], pf.T.cpu().numpy()[0, :h]
+    dJ, dJf = prob.dJ.cpu().numpy()[0, :h], pf.dJ.cpu().numpy()[0, :h]
+    d = ((w.mask & 7) == W.DESIGN)[0, :h]
+    e_T, e_dJ = rel(T, Tf), rel(dJ[d], dJf[d])
+    print(f"[d2q5] converged steps {res['forward']['steps']}/{res['adjoint']['steps']} errors {err}; "
+          f"half vs full T {e_T:.2e} dJ {e_dJ:.2e}; J {res['J']:.9g} x 2 vs {rf['J']:.9g}",
+          flush=True)
+    # J = -sum Q doubles on the full domain; a half cell is two mirror cells
+    assert e_T < 1e-5 and e_dJ < 1e-4
+    assert math.isclose(2.0 * res["J"], rf["J"], rel_tol=1e-5)
+
+
+def test_thermal_2d_full_size_step_parity():
+    from test_gpu_parity import _step_check
+    w = W.paper_heat_sink_2d()
+    print(f"[d2q5] step check {w.nx}x{w.ny}", flush=True)
+    err, J = _step_check(w)
+    print(f"[d2q5] step errors {err}", flush=True)
+    for key, v in err.items():
+        assert v < (1e-4 if key == "sens" else 1e-5), (key, err)
+
+
+def test_thermal_2d_autograd_matches_direct_path():
+    """The differentiable form on the 2D lattice: its backward re-solves the
+    D2Q5 lattice from (gamma, u, T) and gives the direct path's gradient."""
+    from paper_2501_02161_amd import autograd
+    w = small_heat_sink_2d().replace(max_steps=60000, tol=1e-8, check_every=500)
+    prob = lbm.Problem(w, device="cuda:0")
+    gamma = torch.tensor(w.gamma, dtype=torch.float32, device="cuda:0", requires_grad=True)
+    J = autograd.objective(gamma, prob)
+    J.backward()
+    direct = lbm.Problem(w, device="cuda:0")
+    res = direct.solve(w.gamma)
+    torch.cuda.synchronize()
+    d = ((w.mask & 7) == W.DESIGN).reshape(-1)
+    g = gamma.grad.reshape(-1).cpu().numpy()[d]
+    ref = direct.dJ.reshape(-1).cpu().numpy()[d]
+    print(f"[d2q5] autograd vs direct {rel(g, ref):.2e}", flush=True)
+    assert float(J) == res["J"]
+    assert rel(g, ref) < 1e-4

@@ -238,3 +238,39 @@ def test_thermal_2d_autograd_matches_direct_path():
     print(f"[d2q5] autograd vs direct {rel(g, ref):.2e}", flush=True)
     assert float(J) == res["J"]
     assert rel(g, ref) < 1e-4
+
+
+def test_batch_mixes_2d_and_3d_heat():
+    """A thermal batch engine (heat-generation objective) steps 2D (D2Q9 +
+    D2Q5) and 3D (D3Q19 + D3Q7) heat sinks in the same launches; each result
+    is its single solve's, bit for bit."""
+    from paper_2501_02161_amd import serving
+    kw = dict(max_steps=3000, tol=1e-7, check_every=500)
+    reqs = [small_heat_sink_2d().replace(**kw),
+            W.paper_heat_sink(24, 9, 7, Re=10.0, tau=0.8, Pr=1.0, beta_max=2e-3, alpha_max=0.2,
+                              buffer=1, sigma=1.0, seed=5).replace(**kw),
+            W.paper_heat_sink_2d(30, 10, Re=5.0, tau=0.8, Pr=1.0, beta_max=2e-3, alpha_max=0.2,
+                                 buffer=2, sigma=1.5, seed=32).replace(**kw)]
+    eng = serving.BatchEngine(True, W.OBJ_HEATGEN, budget_bytes=256 << 20, max_slots=4, quantum=100)
+    tickets = {eng.submit(w): i for i, w in enumerate(reqs)}
+    results = {}
+    for _ in range(10000):
+        eng.step()
+        for t, i in list(tickets.items()):
+            r = eng.collect(t, reqs[i].N)
+            if r is not None:
+                results[i] = r
+                del tickets[t]
+        if not tickets:
+            break
+    assert len(results) == len(reqs)
+    for i, w in enumerate(reqs):
+        prob, res = run_gpu(w)
+        _, _, _, dJ = gpu_fields(prob)
+        r = results[i]
+        print(f"[d2q5] batch {w.name}: J {r['J']:.9g} vs {res['J']:.9g} steps "
+              f"{r['fwd_steps']}/{r['adj_steps']}", flush=True)
+        assert r["state"] in (lbm.LBM_BATCH_DONE,)
+        assert r["J"] == res["J"]
+        assert r["fwd_steps"] == res["forward"]["steps"]
+        assert np.array_equal(r["dJ"], dJ.astype(np.float32))

@@ -215,3 +215,31 @@ def test_invalid_2d_inputs_are_rejected(lbm, bad):
     with pytest.raises(lbm.LBMError) as e:
         _create(lbm, w, **kw)
     assert e.value.code == lbm.LBM_EINVAL
+
+
+def test_grid_size_limit(lbm):
+    """N = 2^31 / 32 nodes is accepted (32-bit node indices with headroom),
+    one more row is not."""
+    class Spec:
+        pass
+    for ny, ok in ((1024, True), (1025, False)):
+        s = Spec()
+        s.nx, s.ny, s.nz = 256, ny, 256
+        s.thermal, s.periodic, s.objective = False, (False, True, False), W.OBJ_PRESSURE_DROP
+        for k, v in dict(tau=0.8, rho0=1.0, Re=1.0, L_ref=1.0, alpha_max=0.1, q_brink=0.1, Pr=1.0,
+                         k_ratio=1.0, q_ramp=1.0, q_w=0.0, T_in=0.0, w_dp=0.0, tol=0.0).items():
+            setattr(s, k, v)
+        s.max_steps, s.check_every = 1, 0
+        mask = np.full((256, ny, 256), W.DESIGN, dtype=np.uint8)
+        mask[0] = W.WALL
+        mask[-1] = W.WALL
+        mask[:, :, 0] = W.WALL
+        mask[:, :, -1] = W.WALL
+        if ok:
+            h = lbm.lbm_problem_create(lbm.make_desc(s), mask)
+            assert lbm.lbm_workspace_bytes(h) > 4 * 19 * 4 * 256 * ny * 256
+            lbm.lbm_problem_destroy(h)
+        else:
+            with pytest.raises(lbm.LBMError) as e:
+                lbm.lbm_problem_create(lbm.make_desc(s), mask)
+            assert e.value.code == lbm.LBM_EINVAL

@@ -274,3 +274,29 @@ def test_batch_mixes_2d_and_3d_heat():
         assert r["J"] == res["J"]
         assert r["fwd_steps"] == res["forward"]["steps"]
         assert np.array_equal(r["dJ"], dJ.astype(np.float32))
+
+
+def test_conduction_2d_closed_form():
+    """D2Q5 with a heated floor row (heat-sink objective, heated walls) under
+    a Dirichlet top row and no flow: the GPU's steady temperature is the
+    exact linear profile T_top + q_w (ny - 1 - y) / D, D = nu / Pr, and its
+    fixed-step states match the oracle."""
+    w = W.conduction_column_2d(9, 14, tau=0.8, Pr=0.5, q_w=0.003, T_top=0.25)
+    prob, res = run_gpu(w.replace(max_steps=40000, tol=1e-9, check_every=500))
+    T = prob.T.cpu().numpy()[0].astype(np.float64)
+    D = (w.tau - 0.5) / 3.0 / w.Pr
+    ys = np.arange(1, w.ny)
+    expect = w.T_in + w.q_w / D * (w.ny - 1 - ys)
+    e = max(rel(T[1:, x], expect) for x in range(1, w.nx - 1))
+    print(f"[d2q5] conduction steps {res['forward']['steps']} linear-profile error {e:.2e}", flush=True)
+    assert e < 1e-5
+    # fixed steps against the oracle (no flow: u and the pressure are 0 on
+    # the GPU and FP64 round-off in the oracle, so only T is compared)
+    wf = w.replace(max_steps=500, tol=0.0, check_every=100)
+    prob, res = run_gpu(wf)
+    o, ref = run_oracle(wf, steps=500, tol=0.0, check_every=100)
+    live = (wf.mask.reshape(-1) & 7) < W.WALL
+    _, u, Tg, _ = gpu_fields(prob)
+    e_T = rel(Tg[live] - wf.T_in, ref["T"][live] - wf.T_in)
+    print(f"[d2q5] conduction fixed steps T {e_T:.2e}, max |u| {np.abs(u).max():.1e}", flush=True)
+    assert e_T < 1e-5 and np.abs(u).max() < 1e-6

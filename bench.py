@@ -204,30 +204,46 @@ def make_workload(name, adjoint="discrete", Re=0.0):
     return W.heat_sink(Re=Re)
 
 
-def cpu_baseline(w, fwd_steps):
-    """The oracle (as it is) on the host cores: a bounded sample of forward and
-    adjoint steps of the same workload from rest."""
-    import numpy as np
-    import oracle
-    o = oracle.Oracle(w)
+def _oracle_rate(o, w, fwd_steps, adj_steps):
+    """Seconds per forward and per adjoint step of the oracle, from rest."""
     t0 = time.perf_counter()
     fw = o.forward(max_steps=fwd_steps, tol=0.0, check_every=0)
     t1 = time.perf_counter()
-    adj_steps = max(1, fwd_steps // 4)
     if getattr(w, "adjoint_kind", 0) == 1:
         o.cont_adjoint(fw["f"], max_steps=adj_steps, tol=0.0, check_every=0)
     else:
         o.adjoint(fw["f"], fw["g"], max_steps=adj_steps, tol=0.0, check_every=0)
     t2 = time.perf_counter()
-    tf = (t1 - t0) / fwd_steps
-    ta = (t2 - t1) / adj_steps
+    return (t1 - t0) / fwd_steps, (t2 - t1) / adj_steps
+
+
+def cpu_baseline(w, fwd_steps):
+    """The oracle (as it is) on the host cores: a bounded sample of forward and
+    adjoint steps of the same workload from rest; beside it a shorter sample
+    on one core."""
+    import oracle
+    o = oracle.Oracle(w)
+    adj_steps = max(1, fwd_steps // 4)
+    tf, ta = _oracle_rate(o, w, fwd_steps, adj_steps)
     # the GPU solve takes about as many adjoint as forward steps
     mlups = 2 * w.N / (tf + ta) / 1e6
-    return {"value": round(mlups, 4), "unit": "MLUPS", "cores": oracle.threads_used(),
-            "kind": "oracle",
-            "sample": f"{fwd_steps} forward + {adj_steps} adjoint steps of {w.name} from rest "
-                      f"(FP64, {tf * 1e3:.0f} ms/forward step, {ta * 1e3:.0f} ms/adjoint step; "
-                      f"rate for equal forward and adjoint step counts)"}
+    cores = oracle.threads_used()
+    out = {"value": round(mlups, 4), "unit": "MLUPS", "cores": cores, "kind": "oracle",
+           "sample": f"{fwd_steps} forward + {adj_steps} adjoint steps of {w.name} from rest "
+                     f"(FP64, {tf * 1e3:.0f} ms/forward step, {ta * 1e3:.0f} ms/adjoint step; "
+                     f"rate for equal forward and adjoint step counts)"}
+    if cores > 1:
+        f1, a1 = max(1, fwd_steps // 6), max(1, adj_steps // 6)
+        oracle.set_threads(1)
+        try:
+            tf1, ta1 = _oracle_rate(o, w, f1, a1)
+        finally:
+            oracle.set_threads(cores)
+        out["one_core"] = {"value": round(2 * w.N / (tf1 + ta1) / 1e6, 4), "unit": "MLUPS",
+                           "sample": f"{f1} forward + {a1} adjoint steps on 1 thread "
+                                     f"({tf1 * 1e3:.0f} ms/forward step, "
+                                     f"{ta1 * 1e3:.0f} ms/adjoint step)"}
+    return out
 
 
 def serving_leg(n, rate, policy="srw", fill=512):

@@ -43,3 +43,17 @@ def test_bytes_per_node(bench, name, q, thermal):
 def test_headline_workload_is_the_heat_sink(bench):
     w = bench.make_workload("heat_sink_Re200")
     assert (w.nx, w.ny, w.nz) == (160, 80, 40) and w.Re == 200.0 and w.thermal
+
+
+def test_cpu_baseline_fields(bench):
+    """The CPU baseline times the oracle as it is, on every host core and on
+    one core, and says what the sample was."""
+    import oracle
+    import workloads as W
+    w = W.tiny_heat_sink()
+    out = bench.cpu_baseline(w, 12)
+    assert out["kind"] == "oracle" and out["unit"] == "MLUPS" and out["value"] > 0
+    assert out["cores"] == oracle.threads_used()
+    assert "12 forward + 3 adjoint steps" in out["sample"]
+    if out["cores"] > 1:
+        assert out["one_core"]["value"] > 0 and "on 1 thread" in out["one_core"]["sample"]

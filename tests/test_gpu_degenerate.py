@@ -102,3 +102,28 @@ def test_binary_and_uniform_designs_parity(name):
     print(f"[degenerate] {name} errors {err} J {res['J']:.9g} vs {ref['J']:.9g}", flush=True)
     assert abs(res["J"] - ref["J"]) <= 1e-5 * abs(ref["J"])
     prob.close()
+
+
+SMALLEST = {
+    # one-node-wide channel: 45 nodes, 3 design nodes, one tile padded to 64
+    "heat_sink_5x3x3": lambda: W.heat_sink(5, 3, 3, Re=0.3, tau=0.8, sigma=1.0, seed=106),
+    # 28 nodes: the smallest half domain with a mirror row
+    "paper_heat_sink_2d_7x4": lambda: W.paper_heat_sink_2d(7, 4, Re=1.0, tau=0.8, beta_max=1e-2,
+                                                           buffer=1, sigma=1.0),
+    # 112 nodes: the smallest quarter domain with two mirror planes
+    "paper_heat_sink_7x4x4": lambda: W.paper_heat_sink(7, 4, 4, Re=1.0, tau=0.8, beta_max=1e-2,
+                                                       buffer=1, sigma=1.0),
+}
+
+
+@pytest.mark.parametrize("name", list(SMALLEST))
+def test_smallest_grids_parity(name):
+    """Grids of fewer nodes than one wave (a single, padded tile)."""
+    w = SMALLEST[name]().replace(max_steps=300, tol=0.0, check_every=100)
+    print(f"[degenerate] smallest {name} N {w.nx * w.ny * w.nz}", flush=True)
+    prob, res = run_gpu(w)
+    o, ref = run_oracle(w, steps=300, tol=0.0, check_every=100)
+    err = compare_solution(w, prob, ref)
+    print(f"[degenerate] {name} errors {err} J {res['J']:.9g} vs {ref['J']:.9g}", flush=True)
+    assert abs(res["J"] - ref["J"]) <= 1e-5 * abs(ref["J"])
+    prob.close()

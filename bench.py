@@ -95,6 +95,14 @@ def parse():
                     help="pipe bend of the stability sweep: 3D on 32^3 or 2D (D2Q9) on 64^2")
     ap.add_argument("--stability-steps", type=int, default=1000000,
                     help="step cap of each forward and adjoint solve in the stability sweep")
+    ap.add_argument("--accuracy", action="store_true",
+                    help="sensitivity accuracy against finite differences: discrete and "
+                         "continuous adjoint on the 2D pipe bend 64^2 over --accuracy-re, "
+                         "printed as one JSON object")
+    ap.add_argument("--accuracy-re", default="1,5,10,20,40",
+                    help="comma-separated Reynolds numbers of the accuracy study")
+    ap.add_argument("--accuracy-cells", type=int, default=8,
+                    help="design cells checked by central differences per Reynolds number")
     ap.add_argument("--optimize", type=int, default=0,
                     help="run this many level-set optimisation iterations on --workload "
                          "(Sec. 2.2) and print their JSON object")
@@ -316,6 +324,86 @@ def stability_leg(steps, dim=3):
             "seconds": round(el, 1), "points": pts}
 
 
+def accuracy_leg(res, ncells, h=1e-2, settle=10000):
+    """Sensitivity accuracy of the discrete and the continuous adjoint
+    (Sec. 3.1): on the 2D pipe bend 64^2 at each Reynolds number, both
+    adjoint dJ/dgamma fields against central differences of converged GPU
+    forward solves at the design cells of largest discrete |dJ/dgamma| and at
+    seeded random ones (central differences with steps h and h/2, combined by
+    Richardson extrapolation), plus the continuous field's scale and
+    direction against the discrete one."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2501_02161_amd import lbm
+
+    torch.cuda.set_device(0)
+    rows = []
+    t0 = time.perf_counter()
+    for Re in res:
+        w = W.pipe_bend_2d(Re=Re).replace(max_steps=400000, tol=1e-9, check_every=1000)
+        design = np.flatnonzero((w.mask.reshape(-1) & 7) == W.DESIGN)
+        pd = lbm.Problem(w, device="cuda:0")
+        rd = pd.solve(w.gamma)
+        dJd = pd.dJ.reshape(-1).cpu().numpy().astype(np.float64)
+        row = {"Re": Re, "u_peak": Re * (w.tau - 0.5) / 3.0 / w.L_ref, "J": rd["J"],
+               "fwd_steps": rd["forward"]["steps"], "fwd_status": rd["forward"]["status"],
+               "disc_adj_steps": rd["adjoint"]["steps"], "disc_status": rd["adjoint"]["status"]}
+        order = design[np.argsort(-np.abs(dJd[design]))]
+        rng = np.random.default_rng(W.SEED_BASE + 9)
+        rest = order[ncells // 2:]
+        cells = list(order[:ncells // 2]) + list(rng.choice(rest, ncells - ncells // 2,
+                                                            replace=False))
+        # central differences from warm-started forward solves
+        pf = lbm.Problem(w, device="cuda:0")
+        pf.forward(w.gamma)
+        def central(k, step):
+            Jpm = []
+            for sgn in (1.0, -1.0):
+                g = w.gamma.reshape(-1).copy()
+                g[k] += sgn * step
+                pf.forward_resume(g)
+                # settle the slow modes beyond the residual criterion
+                Jpm.append(pf.forward_continue(settle)["J"])
+            return (Jpm[0] - Jpm[1]) / (2.0 * step)
+
+        fd_h = np.array([central(k, h) for k in cells])
+        fd_h2 = np.array([central(k, h / 2) for k in cells])
+        # Richardson extrapolation removes the h^2 term of the central difference
+        fd = (4.0 * fd_h2 - fd_h) / 3.0
+        scale = np.abs(fd).max()
+        row["cells"] = [int(k) for k in cells]
+        row["fd"] = fd.tolist()
+        row["disc"] = dJd[cells].tolist()
+        row["disc_vs_fd"] = float(np.abs(dJd[cells] - fd).max() / scale)
+        row["disc_vs_fd_h"] = float(np.abs(dJd[cells] - fd_h).max() / scale)
+        try:
+            pc = lbm.Problem(w, device="cuda:0", adjoint_kind=1)
+            rc = pc.solve(w.gamma)
+            dJc = pc.dJ.reshape(-1).cpu().numpy().astype(np.float64)
+            a, b = dJc[design], dJd[design]
+            row.update({"cont_adj_steps": rc["adjoint"]["steps"],
+                        "cont_status": rc["adjoint"]["status"], "cont": dJc[cells].tolist(),
+                        "cont_vs_fd": float(np.abs(dJc[cells] - fd).max() / scale),
+                        "cont_rescaled_vs_fd": float(np.abs(dJc[cells] * (dJc[cells] @ fd)
+                                                            / (dJc[cells] @ dJc[cells]) - fd).max()
+                                                     / scale),
+                        "cont_scale": float(np.linalg.norm(a) / np.linalg.norm(b)),
+                        "cont_one_minus_cos": float(1.0 - a @ b / np.linalg.norm(a)
+                                                    / np.linalg.norm(b))})
+            pc.close()
+        except lbm.LBMError as e:
+            row.update({"cont_status": "diverged", "cont_error": str(e)})
+        pd.close()
+        pf.close()
+        print(f"[accuracy] {json.dumps({k: v for k, v in row.items() if k not in ('fd', 'disc', 'cont', 'cells')})}",
+              file=sys.stderr, flush=True)
+        rows.append(row)
+    return {"workload": "pipe_bend_2d_64x64 (D2Q9, tau 0.6, inlet rows 8-23, outlet columns "
+                        "40-55, pressure drop)", "h": h, "tol": 1e-9, "settle_steps": settle,
+            "seconds": round(time.perf_counter() - t0, 1), "rows": rows}
+
+
 def optimize_leg(args):
     """Level-set topology optimisation (Sec. 2.2) on --workload from the
     empty chamber: per iteration a warm-started forward solve, adjoint solve,
@@ -358,6 +446,10 @@ def main():
     if args.stability:
         print(json.dumps({"stability": stability_leg(args.stability_steps, args.stability_dim)}),
               flush=True)
+        return
+    if args.accuracy:
+        res = [float(v) for v in args.accuracy_re.split(",") if v]
+        print(json.dumps({"accuracy": accuracy_leg(res, args.accuracy_cells)}), flush=True)
         return
     if args.optimize > 0:
         print(json.dumps({"optimize": optimize_leg(args)}), flush=True)

@@ -75,6 +75,8 @@ def parse():
     ap.add_argument("--fixed-steps", type=int, default=200)
     ap.add_argument("--copy-bw", action="store_true",
                     help="measure device-to-device copy bandwidth (1 GiB, out of cache) and exit")
+    ap.add_argument("--no-stream-probe", action="store_true",
+                    help="skip timing the forward step's traffic without its arithmetic")
     ap.add_argument("--no-kernel-timing", action="store_true",
                     help="do not bracket the sweeps with HIP events")
     ap.add_argument("--serving-requests", type=int, default=64,
@@ -124,7 +126,8 @@ def profile_run(args):
     """Short fixed workload for kernel traces and HBM counters: two copies of a
     256 MiB buffer (torch's copy kernel, whose FETCH_SIZE / WRITE_SIZE per
     dispatch calibrate the counters), then one solve of exactly
-    --fixed-steps forward and adjoint steps."""
+    --fixed-steps forward and adjoint steps and as many launches of the
+    streaming probe."""
     import torch
     from paper_2501_02161_amd import lbm
     torch.cuda.set_device(0)
@@ -138,9 +141,12 @@ def profile_run(args):
     prob = lbm.Problem(w, device="cuda:0")
     res = prob.solve(w.gamma)
     torch.cuda.synchronize()
+    # then the same number of launches of the streaming probe (after its 10 untimed ones)
+    us = prob.stream_probe(prob.gamma_tensor(w.gamma), args.fixed_steps)
+    torch.cuda.synchronize()
     print(json.dumps({"profile": w.name, "nodes": w.N, "copy_bytes": src.numel() * 4,
                       "fwd_steps": res["forward"]["steps"], "adj_steps": res["adjoint"]["steps"],
-                      "J": res["J"]}), flush=True)
+                      "J": res["J"], "stream_probe_us": us}), flush=True)
 
 
 def copy_bandwidth():
@@ -540,6 +546,16 @@ def main():
              bytes_per_node("adjoint", w) * w.N * ai["steps"]) * args.steps /
             elapsed / 1e9 / HBM_PEAK_GBS, 4),
     }
+    if not args.no_stream_probe:
+        # the forward step's traffic in its own pattern with none of its
+        # arithmetic: the ceiling the pull pattern leaves the step kernel
+        us = prob.stream_probe(gamma, 2000)
+        fwd_us = per_kernel["forward"]["avg_us"]
+        out["stream_ceiling"] = {
+            "probe": "forward step traffic and pull pattern, no arithmetic (lbm_stream_probe)",
+            "avg_us": round(us, 3),
+            "GBps": round(bytes_per_node("forward", w) * w.N / (us * 1e-6) / 1e9, 1),
+            "forward_frac": round(us / fwd_us, 4) if fwd_us else None}
     prob.close()
     if args.serving_requests > 0:
         out["serving"] = serving_leg(args.serving_requests, args.serving_rate,

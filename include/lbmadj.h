@@ -314,6 +314,21 @@ int lbm_copy_state(const lbm_problem_t* p, int32_t which, float* dst, void* stre
 int lbm_set_kernel_timing(lbm_problem_t* p, int32_t enable);
 int lbm_kernel_timing(lbm_problem_t* p, double* ms, int64_t* launches, int32_t reset);
 
+/* Streaming ceiling of the forward step on the bound device: `launches`
+ * back-to-back launches (after 10 untimed ones) of a kernel that moves
+ * exactly the forward step's bytes in its pattern (every population pulled
+ * from the same neighbour as in the step, gamma and the node flags read,
+ * the pulled values stored unchanged) but does none of its arithmetic; the
+ * average time per launch (HIP events on `stream`, synchronised) goes to
+ * us_per_launch.  The step kernel's time over this one is how close the
+ * step runs to what its access pattern allows.  gamma: device [N].  The
+ * probe overwrites the workspace's forward populations, so afterwards no
+ * forward or adjoint state remains (continue, resume and sensitivity calls
+ * return LBM_ESTATE until the next solve).  LBM_EINVAL for launches outside
+ * [1, 1000000]. */
+int lbm_stream_probe(lbm_problem_t* p, const float* gamma, int32_t launches, double* us_per_launch,
+                     void* stream);
+
 /* Direction table of the library: which 0 = D3Q19 (19 entries), 1 = D3Q7
  * (7 entries), 2 = D2Q9 (9 entries, e_z = 0), 3 = D2Q5 (5 entries); e
  * receives 3 ints per direction, w the weight. */

@@ -833,6 +833,54 @@ int lbm_kernel_timing(lbm_problem_t* p, double* ms, int64_t* launches, int32_t r
   return LBM_OK;
 }
 
+int lbm_stream_probe(lbm_problem_t* p, const float* gamma, int32_t launches, double* us_per_launch,
+                     void* stream) {
+  last_error().clear();
+  int rc = check_bound(p);
+  if (rc) return rc;
+  if (!gamma || !us_per_launch) return fail(LBM_EINVAL, "null argument");
+  if (launches < 1 || launches > 1000000) return fail(LBM_EINVAL, "launches must be in [1, 1000000]");
+  DeviceGuard guard(p->dev);
+  hipStream_t s = (hipStream_t)stream;
+  // the probe overwrites both forward buffers: no state survives it
+  p->fwd_done = p->adj_done = p->adj_state = p->have_gneq = false;
+  p->fcur = 0;
+  FwdArgs a = fwd_args(p, gamma, nullptr, nullptr, nullptr);
+  int cur = 0;
+  auto swap_ab = [&]() {
+    cur = 1 - cur;
+    a.fin = p->f[cur];
+    a.fout = p->f[1 - cur];
+    a.gin = p->g[cur];
+    a.gout = p->g[1 - cur];
+  };
+  for (int i = 0; i < 10; ++i) {
+    HIPCHK(launch_stream_probe(a, thermal_of(p), s));
+    swap_ab();
+  }
+  hipEvent_t ev[2];
+  HIPCHK(hipEventCreate(&ev[0]));
+  hipError_t e = hipEventCreate(&ev[1]);
+  if (e != hipSuccess) {
+    (void)hipEventDestroy(ev[0]);
+    return fail(LBM_EDEVICE, std::string("hipEventCreate: ") + hipGetErrorString(e));
+  }
+  e = hipEventRecord(ev[0], s);
+  for (int i = 0; i < launches && e == hipSuccess; ++i) {
+    e = launch_stream_probe(a, thermal_of(p), s);
+    swap_ab();
+  }
+  if (e == hipSuccess) e = hipEventRecord(ev[1], s);
+  if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+  float ms = 0.0f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
+  if (e != hipSuccess) return fail(LBM_EDEVICE, std::string("stream probe: ") + hipGetErrorString(e));
+  *us_per_launch = 1e3 * (double)ms / launches;
+  return LBM_OK;
+}
+
 int lbm_lattice(int32_t which, int32_t* e, double* w) {
   if (!e || !w || which < 0 || which > 3) return fail(LBM_EINVAL, "bad arguments");
   lattice_table(which, e, w);

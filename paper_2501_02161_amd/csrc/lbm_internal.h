@@ -158,6 +158,8 @@ hipError_t launch_adjoint(const AdjArgs& a, bool thermal, int objective, bool di
                           hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 hipError_t launch_sensitivity(const SensArgs& a, bool thermal, hipStream_t s);
 hipError_t launch_thermal(const ThermArgs& a, bool diag, hipStream_t s);
+// The forward step's pulls and stores with no arithmetic (fin -> fout, gin -> gout).
+hipError_t launch_stream_probe(const FwdArgs& a, bool thermal, hipStream_t s);
 hipError_t launch_thermal_init(const ThermArgs& a, hipStream_t s);
 hipError_t launch_dissipation_source(const float* u, const float* gamma, const uint8_t* flags,
                                      float* G, const KParams& P, hipStream_t s);

@@ -1222,6 +1222,42 @@ static void launch_step(K kern, int nblk, const A& a, hipStream_t s, hipEvent_t 
     hipLaunchKernelGGL(kern, dim3(nblk), dim3(kBlock), 0, s, a);
 }
 
+// ---------------------------------------------------------------------------
+// Streaming probe: the forward step's memory traffic without its arithmetic.
+// Every population is pulled exactly as k_forward pulls it (same neighbour
+// offsets, zero beyond non-periodic faces), gamma and the flag byte are read,
+// and the pulled values are stored unchanged.  Its time per launch is the
+// ceiling the pull pattern itself leaves the step kernel on the device.
+// ---------------------------------------------------------------------------
+template <class L, bool THERMAL>
+__global__ __launch_bounds__(kBlock) void k_stream_probe(FwdArgs A) {
+  using G = typename ThermalOf<L>::type;
+  const KParams& P = A.P;
+  const int n = remap_block(blockIdx.x, P) * kBlock + threadIdx.x;
+  if (n >= P.N) return;
+  const int x = n % P.nx, t = n / P.nx, y = t % P.ny, z = t / P.ny;
+  const Nbr nb = make_nbr(x, y, z, P);
+  const Mirror mr{false, false, false};
+  // bit 7 of a flag byte is always clear: the select keeps the pulled value
+  // while gamma and the flags are still read as the step reads them
+  const bool never = (A.flags[n] & 0x80u) != 0;
+  const float gv = A.gamma[n];
+  float h[L::Q];
+  sfor<L::Q>([&](auto I) {
+    constexpr int i = I;
+    h[i] = load_pull<L, i, -L::ex[i], -L::ey[i], -L::ez[i]>(A.fin, P.Np, nb, n, mr);
+  });
+  float k[G::Q];
+  if constexpr (THERMAL) {
+    sfor<G::Q>([&](auto I) {
+      constexpr int i = I;
+      k[i] = load_pull<G, i, -G::ex[i], -G::ey[i], -G::ez[i]>(A.gin, P.Np, nb, n, mr);
+    });
+  }
+  sfor<L::Q>([&](auto I) { A.fout[(size_t)I * P.Np + n] = never ? gv : h[I]; });
+  if constexpr (THERMAL) sfor<G::Q>([&](auto I) { A.gout[(size_t)I * P.Np + n] = never ? gv : k[I]; });
+}
+
 template <class L, bool TH>
 static void fwd_dispatch(const FwdArgs& a, bool diag, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   if ((a.P.sx | a.P.sy | a.P.sz) != 0) {
@@ -1239,6 +1275,14 @@ hipError_t launch_forward(const FwdArgs& a, bool thermal, bool diag, hipStream_t
   else if (thermal) fwd_dispatch<Q19, true>(a, diag, s, ev0, ev1);
   else if (a.P.q == 9) fwd_dispatch<Q9, false>(a, diag, s, ev0, ev1);
   else fwd_dispatch<Q19, false>(a, diag, s, ev0, ev1);
+  return hipGetLastError();
+}
+
+hipError_t launch_stream_probe(const FwdArgs& a, bool thermal, hipStream_t s) {
+  if (thermal && a.P.q == 9) launch_step(k_stream_probe<Q9, true>, a.P.nblk, a, s, nullptr, nullptr);
+  else if (thermal) launch_step(k_stream_probe<Q19, true>, a.P.nblk, a, s, nullptr, nullptr);
+  else if (a.P.q == 9) launch_step(k_stream_probe<Q9, false>, a.P.nblk, a, s, nullptr, nullptr);
+  else launch_step(k_stream_probe<Q19, false>, a.P.nblk, a, s, nullptr, nullptr);
   return hipGetLastError();
 }
 

@@ -81,7 +81,8 @@ EXPORTS = ("lbm_problem_create", "lbm_workspace_bytes", "lbm_bind_workspace", "l
            "lbm_forward_continue", "lbm_adjoint_solve", "lbm_adjoint_continue",
            "lbm_thermal_resolve", "lbm_sensitivity", "lbm_forward_resume",
            "lbm_adjoint_resume", "lbm_levelset_update",
-           "lbm_copy_state", "lbm_set_kernel_timing", "lbm_kernel_timing", "lbm_lattice",
+           "lbm_copy_state", "lbm_set_kernel_timing", "lbm_kernel_timing", "lbm_stream_probe",
+           "lbm_lattice",
            "lbm_problem_destroy", "lbm_last_error", "lbm_batch_create", "lbm_batch_table_bytes",
            "lbm_batch_bind_arena", "lbm_batch_set_policy", "lbm_batch_submit", "lbm_batch_step", "lbm_batch_poll",
            "lbm_batch_stats", "lbm_batch_destroy")
@@ -130,6 +131,8 @@ def load_library(path: str = LIB_PATH):
     lib.lbm_set_kernel_timing.restype = c_int
     lib.lbm_kernel_timing.argtypes = [P, P, P, c_int32]
     lib.lbm_kernel_timing.restype = c_int
+    lib.lbm_stream_probe.argtypes = [P, P, c_int32, POINTER(c_double), P]
+    lib.lbm_stream_probe.restype = c_int
     lib.lbm_lattice.argtypes = [c_int32, P, P]
     lib.lbm_lattice.restype = c_int
     lib.lbm_problem_destroy.argtypes = [P]
@@ -283,6 +286,15 @@ def lbm_kernel_timing(p, reset: bool = False):
     _check(load_library().lbm_kernel_timing(p, c_void_p(ms.ctypes.data), c_void_p(n.ctypes.data),
                                             int(bool(reset))))
     return (float(ms[0]), float(ms[1])), (int(n[0]), int(n[1]))
+
+
+def lbm_stream_probe(p, gamma, launches: int, stream=None) -> float:
+    """Microseconds per launch of the forward step's traffic without its
+    arithmetic (the workspace's states are lost)."""
+    us = c_double(0.0)
+    _check(load_library().lbm_stream_probe(p, _ptr(gamma), int(launches), byref(us),
+                                           _stream(stream, gamma.device)))
+    return us.value
 
 
 def lbm_lattice(which: int):
@@ -481,6 +493,12 @@ class Problem:
         ai = self.adjoint(stream=stream)
         J = self.sensitivity(stream=stream)
         return {"forward": fi, "adjoint": ai, "J": J}
+
+    def stream_probe(self, gamma, launches: int = 1000, stream=None) -> float:
+        """Microseconds per launch of the forward step's memory traffic with
+        none of its arithmetic; every solve state is lost."""
+        with torch.cuda.device(self.device):
+            return lbm_stream_probe(self.h, self.gamma_tensor(gamma), launches, stream)
 
     def state(self, which: int) -> torch.Tensor:
         qf, qg = (9, 5) if self.spec.nz == 1 else (19, 7)

@@ -117,6 +117,35 @@ def test_determinism_and_wall_outputs():
     assert np.all(f1[0][wall] == 0) and np.all(f1[1][wall] == 0) and np.all(f1[2][wall] == 0)
 
 
+@pytest.mark.parametrize("two_d", [False, True])
+def test_stream_probe_times_and_drops_state(two_d):
+    """The streaming probe reports a positive time per launch, leaves no
+    solve state behind, and a later solve is unaffected by it."""
+    w = (W.paper_heat_sink_2d(40, 12, Re=10.0, tau=0.7, beta_max=1e-3, buffer=2, sigma=1.5)
+         if two_d else small_heat_sink()).replace(max_steps=300, tol=0.0, check_every=100)
+    p1, r1 = run_gpu(w)
+    ref = [x.copy() for x in gpu_fields(p1)]
+    g = p1.gamma_tensor(w.gamma)
+    with pytest.raises(lbm.LBMError) as e:
+        p1.stream_probe(g, 0)
+    assert e.value.code == lbm.LBM_EINVAL
+    us = p1.stream_probe(g, 200)
+    print(f"[probe] {w.name}: {us:.3f} us per launch", flush=True)
+    assert 0.0 < us < 1e4
+    for call in (lambda: p1.forward_continue(10), lambda: p1.adjoint_resume(),
+                 lambda: p1.sensitivity()):
+        with pytest.raises(lbm.LBMError) as e:
+            call()
+        assert e.value.code == lbm.LBM_ESTATE
+    r2 = p1.solve(w.gamma)
+    torch.cuda.synchronize()
+    for a, b in zip(ref, gpu_fields(p1)):
+        if a is not None:
+            assert np.array_equal(a, b)
+    assert r1["J"] == r2["J"]
+    p1.close()
+
+
 def test_error_paths():
     w = small_heat_sink().replace(max_steps=50, tol=0.0, check_every=0)
     prob = lbm.Problem(w, device="cuda:0")

@@ -233,12 +233,25 @@ __device__ __forceinline__ float khat_of(float g, const KParams& P) {
 struct Normal {
   int x, y, z;
 };
-__device__ __forceinline__ Normal normal_of(int c) {
-  Normal v;
-  v.x = (c == 0) - (c == 1);
-  v.y = (c == 2) - (c == 3);
-  v.z = (c == 4) - (c == 5);
-  return v;
+
+// Calls f(n) with the inward normal of code nc as a compile-time constant in
+// each case, so that the direction tests of the port rules below fold away
+// (a runtime normal costs every wave that holds a port node the generic
+// select chains).  2D lattices have no z normals.
+template <class L, class F>
+__device__ __forceinline__ void with_normal(int nc, F&& f) {
+  switch (nc) {
+    case 0: f(Normal{1, 0, 0}); break;
+    case 1: f(Normal{-1, 0, 0}); break;
+    case 2: f(Normal{0, 1, 0}); break;
+    case 3: f(Normal{0, -1, 0}); break;
+    default:
+      if constexpr (L::Q != 9) {
+        if (nc == 4) f(Normal{0, 0, 1});
+        else f(Normal{0, 0, -1});
+      }
+      break;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -437,7 +450,8 @@ __device__ __forceinline__ void forward_tile(const FwdArgs& A, int blk) {
       if (kind == K_INLET || kind == K_OUTLET) {
         const bool vin = kind == K_INLET && !P.pin;   // velocity inlet
         const float jn = vin ? A.uin[n] * P.rho0 : 0.f;
-        zou_he<L>(h, normal_of(nc), vin, jn, (kind == K_INLET) ? P.drho_in : 0.0f);
+        const float drho_b = (kind == K_INLET) ? P.drho_in : 0.0f;
+        with_normal<L>(nc, [&](Normal nv) { zou_he<L>(h, nv, vin, jn, drho_b); });
       }
       if constexpr (THERMAL) {
         if (kind == K_INLET) {
@@ -581,7 +595,7 @@ __device__ __forceinline__ void adjoint_tile(const AdjArgs& A, int blk) {
         // gives the objective no boundary term there
         const bool prs = kind == K_OUTLET || P.pin;
         const float src = (OBJ == OBJ_PRESSURE_DROP && !prs) ? 2.0f * P.c_in : 0.0f;
-        zou_he_continuous<L>(a, normal_of(nc), prs, src);
+        with_normal<L>(nc, [&](Normal nv) { zou_he_continuous<L>(a, nv, prs, src); });
       }
     }
     // the new state, stored once after both branches (one full store per
@@ -671,8 +685,10 @@ __device__ __forceinline__ void adjoint_tile(const AdjArgs& A, int blk) {
         c[i] = v;
       });
       if constexpr (!CONT) {
-        if (kind == K_INLET || kind == K_OUTLET)
-          zou_he_transpose<L>(c, normal_of(nc), kind == K_OUTLET || P.pin);
+        if (kind == K_INLET || kind == K_OUTLET) {
+          const bool outlet = kind == K_OUTLET || P.pin;
+          with_normal<L>(nc, [&](Normal nv) { zou_he_transpose<L>(c, nv, outlet); });
+        }
       }
       if constexpr (THERMAL) {
         const float bb = og * Bg - dsrc - bq * Sbw;

@@ -382,7 +382,11 @@ __device__ __forceinline__ void block_reduce_store(double (&acc)[NV], double* __
 // node's velocity.  DIAG additionally writes the macroscopic fields, the
 // thermal non-equilibrium populations and the residual partial sums.
 // ---------------------------------------------------------------------------
-template <class L, bool MIR, bool THERMAL, bool DIAG>
+// EARLY: the node's own inputs are read together with the populations (one
+// dependent memory round trip per step instead of two); pays off on lattices
+// too small to keep several waves per SIMD in flight, and costs the large
+// in-cache ones, so the launch chooses it by block count.
+template <class L, bool MIR, bool THERMAL, bool DIAG, bool EARLY = false>
 __device__ __forceinline__ void forward_tile(const FwdArgs& A, int blk) {
   using G = typename ThermalOf<L>::type;  // thermal lattice
   const KParams& P = A.P;
@@ -394,6 +398,8 @@ __device__ __forceinline__ void forward_tile(const FwdArgs& A, int blk) {
     const Mirror mr = MIR ? mirror_of(x, y, z, P) : Mirror{false, false, false};
     const unsigned fl = A.flags[n];
     const int kind = fl & 7, nc = (fl >> 3) & 7;
+    float gam_n = 1.0f;
+    if constexpr (EARLY) gam_n = A.gamma[n];
     float h[L::Q];
     sfor<L::Q>([&](auto I) {
       constexpr int i = I;
@@ -474,7 +480,8 @@ __device__ __forceinline__ void forward_tile(const FwdArgs& A, int blk) {
       const float inv_rho0 = 1.0f / P.rho0;
       const float ux = jx * inv_rho0, uy = jy * inv_rho0, uz = jz * inv_rho0;
       float gam = 1.0f;
-      if (kind == K_DESIGN) gam = A.gamma[n];
+      if constexpr (EARLY) gam = (kind == K_DESIGN) ? gam_n : 1.0f;
+      else if (kind == K_DESIGN) gam = A.gamma[n];
       const float chi = (kind == K_DESIGN) ? chi_of(gam, P) : 1.0f;
       const float vx = chi * ux, vy = chi * uy, vz = chi * uz;
       const float vv = vx * vx + vy * vy + vz * vz;
@@ -522,9 +529,9 @@ __device__ __forceinline__ void forward_tile(const FwdArgs& A, int blk) {
   if constexpr (DIAG) block_reduce_store<kRedFwd>(acc, A.partials + (size_t)blk * kRedFwd);
 }
 
-template <class L, bool MIR, bool THERMAL, bool DIAG>
+template <class L, bool MIR, bool THERMAL, bool DIAG, bool EARLY = false>
 __global__ __launch_bounds__(kBlock) void k_forward(FwdArgs A) {
-  forward_tile<L, MIR, THERMAL, DIAG>(A, remap_block(blockIdx.x, A.P));
+  forward_tile<L, MIR, THERMAL, DIAG, EARLY>(A, remap_block(blockIdx.x, A.P));
 }
 
 // ---------------------------------------------------------------------------
@@ -538,7 +545,7 @@ __global__ __launch_bounds__(kBlock) void k_forward(FwdArgs A) {
 // the coupling from the thermal lattice adds e_i.W, W = 4 T/(tau_g rho0) sum w b e,
 // and the thermal transpose is (1 - 1/tau_g) b_i + (1/tau_g) sum w b (1 + 4 e.u).
 // ---------------------------------------------------------------------------
-template <class L, bool MIR, bool THERMAL, int OBJ, bool DIAG, bool CONT = false>
+template <class L, bool MIR, bool THERMAL, int OBJ, bool DIAG, bool CONT = false, bool EARLY = false>
 __device__ __forceinline__ void adjoint_tile(const AdjArgs& A, int blk) {
   using G = typename ThermalOf<L>::type;  // thermal lattice
   static_assert(!(CONT && THERMAL), "the continuous variant is for the flow lattice");
@@ -551,6 +558,14 @@ __device__ __forceinline__ void adjoint_tile(const AdjArgs& A, int blk) {
     const Mirror mr = MIR ? mirror_of(x, y, z, P) : Mirror{false, false, false};
     const unsigned fl = A.flags[n];
     const int kind = fl & 7, nc = (fl >> 3) & 7;
+    float gam_n = 1.0f, ux_n = 0.f, uy_n = 0.f, uz_n = 0.f, T_n = 0.f;
+    if constexpr (EARLY) {
+      gam_n = A.gamma[n];
+      ux_n = A.u[n];
+      uy_n = A.u[P.N + n];
+      if constexpr (L::Q != 9) uz_n = A.u[2 * P.N + n];
+      if constexpr (THERMAL) T_n = A.T[n];
+    }
     float a[L::Q];
     sfor<L::Q>([&](auto I) {
       constexpr int i = I;
@@ -614,9 +629,18 @@ __device__ __forceinline__ void adjoint_tile(const AdjArgs& A, int blk) {
         });
       }
     } else {
-      const float ux = A.u[n], uy = A.u[P.N + n], uz = (L::Q == 9) ? 0.0f : A.u[2 * P.N + n];  // 2D: no z component
-      float gam = 1.0f;
-      if (kind == K_DESIGN) gam = A.gamma[n];
+      float ux, uy, uz, gam = 1.0f;
+      if constexpr (EARLY) {
+        ux = ux_n;
+        uy = uy_n;
+        uz = uz_n;
+        gam = (kind == K_DESIGN) ? gam_n : 1.0f;
+      } else {
+        ux = A.u[n];
+        uy = A.u[P.N + n];
+        uz = (L::Q == 9) ? 0.0f : A.u[2 * P.N + n];  // 2D: no z component
+        if (kind == K_DESIGN) gam = A.gamma[n];
+      }
       const float chi = (kind == K_DESIGN) ? chi_of(gam, P) : 1.0f;
       const float vx = chi * ux, vy = chi * uy, vz = chi * uz;
       float M0 = 0.f, M1x = 0.f, M1y = 0.f, M1z = 0.f, Kx = 0.f, Ky = 0.f, Kz = 0.f;
@@ -636,7 +660,7 @@ __device__ __forceinline__ void adjoint_tile(const AdjArgs& A, int blk) {
       float Wx = 0.f, Wy = 0.f, Wz = 0.f;
       float Bg = 0.f, og = 0.f, Sbw = 0.f;
       if constexpr (THERMAL) {
-        const float Tn = A.T[n];
+        const float Tn = EARLY ? T_n : A.T[n];
         const float tg = 0.5f + P.dfc * ((kind == K_DESIGN) ? khat_of(gam, P) : 1.0f);
         og = 1.0f / tg;
         float Sb = 0.f, Mbx = 0.f, Mby = 0.f, Mbz = 0.f;
@@ -711,9 +735,9 @@ __device__ __forceinline__ void adjoint_tile(const AdjArgs& A, int blk) {
   if constexpr (DIAG) block_reduce_store<kRedAdj>(acc, A.partials + (size_t)blk * kRedAdj);
 }
 
-template <class L, bool MIR, bool THERMAL, int OBJ, bool DIAG, bool CONT = false>
+template <class L, bool MIR, bool THERMAL, int OBJ, bool DIAG, bool CONT = false, bool EARLY = false>
 __global__ __launch_bounds__(kBlock) void k_adjoint(AdjArgs A) {
-  adjoint_tile<L, MIR, THERMAL, OBJ, DIAG, CONT>(A, remap_block(blockIdx.x, A.P));
+  adjoint_tile<L, MIR, THERMAL, OBJ, DIAG, CONT, EARLY>(A, remap_block(blockIdx.x, A.P));
 }
 
 // ---------------------------------------------------------------------------
@@ -1230,6 +1254,11 @@ hipError_t launch_fill(float* p, size_t count, hipStream_t s) {
 }
 
 // Launch `kern` plainly, or with start/stop events stamped by the dispatch.
+// Below this many blocks (4 waves per SIMD on 256 CUs) a lattice cannot keep
+// enough waves in flight to hide memory latency: the step kernels then read
+// the node's own inputs early (EARLY above).
+constexpr int kEarlyBlocks = 1024;
+
 template <class K, class A>
 static void launch_step(K kern, int nblk, const A& a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   if (ev0 && ev1)
@@ -1278,9 +1307,11 @@ template <class L, bool TH>
 static void fwd_dispatch(const FwdArgs& a, bool diag, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   if ((a.P.sx | a.P.sy | a.P.sz) != 0) {
     if (diag) launch_step(k_forward<L, true, TH, true>, a.P.nblk, a, s, ev0, ev1);
+    else if (TH && a.P.nblk < kEarlyBlocks) launch_step(k_forward<L, true, TH, false, TH>, a.P.nblk, a, s, ev0, ev1);
     else launch_step(k_forward<L, true, TH, false>, a.P.nblk, a, s, ev0, ev1);
   } else {
     if (diag) launch_step(k_forward<L, false, TH, true>, a.P.nblk, a, s, ev0, ev1);
+    else if (TH && a.P.nblk < kEarlyBlocks) launch_step(k_forward<L, false, TH, false, TH>, a.P.nblk, a, s, ev0, ev1);
     else launch_step(k_forward<L, false, TH, false>, a.P.nblk, a, s, ev0, ev1);
   }
 }
@@ -1312,6 +1343,7 @@ static void adj_launch(const AdjArgs& a, bool diag, hipStream_t s, hipEvent_t ev
     }
   }
   if (diag) launch_step(k_adjoint<L, MIR, TH, OBJ, true>, a.P.nblk, a, s, ev0, ev1);
+  else if (TH && a.P.nblk < kEarlyBlocks) launch_step(k_adjoint<L, MIR, TH, OBJ, false, false, TH>, a.P.nblk, a, s, ev0, ev1);
   else launch_step(k_adjoint<L, MIR, TH, OBJ, false>, a.P.nblk, a, s, ev0, ev1);
 }
 

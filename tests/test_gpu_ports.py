@@ -1,0 +1,54 @@
+"""GPU parity on a lattice whose ports cover all six inward normals
+(`workloads.six_port_box`), against the FP64 oracle: each port rule (forward
+Zou-He, its transpose, the continuous adjoint's boundary step, the thermal
+Dirichlet and outflow rules) runs in the copy specialised for its normal, so
+every copy is checked.  Fields 1e-5, dJ/dgamma 1e-4 (norm-wise relative)."""
+import pytest
+import torch
+
+import workloads as W
+from _parity import compare_solution, run_gpu, run_oracle
+from paper_2501_02161_amd import lbm
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    torch.cuda.set_device(0)
+    lbm.load_library()
+    yield
+
+
+VARIANTS = {
+    "flow_discrete": dict(),
+    "flow_continuous": dict(adjoint_kind=1),
+    "heat_generation": dict(thermal=True, objective=W.OBJ_HEATGEN, beta_max=2e-3),
+}
+
+
+@pytest.mark.parametrize("name", list(VARIANTS))
+def test_six_port_fixed_steps_parity(name):
+    w = W.six_port_box(**VARIANTS[name]).replace(max_steps=500, tol=0.0, check_every=250)
+    print(f"[ports] {name} fixed steps", flush=True)
+    prob, res = run_gpu(w)
+    o, ref = run_oracle(w, steps=500, tol=0.0, check_every=250)
+    err = compare_solution(w, prob, ref)
+    print(f"[ports] {name} errors {err} J {res['J']:.9g} vs {ref['J']:.9g}", flush=True)
+    assert abs(res["J"] - ref["J"]) <= 1e-5 * abs(ref["J"])
+    prob.close()
+
+
+@pytest.mark.parametrize("name", list(VARIANTS))
+def test_six_port_converged_parity(name):
+    w = W.six_port_box(**VARIANTS[name]).replace(max_steps=100000, tol=1e-7, check_every=250)
+    print(f"[ports] {name} converged", flush=True)
+    prob, res = run_gpu(w)
+    assert res["forward"]["status"] == 0 and res["adjoint"]["status"] == 0, res
+    o, ref = run_oracle(w, steps=400000, tol=1e-11, check_every=250)
+    assert ref["fwd_status"] == 0 and ref["adj_status"] == 0
+    err = compare_solution(w, prob, ref)
+    print(f"[ports] {name} converged steps {res['forward']['steps']}/{res['adjoint']['steps']} "
+          f"errors {err}", flush=True)
+    prob.close()

@@ -1,0 +1,52 @@
+"""Pins of the oracle on a lattice whose ports cover all six inward normals
+(`workloads.six_port_box`: pressure inlets on x = 0, y = ny-1, z = 0 and
+pressure outlets on x = nx-1, y = 0, z = nz-1), no GPU:
+
+* the steady state balances mass through the six ports (the pressure port
+  rules of Eq. 8 generalised to every normal, R7, R32);
+* the converged discrete adjoint's dJ/dgamma equals complex-step derivatives
+  of the converged J at sampled cells, flow only (dissipation) and coupled
+  with heat generation (Eqs. 54-66 with every normal's transpose).
+"""
+import concurrent.futures as cf
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from test_oracle_adjoint import _complex_step_cell, _converged, _port_fluxes
+
+
+def test_every_normal_occurs():
+    w = W.six_port_box()
+    m = w.mask.reshape(-1)
+    ports = (m & 7 == W.INLET) | (m & 7 == W.OUTLET)
+    assert sorted(set(((m[ports] >> 3) & 7).tolist())) == [0, 1, 2, 3, 4, 5]
+
+
+def test_six_port_mass_balance():
+    o = oracle.Oracle(W.six_port_box())
+    fw = o.forward(max_steps=200000, tol=1e-14, check_every=250)
+    assert fw["status"] == 0
+    mass, _ = _port_fluxes(o, fw["f"], None)
+    assert mass[W.INLET] > 0.0 and mass[W.OUTLET] < 0.0
+    assert abs(mass[W.INLET] + mass[W.OUTLET]) <= 1e-9 * mass[W.INLET]
+
+
+@pytest.mark.parametrize("variant", ["flow_dissipation", "heat_generation"])
+def test_six_port_gradient_matches_complex_step(variant):
+    w = W.six_port_box() if variant == "flow_dissipation" else \
+        W.six_port_box(thermal=True, objective=W.OBJ_HEATGEN, beta_max=2e-3)
+    o = oracle.Oracle(w)
+    fw, ad, dJ = _converged(o)
+    design = np.nonzero((w.mask.reshape(-1) & 7) == W.DESIGN)[0]
+    rng = np.random.default_rng(23)
+    cells = list(rng.choice(design, size=3, replace=False)) + [int(design[np.argmax(
+        np.abs(dJ[design]))])]
+    steps = max(int(2.5 * fw["steps"]), 3000)
+    with cf.ThreadPoolExecutor(max_workers=4) as ex:
+        ref = list(ex.map(lambda k: _complex_step_cell(o, fw, k, steps), cells))
+    scale = np.abs(dJ[design]).max()
+    for k, r in zip(cells, ref):
+        assert abs(dJ[k] - r) <= 1e-8 * scale, (k, dJ[k], r)

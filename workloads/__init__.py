@@ -429,6 +429,31 @@ def tiny_paper_heat_sink_2d(nx: int = 14, ny: int = 7, Re: float = 10.0, tau: fl
                               name=f"tiny_paper_heat_sink_2d_{nx}x{ny}")
 
 
+def six_port_box(nx: int = 14, ny: int = 13, nz: int = 12, thermal: bool = False,
+                 objective: int = OBJ_DISSIPATION, adjoint_kind: int = 0, tau: float = 0.8,
+                 drho_in: float = 3e-3, beta_max: float = 0.0,
+                 seed: Optional[int] = None) -> Workload:
+    """A walled box with one port patch on each of its six faces, so that
+    every inward normal of the port rules occurs on one lattice: pressure
+    inlets (at rho0 + drho_in) on x = 0, y = ny-1 and z = 0, pressure outlets
+    on x = nx-1, y = 0 and z = nz-1, each a 4 x 4 patch inside its face;
+    seeded smoothed design field in the interior."""
+    seed = SEED_BASE + 10 if seed is None else seed
+    m = walled_box(nx, ny, nz)
+    m[3:7, 3:7, 0] = code(INLET, NPX)
+    m[3:7, 4:8, nx - 1] = code(OUTLET, NMX)
+    m[4:8, 0, 3:7] = code(OUTLET, NPY)
+    m[4:8, ny - 1, 5:9] = code(INLET, NMY)
+    m[0, 3:7, 4:8] = code(INLET, NPZ)
+    m[nz - 1, 5:9, 3:7] = code(OUTLET, NMZ)
+    gamma = smoothed_noise((nz, ny, nx), 1.5, seed)
+    return Workload(name=f"six_port_box_{nx}x{ny}x{nz}", dim=3, nx=nx, ny=ny, nz=nz,
+                    thermal=thermal, tau=tau, Re=0.0, L_ref=1.0, objective=objective, mask=m,
+                    gamma=gamma, alpha_max=0.1, q_brink=0.1, Pr=1.0, k_ratio=10.0, q_ramp=1.0,
+                    q_w=0.0, T_in=0.0, w_dp=0.0, seed=seed, adjoint_kind=adjoint_kind,
+                    inlet_rho=1.0 + drho_in, beta_max=beta_max)
+
+
 def tiny_heat_sink(nx: int = 10, ny: int = 8, nz: int = 6, seed: int = 7, Re: float = 5.0,
                    Pr: float = 1.0, tau: float = 0.8, alpha_max: float = 0.2,
                    sigma: float = 1.0) -> Workload:

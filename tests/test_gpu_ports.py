@@ -25,6 +25,10 @@ VARIANTS = {
     "flow_discrete": dict(),
     "flow_continuous": dict(adjoint_kind=1),
     "heat_generation": dict(thermal=True, objective=W.OBJ_HEATGEN, beta_max=2e-3),
+    "2d_flow_discrete": dict(nz=1, nx=16, ny=14),
+    "2d_flow_continuous": dict(nz=1, nx=16, ny=14, adjoint_kind=1),
+    "2d_heat_generation": dict(nz=1, nx=16, ny=14, thermal=True, objective=W.OBJ_HEATGEN,
+                               beta_max=2e-3),
 }
 
 

@@ -6,7 +6,8 @@ pressure outlets on x = nx-1, y = 0, z = nz-1), no GPU:
   rules of Eq. 8 generalised to every normal, R7, R32);
 * the converged discrete adjoint's dJ/dgamma equals complex-step derivatives
   of the converged J at sampled cells, flow only (dissipation) and coupled
-  with heat generation (Eqs. 54-66 with every normal's transpose).
+  with heat generation (Eqs. 54-66 with every normal's transpose), in 3D and
+  in the 2D form (four ports, D2Q9 + D2Q5).
 """
 import concurrent.futures as cf
 
@@ -19,10 +20,11 @@ from test_oracle_adjoint import _complex_step_cell, _converged, _port_fluxes
 
 
 def test_every_normal_occurs():
-    w = W.six_port_box()
-    m = w.mask.reshape(-1)
-    ports = (m & 7 == W.INLET) | (m & 7 == W.OUTLET)
-    assert sorted(set(((m[ports] >> 3) & 7).tolist())) == [0, 1, 2, 3, 4, 5]
+    for w, normals in ((W.six_port_box(), [0, 1, 2, 3, 4, 5]),
+                       (W.six_port_box(nz=1, nx=16, ny=14), [0, 1, 2, 3])):
+        m = w.mask.reshape(-1)
+        ports = (m & 7 == W.INLET) | (m & 7 == W.OUTLET)
+        assert sorted(set(((m[ports] >> 3) & 7).tolist())) == normals
 
 
 def test_six_port_mass_balance():
@@ -34,10 +36,12 @@ def test_six_port_mass_balance():
     assert abs(mass[W.INLET] + mass[W.OUTLET]) <= 1e-9 * mass[W.INLET]
 
 
-@pytest.mark.parametrize("variant", ["flow_dissipation", "heat_generation"])
+@pytest.mark.parametrize("variant", ["flow_dissipation", "heat_generation", "2d_flow",
+                                     "2d_heat_generation"])
 def test_six_port_gradient_matches_complex_step(variant):
-    w = W.six_port_box() if variant == "flow_dissipation" else \
-        W.six_port_box(thermal=True, objective=W.OBJ_HEATGEN, beta_max=2e-3)
+    kw = {"nz": 1, "nx": 16, "ny": 14} if variant.startswith("2d") else {}
+    w = W.six_port_box(**kw) if variant.endswith("flow") or variant == "flow_dissipation" else \
+        W.six_port_box(thermal=True, objective=W.OBJ_HEATGEN, beta_max=2e-3, **kw)
     o = oracle.Oracle(w)
     fw, ad, dJ = _converged(o)
     design = np.nonzero((w.mask.reshape(-1) & 7) == W.DESIGN)[0]

@@ -437,17 +437,26 @@ def six_port_box(nx: int = 14, ny: int = 13, nz: int = 12, thermal: bool = False
     every inward normal of the port rules occurs on one lattice: pressure
     inlets (at rho0 + drho_in) on x = 0, y = ny-1 and z = 0, pressure outlets
     on x = nx-1, y = 0 and z = nz-1, each a 4 x 4 patch inside its face;
-    seeded smoothed design field in the interior."""
+    seeded smoothed design field in the interior.  With nz = 1 the 2D form:
+    four ports of 4 nodes, one per edge (D2Q9, every 2D normal)."""
     seed = SEED_BASE + 10 if seed is None else seed
-    m = walled_box(nx, ny, nz)
-    m[3:7, 3:7, 0] = code(INLET, NPX)
-    m[3:7, 4:8, nx - 1] = code(OUTLET, NMX)
-    m[4:8, 0, 3:7] = code(OUTLET, NPY)
-    m[4:8, ny - 1, 5:9] = code(INLET, NMY)
-    m[0, 3:7, 4:8] = code(INLET, NPZ)
-    m[nz - 1, 5:9, 3:7] = code(OUTLET, NMZ)
+    if nz == 1:
+        # the 2D form: four ports, one per edge (D2Q9 + D2Q5)
+        m = walled_box(nx, ny, 1, dim=2)
+        m[0, 3:7, 0] = code(INLET, NPX)
+        m[0, 4:8, nx - 1] = code(OUTLET, NMX)
+        m[0, 0, 3:7] = code(OUTLET, NPY)
+        m[0, ny - 1, 5:9] = code(INLET, NMY)
+    else:
+        m = walled_box(nx, ny, nz)
+        m[3:7, 3:7, 0] = code(INLET, NPX)
+        m[3:7, 4:8, nx - 1] = code(OUTLET, NMX)
+        m[4:8, 0, 3:7] = code(OUTLET, NPY)
+        m[4:8, ny - 1, 5:9] = code(INLET, NMY)
+        m[0, 3:7, 4:8] = code(INLET, NPZ)
+        m[nz - 1, 5:9, 3:7] = code(OUTLET, NMZ)
     gamma = smoothed_noise((nz, ny, nx), 1.5, seed)
-    return Workload(name=f"six_port_box_{nx}x{ny}x{nz}", dim=3, nx=nx, ny=ny, nz=nz,
+    return Workload(name=f"six_port_box_{nx}x{ny}x{nz}", dim=2 if nz == 1 else 3, nx=nx, ny=ny, nz=nz,
                     thermal=thermal, tau=tau, Re=0.0, L_ref=1.0, objective=objective, mask=m,
                     gamma=gamma, alpha_max=0.1, q_brink=0.1, Pr=1.0, k_ratio=10.0, q_ramp=1.0,
                     q_w=0.0, T_in=0.0, w_dp=0.0, seed=seed, adjoint_kind=adjoint_kind,

@@ -2,7 +2,8 @@
 (`workloads.six_port_box`), against the FP64 oracle: each port rule (forward
 Zou-He, its transpose, the continuous adjoint's boundary step, the thermal
 Dirichlet and outflow rules) runs in the copy specialised for its normal, so
-every copy is checked.  Fields 1e-5, dJ/dgamma 1e-4 (norm-wise relative)."""
+every copy is checked; with `heated` the heated-wall rule meets every
+normal too.  Fields 1e-5, dJ/dgamma 1e-4 (norm-wise relative)."""
 import pytest
 import torch
 
@@ -29,6 +30,9 @@ VARIANTS = {
     "2d_flow_continuous": dict(nz=1, nx=16, ny=14, adjoint_kind=1),
     "2d_heat_generation": dict(nz=1, nx=16, ny=14, thermal=True, objective=W.OBJ_HEATGEN,
                                beta_max=2e-3),
+    "heated_walls": dict(thermal=True, objective=W.OBJ_HEATSINK, heated=True),
+    "2d_heated_walls": dict(nz=1, nx=16, ny=14, thermal=True, objective=W.OBJ_HEATSINK,
+                            heated=True),
 }
 
 

@@ -431,14 +431,16 @@ def tiny_paper_heat_sink_2d(nx: int = 14, ny: int = 7, Re: float = 10.0, tau: fl
 
 def six_port_box(nx: int = 14, ny: int = 13, nz: int = 12, thermal: bool = False,
                  objective: int = OBJ_DISSIPATION, adjoint_kind: int = 0, tau: float = 0.8,
-                 drho_in: float = 3e-3, beta_max: float = 0.0,
+                 drho_in: float = 3e-3, beta_max: float = 0.0, heated: bool = False,
                  seed: Optional[int] = None) -> Workload:
     """A walled box with one port patch on each of its six faces, so that
     every inward normal of the port rules occurs on one lattice: pressure
     inlets (at rho0 + drho_in) on x = 0, y = ny-1 and z = 0, pressure outlets
     on x = nx-1, y = 0 and z = nz-1, each a 4 x 4 patch inside its face;
     seeded smoothed design field in the interior.  With nz = 1 the 2D form:
-    four ports of 4 nodes, one per edge (D2Q9, every 2D normal)."""
+    four ports of 4 nodes, one per edge (D2Q9, every 2D normal).  `heated`
+    adds a HEATED patch (q_w = 0.01) beside the port on every face or edge,
+    so the heated-wall rule also meets every inward normal."""
     seed = SEED_BASE + 10 if seed is None else seed
     if nz == 1:
         # the 2D form: four ports, one per edge (D2Q9 + D2Q5)
@@ -447,6 +449,11 @@ def six_port_box(nx: int = 14, ny: int = 13, nz: int = 12, thermal: bool = False
         m[0, 4:8, nx - 1] = code(OUTLET, NMX)
         m[0, 0, 3:7] = code(OUTLET, NPY)
         m[0, ny - 1, 5:9] = code(INLET, NMY)
+        if heated:
+            m[0, 8:11, 0] = code(HEATED, NPX)
+            m[0, 9:12, nx - 1] = code(HEATED, NMX)
+            m[0, 0, 9:12] = code(HEATED, NPY)
+            m[0, ny - 1, 10:13] = code(HEATED, NMY)
     else:
         m = walled_box(nx, ny, nz)
         m[3:7, 3:7, 0] = code(INLET, NPX)
@@ -455,11 +462,19 @@ def six_port_box(nx: int = 14, ny: int = 13, nz: int = 12, thermal: bool = False
         m[4:8, ny - 1, 5:9] = code(INLET, NMY)
         m[0, 3:7, 4:8] = code(INLET, NPZ)
         m[nz - 1, 5:9, 3:7] = code(OUTLET, NMZ)
+        if heated:
+            m[8:10, 8:11, 0] = code(HEATED, NPX)
+            m[8:10, 8:11, nx - 1] = code(HEATED, NMX)
+            m[8:10, 0, 8:11] = code(HEATED, NPY)
+            m[1:3, ny - 1, 9:12] = code(HEATED, NMY)
+            m[0, 8:11, 9:12] = code(HEATED, NPZ)
+            m[nz - 1, 1:4, 9:12] = code(HEATED, NMZ)
     gamma = smoothed_noise((nz, ny, nx), 1.5, seed)
     return Workload(name=f"six_port_box_{nx}x{ny}x{nz}", dim=2 if nz == 1 else 3, nx=nx, ny=ny, nz=nz,
                     thermal=thermal, tau=tau, Re=0.0, L_ref=1.0, objective=objective, mask=m,
                     gamma=gamma, alpha_max=0.1, q_brink=0.1, Pr=1.0, k_ratio=10.0, q_ramp=1.0,
-                    q_w=0.0, T_in=0.0, w_dp=0.0, seed=seed, adjoint_kind=adjoint_kind,
+                    q_w=0.01 if heated else 0.0, T_in=0.0, w_dp=0.0, seed=seed,
+                    adjoint_kind=adjoint_kind,
                     inlet_rho=1.0 + drho_in, beta_max=beta_max)
 
 

@@ -247,7 +247,8 @@ def paper_heat_sink(nx: int = 128, ny: int = 33, nz: int = 25, Re: float = 60.0,
 def mirror_full(w: Workload) -> Workload:
     """The full-domain problem whose quarter (or half) is w: every symmetric
     axis is unfolded about its mirror plane (the SYM layer dropped, the rest
-    reflected), mask and design field alike."""
+    reflected, with the inward normals along that axis reversed in the
+    reflected copy), mask and design field alike."""
     m, g = w.mask, w.gamma
     for a, ax in ((0, 2), (1, 1), (2, 0)):   # x, y, z -> array axes 2, 1, 0
         if not w.symmetric[a]:
@@ -255,7 +256,12 @@ def mirror_full(w: Workload) -> Workload:
         sl = [slice(None)] * 3
         sl[ax] = slice(0, m.shape[ax] - 1)
         m, g = m[tuple(sl)], g[tuple(sl)]
-        m = np.concatenate([m, np.flip(m, axis=ax)], axis=ax)
+        # the reflected copy: inward normals along the axis change sign
+        r = np.flip(m, axis=ax).copy()
+        kind, nc = r & 7, (r >> 3) & 7
+        along = np.isin(kind, (INLET, OUTLET, HEATED)) & (nc // 2 == a)
+        r[along] = (kind[along] | ((nc[along] ^ 1) << 3)).astype(np.uint8)
+        m = np.concatenate([m, r], axis=ax)
         g = np.concatenate([g, np.flip(g, axis=ax)], axis=ax)
     nz, ny, nx = m.shape
     return w.replace(mask=np.ascontiguousarray(m), gamma=np.ascontiguousarray(g), nx=nx, ny=ny,

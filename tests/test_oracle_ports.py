@@ -39,8 +39,10 @@ def test_six_port_mass_balance():
 
 VARIANTS = {
     "flow_dissipation": dict(),
-    "heat_generation": dict(thermal=True, objective=W.OBJ_HEATGEN, beta_max=2e-3),
-    "heated_walls": dict(thermal=True, objective=W.OBJ_HEATSINK, heated=True),
+    # heat generation and heated walls on every face together (one slow 3D
+    # thermal case instead of two)
+    "heat_generation_heated_walls": dict(thermal=True, objective=W.OBJ_HEATGEN, beta_max=1e-2,
+                                         heated=True),
     "2d_flow": dict(nz=1, nx=16, ny=14),
     "2d_heat_generation": dict(nz=1, nx=16, ny=14, thermal=True, objective=W.OBJ_HEATGEN,
                                beta_max=2e-3),

@@ -1136,6 +1136,17 @@ bool build_problem(const OrcConfig& c, const uint8_t* mask, Problem& P, std::str
       err = "SYM nodes must fill exactly the last layer of each symmetric axis";
       return false;
     }
+    // a port sits on the face its inward normal points away from; a heated
+    // wall's inward neighbour lies inside the box
+    const int k = P.kind[n], nc = P.ncode[n], ax = nc / 2, sgn = (nc % 2 == 0) ? 1 : -1;
+    if ((k == K_INLET || k == K_OUTLET) && x[ax] != (sgn > 0 ? 0 : lim[ax] - 1)) {
+      err = "port normal is not the inward normal of its face";
+      return false;
+    }
+    if (k == K_HEATED && (x[ax] + sgn < 0 || x[ax] + sgn >= lim[ax])) {
+      err = "heated wall normal points out of the box";
+      return false;
+    }
   }
   if (c.beta_max < 0.0 || (c.beta_max > 0.0 && !c.thermal)) {
     err = "beta_max must be >= 0 and needs the thermal lattice";

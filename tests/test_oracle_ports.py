@@ -66,3 +66,17 @@ def test_six_port_gradient_matches_complex_step(variant):
     scale = np.abs(dJ[design]).max()
     for k, r in zip(cells, ref):
         assert abs(dJ[k] - r) <= 1e-8 * scale, (k, dJ[k], r)
+
+
+def test_oracle_rejects_outward_port_normals():
+    """A port whose normal points out of the box (the mistake of unfolding a
+    mirror plane without reversing the normals along it) is refused."""
+    w = W.six_port_box()
+    m = w.mask.copy()
+    m[3:7, 4:8, w.nx - 1] = W.code(W.OUTLET, W.NPX)
+    with pytest.raises(ValueError, match="inward normal"):
+        oracle.Oracle(w.replace(mask=m))
+    m = w.mask.copy()
+    m[0, 8:11, 9:12] = W.code(W.HEATED, W.NMZ)
+    with pytest.raises(ValueError, match="out of the box"):
+        oracle.Oracle(w.replace(mask=m))

@@ -260,8 +260,10 @@ __device__ __forceinline__ void with_normal(int nc, F&& f) {
 //   h_i = h_ibar + 6 w_i j_n - 1/2 e_i.N,  N = sum_{e_j.n = 0} e_j h_j
 // (N has no normal component, so e_i.N is the sum over the tangential axes);
 // j_n = rho0 u_n at a velocity inlet, and at a pressure outlet rho = rho0
-// gives j_n = -sum_{e.n=0} h - 2 sum_{e.n<0} h.  Written with selects on the
-// runtime normal so the populations stay in registers.
+// gives j_n = -sum_{e.n=0} h - 2 sum_{e.n<0} h.  Written generically in the
+// normal with selects, so the populations stay in registers; the step kernels
+// call it through with_normal, where the normal is a constant and the
+// selects fold.
 // ---------------------------------------------------------------------------
 // Generic Zou-He rule on shifted populations (f - w rho0).  Velocity inlet:
 // prescribed rho0 u_n = jn_in.  Pressure outlet / pressure inlet:

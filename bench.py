@@ -33,6 +33,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "fwd+adj MLUPS & % HBM peak (D3Q19+D3Q7 FP32); p50/p99 sensitivity latency"
 HBM_PEAK_GBS = 8000.0
+MALL_BYTES = 256 * 1024 * 1024      # Infinity Cache of the device
+STATUS = {0: "converged", 1: "step cap reached"}
 
 def bytes_per_node(kernel, w):
     """Algorithmic bytes per node-update of a step kernel for workload w:
@@ -68,7 +70,10 @@ def parse():
                     help="adjoint kind (the continuous variant is for the flow-only pipe bend)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-fwd-steps", type=int, default=0,
-                    help="oracle sample size in forward steps (0: 48)")
+                    help="oracle sample size in forward (and as many adjoint) steps (0: 300)")
+    ap.add_argument("--out-of-cache-steps", type=int, default=1000,
+                    help="fixed forward and adjoint steps of the out-of-cache heat sink "
+                         "320x160x80 timed for its roofline object (0: skip)")
     ap.add_argument("--profile", action="store_true",
                     help="profiling run for rocprofv3: a plain device copy of known size, then "
                          "one forward + adjoint + sensitivity solve of --fixed-steps steps each")
@@ -150,9 +155,12 @@ def profile_run(args):
 
 
 def copy_bandwidth(quiet=False):
-    """Best read+write bandwidth of torch's device copy on 1 GiB buffers (out
-    of the 256 MB Infinity Cache)."""
+    """Best read+write bandwidth of a device copy of 1 GiB (out of the 256 MB
+    Infinity Cache): torch's copy kernel and the library's own 16-byte
+    streaming copy (lbm_copy_probe), the measured HBM ceiling of a plain
+    stream beside the vendor peak."""
     import torch
+    from paper_2501_02161_amd import lbm
     torch.cuda.set_device(0)
     n = 256 * 1024 * 1024
     a = torch.ones(n, dtype=torch.float32, device="cuda:0")
@@ -167,7 +175,11 @@ def copy_bandwidth(quiet=False):
         e1.record()
         e1.synchronize()
         best = max(best, 2 * n * 4 / (e0.elapsed_time(e1) / 1e3) / 1e9)
-    out = {"copy_GBps_read_plus_write": round(best, 1), "bytes": 2 * n * 4}
+    us = min(lbm.lbm_copy_probe(a, b, 10) for _ in range(3))
+    own = 2 * n * 4 / (us * 1e-6) / 1e9
+    out = {"copy_GBps_read_plus_write": round(best, 1), "bytes": 2 * n * 4,
+           "dwordx4_copy_GBps": round(own, 1),
+           "best_GBps": round(max(best, own), 1)}
     del a, b
     torch.cuda.empty_cache()
     if not quiet:
@@ -175,17 +187,21 @@ def copy_bandwidth(quiet=False):
     return out
 
 
-COUNTERS = os.path.join(ROOT, "profiles", "hbm_counters_heat_sink_160x80x40_Re200.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2501_02161_amd", "csrc", "lbm_kernels.hip")
+
+
+def counters_path(workload):
+    return os.path.join(ROOT, "profiles", f"hbm_counters_{workload}.json")
 
 
 def counter_traffic(workload, kernel):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary (FETCH_SIZE and WRITE_SIZE scaled by the copy-kernel calibration),
-    or None if there is none for this workload or the kernels changed since."""
+    summary of `workload` (FETCH_SIZE and WRITE_SIZE scaled by the copy-kernel
+    calibration), or None if there is none for this workload or the kernels
+    changed since."""
     import hashlib
     try:
-        with open(COUNTERS) as fh:
+        with open(counters_path(workload)) as fh:
             c = json.load(fh)
         with open(KERNEL_SRC, "rb") as fh:
             sha = hashlib.sha256(fh.read()).hexdigest()
@@ -219,9 +235,61 @@ def make_workload(name, adjoint="discrete", Re=0.0):
     if name.startswith("paper_heat_sink"):
         return W.paper_heat_sink(Re=float(name.split("Re")[1]))
     if name == "heat_sink_320x160x80_Re200":
-        return W.heat_sink(320, 160, 80, Re=200.0, name="heat_sink_320x160x80_Re200")
+        return out_of_cache_workload()
     Re = float(name.split("Re")[1])
     return W.heat_sink(Re=Re)
+
+
+def out_of_cache_workload():
+    """The heat sink at twice the benchmark grid in every axis (4.1 M nodes,
+    0.87 GB of populations per forward step): its working set does not fit
+    the 256 MB Infinity Cache, so its step kernels stream from HBM."""
+    import workloads as W
+    return W.heat_sink(320, 160, 80, Re=200.0, name="heat_sink_320x160x80_Re200")
+
+
+def working_set_bytes(kernel, w):
+    """Bytes a step kernel touches per launch: both population buffers and
+    the per-node inputs."""
+    return bytes_per_node(kernel, w) * w.N
+
+
+def out_of_cache_leg(fixed_steps, copy_best_gbps):
+    """Step kernels of the out-of-cache heat sink at a fixed number of forward
+    and adjoint steps (their average launch duration from the sweep events),
+    against the vendor HBM peak and the measured device copy."""
+    import torch
+    from paper_2501_02161_amd import lbm
+    w = out_of_cache_workload().replace(max_steps=fixed_steps, tol=0.0, check_every=1000)
+    prob = lbm.Problem(w, device="cuda:0")
+    gamma = prob.gamma_tensor(w.gamma)
+    warm = lbm.Problem(w.replace(max_steps=200), device="cuda:0")
+    warm.solve(gamma)
+    warm.close()
+    del warm
+    torch.cuda.synchronize()
+    lbm.lbm_set_kernel_timing(prob.h, True)
+    lbm.lbm_kernel_timing(prob.h, reset=True)
+    res = prob.solve(gamma)
+    torch.cuda.synchronize()
+    (ms_f, ms_a), (n_f, n_a) = lbm.lbm_kernel_timing(prob.h, reset=True)
+    prob.close()
+    out = {"workload": w.name, "nodes": w.N, "fwd_steps": res["forward"]["steps"],
+           "adj_steps": res["adjoint"]["steps"], "bound": "hbm", "peak": HBM_PEAK_GBS,
+           "unit": "GB/s", "device_copy_GBps": copy_best_gbps, "kernels": {}}
+    for k, ms, n in (("forward", ms_f, n_f), ("adjoint", ms_a, n_a)):
+        bpl = bytes_per_node(k, w) * w.N
+        ach = bpl / (ms / 1e3 / n) / 1e9
+        out["kernels"][k] = {"avg_us": round(ms * 1e3 / n, 3), "launches": n,
+                             "algorithmic_bytes_per_launch": bpl, "achieved": round(ach, 1),
+                             "frac": round(ach / HBM_PEAK_GBS, 4),
+                             "frac_of_device_copy": round(ach / copy_best_gbps, 4)
+                             if copy_best_gbps else None,
+                             "traffic": counter_traffic(w.name, k)}
+    dom = max(out["kernels"], key=lambda k: out["kernels"][k]["avg_us"] * out["kernels"][k]["launches"])
+    out.update({"kernel": dom, "achieved": out["kernels"][dom]["achieved"],
+                "frac": out["kernels"][dom]["frac"], "traffic": out["kernels"][dom]["traffic"]})
+    return out
 
 
 def _oracle_rate(o, w, fwd_steps, adj_steps):
@@ -238,12 +306,12 @@ def _oracle_rate(o, w, fwd_steps, adj_steps):
 
 
 def cpu_baseline(w, fwd_steps):
-    """The oracle (as it is) on the host cores: a bounded sample of forward and
-    adjoint steps of the same workload from rest; beside it a shorter sample
-    on one core."""
+    """The oracle (as it is) on the host cores: a bounded sample of equal
+    numbers of forward and adjoint steps of the same workload from rest;
+    beside it a shorter sample on one core."""
     import oracle
     o = oracle.Oracle(w)
-    adj_steps = max(1, fwd_steps // 4)
+    adj_steps = fwd_steps
     tf, ta = _oracle_rate(o, w, fwd_steps, adj_steps)
     # the GPU solve takes about as many adjoint as forward steps
     mlups = 2 * w.N / (tf + ta) / 1e6
@@ -253,7 +321,7 @@ def cpu_baseline(w, fwd_steps):
                      f"(FP64, {tf * 1e3:.0f} ms/forward step, {ta * 1e3:.0f} ms/adjoint step; "
                      f"rate for equal forward and adjoint step counts)"}
     if cores > 1:
-        f1, a1 = max(1, fwd_steps // 6), max(1, adj_steps // 6)
+        f1, a1 = max(1, fwd_steps // 30), max(1, adj_steps // 30)
         oracle.set_threads(1)
         try:
             tf1, ta1 = _oracle_rate(o, w, f1, a1)
@@ -539,13 +607,22 @@ def main():
                    "adjoint": "continuous" if w.adjoint_kind else "discrete",
                    "tau": round(w.tau, 6),
                    "tol": w.tol, "max_steps": w.max_steps, "fwd_steps": fi["steps"],
-                   "adj_steps": ai["steps"], "J": J},
+                   "adj_steps": ai["steps"], "J": J,
+                   "fwd_status": STATUS.get(fi["status"], fi["status"]),
+                   "adj_status": STATUS.get(ai["status"], ai["status"]),
+                   "fwd_residual": [float(v) for v in fi["residual"]],
+                   "adj_residual": [float(v) for v in ai["residual"]]},
         "roofline": {"bound": "hbm", "kernel": dom,
                      "achieved": round(achieved, 1) if achieved else None,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
                      "traffic": counter_traffic(w.name, dom),
-                     "algorithmic_bytes_per_launch": bpn * w.N},
+                     "algorithmic_bytes_per_launch": bpn * w.N,
+                     # the populations a sweep keeps touching fit the Infinity
+                     # Cache, so the kernel may stream faster than HBM alone
+                     "working_set_bytes": working_set_bytes(dom, w),
+                     "residency": "infinity_cache" if working_set_bytes(dom, w) < MALL_BYTES
+                                  else "hbm"},
         "kernels": per_kernel,
         "hbm_frac_whole_job": round(
             (bytes_per_node("forward", w) * w.N * fi["steps"] +
@@ -565,11 +642,16 @@ def main():
     prob.close()
     # the best measured device copy beside the vendor peak
     out["copy_bandwidth"] = copy_bandwidth(quiet=True)
+    best = out["copy_bandwidth"]["best_GBps"]
+    if achieved:
+        out["roofline"]["frac_of_device_copy"] = round(achieved / best, 4)
+    if args.out_of_cache_steps > 0 and w.name != out_of_cache_workload().name:
+        out["roofline_out_of_cache"] = out_of_cache_leg(args.out_of_cache_steps, best)
     if args.serving_requests > 0:
         out["serving"] = serving_leg(args.serving_requests, args.serving_rate,
                                      args.serving_policy, args.serving_fill)
     if not args.no_cpu_baseline:
-        steps = args.cpu_fwd_steps or 48
+        steps = args.cpu_fwd_steps or 300
         out["cpu_baseline"] = cpu_baseline(w, steps)
     print(json.dumps(out), flush=True)
 

@@ -329,6 +329,18 @@ int lbm_kernel_timing(lbm_problem_t* p, double* ms, int64_t* launches, int32_t r
 int lbm_stream_probe(lbm_problem_t* p, const float* gamma, int32_t launches, double* us_per_launch,
                      void* stream);
 
+/* Device-copy ceiling: `launches` back-to-back launches (after 3 untimed
+ * ones) of the library's streaming copy kernel (16-byte loads and stores,
+ * coalesced) from src to dst, `bytes` each; the average time per launch (HIP
+ * events on `stream`, synchronised) goes to us_per_launch.  2 * bytes over
+ * that time is the read + write bandwidth the device gives a plain stream;
+ * buffers larger than the 256 MB Infinity Cache measure HBM.  src, dst:
+ * caller-owned device buffers, 16-byte aligned, not overlapping; dst is
+ * overwritten.  LBM_EINVAL for null or misaligned pointers, overlap, bytes
+ * not a positive multiple of 16, or launches outside [1, 1000000]. */
+int lbm_copy_probe(const void* src, void* dst, uint64_t bytes, int32_t launches,
+                   double* us_per_launch, void* stream);
+
 /* Direction table of the library: which 0 = D3Q19 (19 entries), 1 = D3Q7
  * (7 entries), 2 = D2Q9 (9 entries, e_z = 0), 3 = D2Q5 (5 entries); e
  * receives 3 ints per direction, w the weight. */

@@ -24,26 +24,56 @@ def hipcc() -> str:
     return "hipcc"
 
 
-def command(out: str) -> list:
-    return [hipcc(), "-std=c++17", "-O3", f"--offload-arch={ARCH}", "-fPIC", "-shared",
-            # packed-FP32 instructions stay off: the compiler may not emit v_pk_*_f32
-            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-            "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument",
-            "-I", os.path.join(ROOT, "include"), "-o", out] + SOURCES
+FLAGS = ["-std=c++17", "-O3", f"--offload-arch={ARCH}", "-fPIC",
+         # packed-FP32 instructions stay off: the compiler may not emit v_pk_*_f32
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument",
+         "-I", os.path.join(ROOT, "include")]
+
+
+def compile_commands(tmpdir: str) -> list:
+    """One hipcc -c per source (run in parallel), then the shared-library link."""
+    objs = [os.path.join(tmpdir, os.path.basename(src) + ".o") for src in SOURCES]
+    cc = [[hipcc()] + FLAGS + ["-c", src, "-o", obj] for src, obj in zip(SOURCES, objs)]
+    return cc, objs
 
 
 def build(verbose: bool = False) -> str:
     """Compile the library (always) and return its path."""
     os.makedirs(os.path.dirname(LIB), exist_ok=True)
+    tmpdir = os.path.join(os.path.dirname(LIB), f"obj{os.getpid()}")
+    os.makedirs(tmpdir, exist_ok=True)
     tmp = LIB + f".tmp{os.getpid()}"
-    cmd = command(tmp)
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed building liblbmadj.so")
-    os.replace(tmp, LIB)
+    cc, objs = compile_commands(tmpdir)
+    link = [hipcc(), f"--offload-arch={ARCH}", "-fPIC", "-shared", "-o", tmp] + objs
+    try:
+        procs = []
+        for cmd in cc:
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            procs.append(subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT,
+                                          text=True))
+        failed = False
+        for pr in procs:
+            out, _ = pr.communicate()
+            if pr.returncode != 0:
+                sys.stderr.write(out)
+                failed = True
+        if failed:
+            raise RuntimeError("hipcc failed compiling liblbmadj.so")
+        if verbose:
+            print(" ".join(link), flush=True)
+        r = subprocess.run(link, capture_output=True, text=True)
+        if r.returncode != 0:
+            sys.stderr.write(r.stdout + r.stderr)
+            raise RuntimeError("hipcc failed linking liblbmadj.so")
+        os.replace(tmp, LIB)
+    finally:
+        for f in objs:
+            if os.path.exists(f):
+                os.remove(f)
+        if os.path.isdir(tmpdir):
+            os.rmdir(tmpdir)
     return LIB
 
 

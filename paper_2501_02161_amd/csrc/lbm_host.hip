@@ -833,6 +833,39 @@ int lbm_kernel_timing(lbm_problem_t* p, double* ms, int64_t* launches, int32_t r
   return LBM_OK;
 }
 
+int lbm_copy_probe(const void* src, void* dst, uint64_t bytes, int32_t launches,
+                   double* us_per_launch, void* stream) {
+  last_error().clear();
+  if (!src || !dst || !us_per_launch) return fail(LBM_EINVAL, "null argument");
+  if (((uintptr_t)src | (uintptr_t)dst) & 15u) return fail(LBM_EINVAL, "buffers must be 16-byte aligned");
+  if (bytes == 0 || (bytes & 15u)) return fail(LBM_EINVAL, "bytes must be a positive multiple of 16");
+  if (launches < 1 || launches > 1000000) return fail(LBM_EINVAL, "launches must be in [1, 1000000]");
+  const char* s0 = (const char*)src;
+  const char* d0 = (const char*)dst;
+  if (s0 < d0 + bytes && d0 < s0 + bytes) return fail(LBM_EINVAL, "buffers overlap");
+  hipStream_t s = (hipStream_t)stream;
+  const size_t n16 = (size_t)(bytes / 16);
+  for (int i = 0; i < 3; ++i) HIPCHK(launch_copy16(src, dst, n16, s));
+  hipEvent_t ev[2];
+  HIPCHK(hipEventCreate(&ev[0]));
+  hipError_t e = hipEventCreate(&ev[1]);
+  if (e != hipSuccess) {
+    (void)hipEventDestroy(ev[0]);
+    return fail(LBM_EDEVICE, std::string("hipEventCreate: ") + hipGetErrorString(e));
+  }
+  e = hipEventRecord(ev[0], s);
+  for (int i = 0; i < launches && e == hipSuccess; ++i) e = launch_copy16(src, dst, n16, s);
+  if (e == hipSuccess) e = hipEventRecord(ev[1], s);
+  if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+  float ms = 0.0f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
+  if (e != hipSuccess) return fail(LBM_EDEVICE, std::string("copy probe: ") + hipGetErrorString(e));
+  *us_per_launch = (double)ms * 1e3 / launches;
+  return LBM_OK;
+}
+
 int lbm_stream_probe(lbm_problem_t* p, const float* gamma, int32_t launches, double* us_per_launch,
                      void* stream) {
   last_error().clear();

@@ -132,6 +132,8 @@ struct Tile {
 
 // Launchers (return the hipError_t of the launch).
 hipError_t launch_fill(float* p, size_t count, hipStream_t s);
+// Copy of n16 16-byte words (dwordx4 loads and stores); both pointers 16-byte aligned.
+hipError_t launch_copy16(const void* src, void* dst, size_t n16, hipStream_t s);
 // Level-set design update (per-block FP64 partials: stats 2 values, lambda 1).
 hipError_t launch_levelset_stats(const float* phi, const float* dJ, const uint8_t* flags,
                                  double* partials, const KParams& P, hipStream_t s);

@@ -522,7 +522,9 @@ __device__ __forceinline__ void forward_tile(const FwdArgs& A, int blk) {
         acc[0] = sqrt((double)ux * ux + (double)uy * uy + (double)uz * uz);
         acc[1] = (double)Tabs;
         if (kind == K_INLET) acc[2] = (double)drho;
-        if (fl & kLayerBit) acc[3] = (double)Tabs;
+        // slot 3 holds the objective's own sum: the heat generated (J = -sum Q)
+        // or the temperature of the layer next to the heated walls
+        if (!P.heatgen && (fl & kLayerBit)) acc[3] = (double)Tabs;
       }
     }
     sfor<L::Q>([&](auto I) { A.fout[(size_t)I * P.Np + n] = fo[I]; });
@@ -1042,7 +1044,7 @@ __global__ __launch_bounds__(kBlock) void k_thermal(ThermArgs A) {
       });
       if constexpr (DIAG) {
         acc[1] = (double)Tabs;
-        if (fl & kLayerBit) acc[3] = (double)Tabs;
+        if (!P.heatgen && (fl & kLayerBit)) acc[3] = (double)Tabs;
       }
     }
     sfor<G::Q>([&](auto I) { A.gout[(size_t)I * P.Np + n] = ko[I]; });
@@ -1066,6 +1068,27 @@ __global__ __launch_bounds__(kBlock) void k_thermal_init(ThermArgs A) {
     const float keq = G::w[i] * ((Tabs - P.T_ref) + 4.0f * Tabs * eu);
     A.gout[(size_t)i * P.Np + n] = (kind >= K_WALL) ? 0.0f : keq;
   });
+}
+
+// Device copy in 16-byte words: each thread loads four words a block width
+// apart (dwordx4 loads, all in flight before the first store), then stores
+// them; consecutive lanes touch consecutive words.  The measured device
+// ceiling that the step kernels' bytes are set against.
+constexpr int kCopyUnroll = 4;
+__global__ __launch_bounds__(kBlock) void k_copy16(const float4* __restrict__ src,
+                                                   float4* __restrict__ dst, size_t n16) {
+  const size_t base = (size_t)blockIdx.x * (kBlock * kCopyUnroll) + threadIdx.x;
+  float4 v[kCopyUnroll];
+#pragma unroll
+  for (int k = 0; k < kCopyUnroll; ++k) {
+    const size_t i = base + (size_t)k * kBlock;
+    if (i < n16) v[k] = src[i];
+  }
+#pragma unroll
+  for (int k = 0; k < kCopyUnroll; ++k) {
+    const size_t i = base + (size_t)k * kBlock;
+    if (i < n16) dst[i] = v[k];
+  }
 }
 
 __global__ void k_fill(float* __restrict__ p, size_t count) {
@@ -1245,6 +1268,15 @@ hipError_t launch_heat_init(float* g, const float* gamma, const uint8_t* flags, 
   const dim3 grid((P.N + kBlock - 1) / kBlock), block(kBlock);
   if (P.q == 9) hipLaunchKernelGGL((k_heat_init<Q5>), grid, block, 0, s, g, gamma, flags, P);
   else hipLaunchKernelGGL((k_heat_init<Q7>), grid, block, 0, s, g, gamma, flags, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy16(const void* src, void* dst, size_t n16, hipStream_t s) {
+  if (n16 == 0) return hipSuccess;
+  const size_t per = (size_t)kBlock * kCopyUnroll;
+  const unsigned blocks = (unsigned)((n16 + per - 1) / per);
+  hipLaunchKernelGGL(k_copy16, dim3(blocks), dim3(kBlock), 0, s, (const float4*)src, (float4*)dst,
+                     n16);
   return hipGetLastError();
 }
 

@@ -12,7 +12,7 @@ from __future__ import annotations
 
 import ctypes
 import os
-from ctypes import POINTER, byref, c_char_p, c_double, c_int, c_int32, c_size_t, c_void_p
+from ctypes import POINTER, byref, c_char_p, c_double, c_int, c_int32, c_size_t, c_uint64, c_void_p
 
 import torch
 
@@ -82,6 +82,7 @@ EXPORTS = ("lbm_problem_create", "lbm_workspace_bytes", "lbm_bind_workspace", "l
            "lbm_thermal_resolve", "lbm_sensitivity", "lbm_forward_resume",
            "lbm_adjoint_resume", "lbm_levelset_update",
            "lbm_copy_state", "lbm_set_kernel_timing", "lbm_kernel_timing", "lbm_stream_probe",
+           "lbm_copy_probe",
            "lbm_lattice",
            "lbm_problem_destroy", "lbm_last_error", "lbm_batch_create", "lbm_batch_table_bytes",
            "lbm_batch_bind_arena", "lbm_batch_set_policy", "lbm_batch_submit", "lbm_batch_step", "lbm_batch_poll",
@@ -133,6 +134,8 @@ def load_library(path: str = LIB_PATH):
     lib.lbm_kernel_timing.restype = c_int
     lib.lbm_stream_probe.argtypes = [P, P, c_int32, POINTER(c_double), P]
     lib.lbm_stream_probe.restype = c_int
+    lib.lbm_copy_probe.argtypes = [P, P, c_uint64, c_int32, POINTER(c_double), P]
+    lib.lbm_copy_probe.restype = c_int
     lib.lbm_lattice.argtypes = [c_int32, P, P]
     lib.lbm_lattice.restype = c_int
     lib.lbm_problem_destroy.argtypes = [P]
@@ -294,6 +297,21 @@ def lbm_stream_probe(p, gamma, launches: int, stream=None) -> float:
     us = c_double(0.0)
     _check(load_library().lbm_stream_probe(p, _ptr(gamma), int(launches), byref(us),
                                            _stream(stream, gamma.device)))
+    return us.value
+
+
+def lbm_copy_probe(src: torch.Tensor, dst: torch.Tensor, launches: int, stream=None) -> float:
+    """Microseconds per launch of the library's streaming copy of src into
+    dst (same size, 16-byte aligned device tensors)."""
+    if not (src.is_cuda and dst.is_cuda and src.is_contiguous() and dst.is_contiguous()):
+        raise ValueError("copy probe buffers must be contiguous device tensors")
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("copy probe buffers differ in size")
+    us = c_double(0.0)
+    _check(load_library().lbm_copy_probe(c_void_p(src.data_ptr()), c_void_p(dst.data_ptr()),
+                                         nbytes, int(launches), byref(us),
+                                         _stream(stream, src.device)))
     return us.value
 
 

@@ -54,6 +54,17 @@ def test_cpu_baseline_fields(bench):
     out = bench.cpu_baseline(w, 12)
     assert out["kind"] == "oracle" and out["unit"] == "MLUPS" and out["value"] > 0
     assert out["cores"] == oracle.threads_used()
-    assert "12 forward + 3 adjoint steps" in out["sample"]
+    assert "12 forward + 12 adjoint steps" in out["sample"]
     if out["cores"] > 1:
         assert out["one_core"]["value"] > 0 and "on 1 thread" in out["one_core"]["sample"]
+
+
+def test_out_of_cache_workload_does_not_fit_the_infinity_cache(bench):
+    """The added out-of-cache configuration streams from HBM; the headline's
+    forward working set fits the 256 MB Infinity Cache, which the line says."""
+    big = bench.out_of_cache_workload()
+    assert (big.nx, big.ny, big.nz) == (320, 160, 80)
+    for k in ("forward", "adjoint"):
+        assert bench.working_set_bytes(k, big) > 3 * bench.MALL_BYTES
+    head = bench.make_workload("heat_sink_Re200")
+    assert bench.working_set_bytes("forward", head) < bench.MALL_BYTES

@@ -95,6 +95,21 @@ def test_autograd_vs_oracle_gradient_and_fd():
     assert e_fd < 1e-4
 
 
+def test_autograd_refuses_an_unconverged_forward():
+    """A forward sweep stopped at its step cap is no steady state: the
+    autograd form raises (or, with strict=False, warns and goes on)."""
+    w = reduced_case().replace(max_steps=300, tol=1e-7, check_every=100)
+    prob = lbm.Problem(w, device="cuda:0")
+    gamma = torch.tensor(w.gamma, dtype=torch.float32, device="cuda:0", requires_grad=True)
+    with pytest.raises(lbm.LBMError) as e:
+        autograd.objective(gamma, prob)
+    assert e.value.code == lbm.LBM_NOT_CONVERGED
+    with pytest.warns(RuntimeWarning):
+        J = autograd.objective(gamma, prob, strict=False)
+        J.backward()
+    assert torch.isfinite(gamma.grad).all()
+
+
 def test_autograd_full_size_matches_direct_path():
     w = W.differentiable_case()
     print(f"[autograd] full {w.nx}x{w.ny}x{w.nz} tau {w.tau}", flush=True)
@@ -107,5 +122,6 @@ def test_autograd_full_size_matches_direct_path():
     e = rel(grad[design], dJ[design])
     print(f"[autograd] full J {float(J):.9g} vs {res['J']:.9g}; grad vs direct path {e:.2e}; "
           f"forward steps {res['forward']['steps']}", flush=True)
+    assert res["forward"]["status"] == lbm.LBM_OK and res["adjoint"]["status"] == lbm.LBM_OK, res
     assert float(J) == res["J"]
     assert e < 1e-4

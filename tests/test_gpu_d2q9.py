@@ -224,7 +224,10 @@ def test_thermal_2d_autograd_matches_direct_path():
     """The differentiable form on the 2D lattice: its backward re-solves the
     D2Q5 lattice from (gamma, u, T) and gives the direct path's gradient."""
     from paper_2501_02161_amd import autograd
-    w = small_heat_sink_2d().replace(max_steps=60000, tol=1e-8, check_every=500)
+    # the FP32 mean |u| of this nearly still flow jitters at a few 1e-8
+    # between checks, so the criterion is 1e-7 (the autograd form raises if
+    # a sweep stops at its cap)
+    w = small_heat_sink_2d().replace(max_steps=60000, tol=1e-7, check_every=500)
     prob = lbm.Problem(w, device="cuda:0")
     gamma = torch.tensor(w.gamma, dtype=torch.float32, device="cuda:0", requires_grad=True)
     J = autograd.objective(gamma, prob)

@@ -19,7 +19,8 @@ import torch
 
 import oracle
 import workloads as W
-from _parity import (compare_solution, gpu_fields, gpu_pops, kinds, rel, run_gpu, run_oracle)
+from _parity import (check_pointwise, compare_solution, fmt_pointwise, gpu_fields, gpu_pops,
+                     kinds, pointwise, rel, run_gpu, run_oracle)
 from paper_2501_02161_amd import lbm
 
 pytestmark = pytest.mark.gpu
@@ -176,8 +177,15 @@ def _unshift(o, h, lattice, ref_value):
     return h + wt[None, :] * ref_value
 
 
-def _step_check(w, fwd_steps=200, adj_steps=200):
+def _step_check(w, fwd_steps=200, adj_steps=200, tol_point=1e-5, tol_grad_point=1e-4):
+    """One forward step, one adjoint step and the sensitivity contraction at
+    the benchmark's launch configuration, each from the GPU's own state,
+    against the oracle's FP64 step: norm-wise errors (returned) and the
+    pointwise report (printed and asserted: every node within tol_point of
+    its field's scale, every design node within tol_grad_point of
+    max |dJ/dgamma|)."""
     prob = lbm.Problem(w.replace(max_steps=fwd_steps, tol=0.0, check_every=100), device="cuda:0")
+    got, want = {}, {}
     o = oracle.Oracle(w)
     k = kinds(w)
     live = k < W.WALL
@@ -193,21 +201,27 @@ def _step_check(w, fwd_steps=200, adj_steps=200):
     rho, u, T = o.macro(f1, g1)
     drho_g, u_g, T_g, _ = gpu_fields(prob)
     err = {"step_p": rel(drho_g[live], rho[live] - w.rho0), "step_u": rel(u_g[live], u[live])}
+    got.update(step_p=drho_g, step_u=u_g)
+    want.update(step_p=rho - w.rho0, step_u=u)
     if w.thermal:
         err["step_T"] = rel(T_g[live], T[live])
+        got["step_T"], want["step_T"] = T_g - w.T_in, T - w.T_in
     fC2, gC2 = o.collide(f1, g1)
     _, wf = o.lattice(0)
     hC_g = gpu_pops(prob, lbm.STATE_FLOW, o)
     err["step_fC"] = rel(hC_g[live], (fC2 - wf[None, :] * w.rho0)[live])
+    got["step_fC"], want["step_fC"] = hC_g, fC2 - wf[None, :] * w.rho0
     if w.thermal:
         _, wg = o.lattice(1)
         kC_g = gpu_pops(prob, lbm.STATE_THERMAL, o)
         err["step_gC"] = rel(kC_g[live], (gC2 - wg[None, :] * w.T_in)[live])
+        got["step_gC"], want["step_gC"] = kC_g, gC2 - wg[None, :] * w.T_in
         # non-equilibrium thermal populations of the last step
         e7, _ = o.lattice(1)
         geq = wg[None, :] * T_g[:, None] * (1.0 + 4.0 * (u_g @ e7.T.astype(float)))
         gneq_g = gpu_pops(prob, lbm.STATE_GNEQ, o)
         err["gneq"] = rel(gneq_g[live], (g1 - geq)[live])
+        got["gneq"], want["gneq"] = gneq_g, g1 - geq
     # ---- adjoint about the GPU's own (u, T): state f_eq-like with those moments
     prob.adjoint(w.gamma)
     fs = gpu_pops(prob, lbm.STATE_ADJ_FLOW, o)
@@ -226,9 +240,13 @@ def _step_check(w, fwd_steps=200, adj_steps=200):
     fsS, gsS = o.adjoint_stream(fs, gs)
     fsC, gsC = o.adjoint_collide(f_state, g_state, fsS, gsS, jf, jg)
     fs1, gs1 = o.adjoint_bc(fsC, gsC)
-    err["adj_step_f"] = rel(gpu_pops(prob, lbm.STATE_ADJ_FLOW, o)[live], fs1[live])
+    a_g = gpu_pops(prob, lbm.STATE_ADJ_FLOW, o)
+    err["adj_step_f"] = rel(a_g[live], fs1[live])
+    got["adj_step_f"], want["adj_step_f"] = a_g, fs1
     if w.thermal:
-        err["adj_step_g"] = rel(gpu_pops(prob, lbm.STATE_ADJ_THERMAL, o)[live], gs1[live])
+        b_g = gpu_pops(prob, lbm.STATE_ADJ_THERMAL, o)
+        err["adj_step_g"] = rel(b_g[live], gs1[live])
+        got["adj_step_g"], want["adj_step_g"] = b_g, gs1
     # ---- sensitivity from the GPU's final adjoint state
     J = prob.sensitivity()
     torch.cuda.synchronize()
@@ -239,6 +257,10 @@ def _step_check(w, fwd_steps=200, adj_steps=200):
     _, _, _, dJ_g = gpu_fields(prob)
     err["sens"] = rel(dJ_g[design], dJ_ref[design])
     assert np.all(dJ_g[~design] == 0.0)
+    got["dJ"], want["dJ"] = dJ_g, dJ_ref
+    pw = pointwise(w, got, want, live, design)
+    print(f"[pointwise] {w.name} one step: {fmt_pointwise(pw)}", flush=True)
+    check_pointwise(pw, tol_point, tol_grad_point)
     return err, J
 
 

@@ -33,6 +33,12 @@ VARIANTS = {
     "heated_walls": dict(thermal=True, objective=W.OBJ_HEATSINK, heated=True),
     "2d_heated_walls": dict(nz=1, nx=16, ny=14, thermal=True, objective=W.OBJ_HEATSINK,
                             heated=True),
+    # heat generation beside heated walls: J = -sum Q must not pick up the
+    # temperature of the layer next to the heated walls
+    "heat_generation_heated_walls": dict(thermal=True, objective=W.OBJ_HEATGEN, beta_max=2e-3,
+                                         heated=True),
+    "2d_heat_generation_heated_walls": dict(nz=1, nx=16, ny=14, thermal=True,
+                                            objective=W.OBJ_HEATGEN, beta_max=2e-3, heated=True),
 }
 
 

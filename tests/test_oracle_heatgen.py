@@ -119,3 +119,26 @@ def test_half_domain_equals_unfolded_full_domain_2d():
     dh, df = _quarter(h["dJ"], w), _fold(full["dJ"], w, wf)
     assert np.max(np.abs(dh - df)) <= 1e-9 * np.max(np.abs(dh))
     assert np.max(np.abs(dh)) > 0
+
+
+@pytest.mark.parametrize("nz", [12, 1], ids=["3d", "2d"])
+def test_heat_generation_objective_with_heated_walls(nz):
+    """J = -sum over design nodes of beta_max (1 - gamma) (1 - T) (Eqs. 69,
+    72) also where heated walls sit beside the design domain: the objective
+    is the generated heat alone, recomputed here from the oracle's own
+    temperature field; the heated walls change T, not what J sums."""
+    kw = dict(nz=1, nx=16, ny=14) if nz == 1 else {}
+    w = W.six_port_box(thermal=True, objective=W.OBJ_HEATGEN, beta_max=2e-3, heated=True, **kw)
+    o = oracle.Oracle(w)
+    r = o.forward(max_steps=400, tol=0.0, check_every=100)
+    rho, u, T = o.macro(r["f"], r["g"])
+    k = (w.mask & 7).reshape(-1)
+    design = k == W.DESIGN
+    gam = w.gamma.reshape(-1)
+    J = -np.sum(w.beta_max * (1.0 - gam[design]) * (1.0 - T[design]))
+    assert np.isclose(o.objective(r["f"], r["g"]), J, rtol=1e-13, atol=0)
+    # the heated walls do heat the domain (the case is not degenerate)
+    w0 = w.replace(q_w=0.0)
+    o0 = oracle.Oracle(w0)
+    r0 = o0.forward(max_steps=400, tol=0.0, check_every=100)
+    assert abs(o0.objective(r0["f"], r0["g"]) - J) > 1e-6 * abs(J)

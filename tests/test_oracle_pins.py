@@ -334,3 +334,68 @@ def test_conduction_linear_profile():
     for y in range(1, w.ny - 1):
         for x in range(1, w.nx - 1):
             assert np.allclose(T[1:, y, x], expect, rtol=1e-10, atol=0)
+
+
+def ramp_conductivity(gamma, ratio, q):
+    """RAMP interpolation of the conductivity between solid (gamma = 0,
+    conductivity `ratio` in units of the fluid's) and fluid (gamma = 1, 1):
+    k = ratio + (1 - ratio) gamma / (1 + q (1 - gamma))."""
+    return ratio + (1.0 - ratio) * gamma / (1.0 + q * (1.0 - gamma))
+
+
+def layered_conduction_profile(w, D_layer, D_top):
+    """Exact steady D3Q7 (or D2Q5) temperature of a column conducting a flux
+    q_w per step from the heated floor to a Dirichlet top node, for layer
+    diffusivities D_layer[z-1] (z = 1 .. nz-2) and D_top at the top node.
+
+    Derivation (no flow, no dependence on x and y): the in-plane and rest
+    populations are then at equilibrium, so the two populations along z
+    carry T/4 between them.  The net upward count through every link is the
+    same constant F = q_w (the floor injects it, nothing else adds heat);
+    collision at a node of relaxation time tau keeps the up/down sum and
+    scales their difference, which gives F = (1 - 1/(2 tau)) (U - D) for the
+    pre-collision pair (U, D).  Summing the two half-links, the temperature
+    drop across the link (z, z+1) is 2 F [1/(tau_z - 1/2) + 1/(tau_{z+1} -
+    1/2)] = (F / 2) (1/D_z + 1/D_{z+1}) with tau - 1/2 = D / cs2, cs2 = 1/4:
+    each link conducts with the harmonic mean of its two nodes'
+    diffusivities."""
+    D = np.concatenate([np.asarray(D_layer, dtype=np.float64), [D_top]])
+    n = len(D)
+    T = np.zeros(n)
+    T[-1] = w.T_in
+    for i in range(n - 2, -1, -1):
+        T[i] = T[i + 1] + 0.5 * w.q_w * (1.0 / D[i] + 1.0 / D[i + 1])
+    return T   # T at z = 1 .. nz-1
+
+
+LAYER_GAMMAS = [0.0, 0.0, 0.25, 0.25, 0.5, 1.0, 1.0, 0.75, 0.1, 0.0]
+
+
+def test_conduction_through_design_layers_pins_ramp():
+    """Design-dependent conductivity (RAMP, ratio 100, q = 1) through the
+    exact layered conduction profile: a solid slab (gamma = 0) under partly
+    and fully fluid layers.  Fixes k(0) = ratio, k(1) = 1, the RAMP values at
+    gamma = 0.25, 0.5, 0.75 and 0.1 (q (1 - gamma) and q gamma differ at
+    gamma != 0.5), tau_g = 1/2 + D k / cs2 and the harmonic-mean flux across
+    every change of conductivity."""
+    w = W.conduction_layers(5, 5, LAYER_GAMMAS, tau=0.8, Pr=1.0, q_w=0.002, T_top=0.1)
+    o = oracle.Oracle(w)
+    r = o.forward(max_steps=400000, tol=1e-15, check_every=500)
+    assert r["status"] == 0
+    rho, u, T = o.macro(r["f"], r["g"])
+    assert np.abs(u).max() < 1e-15
+    Df = (w.tau - 0.5) / 3.0 / w.Pr
+    k = ramp_conductivity(np.array(LAYER_GAMMAS), w.k_ratio, w.q_ramp)
+    assert k[0] == w.k_ratio and k[5] == 1.0
+    expect = layered_conduction_profile(w, Df * k, Df)
+    T = T.reshape(w.nz, w.ny, w.nx)
+    for y in range(1, w.ny - 1):
+        for x in range(1, w.nx - 1):
+            assert np.allclose(T[1:, y, x], expect, rtol=1e-10, atol=0)
+    # the readings a slip would give differ by far more than the tolerance
+    g = np.array(LAYER_GAMMAS)
+    wrong_q = w.k_ratio + (1.0 - w.k_ratio) * g / (1.0 + w.q_ramp * g)
+    inverted = ramp_conductivity(1.0 - g, w.k_ratio, w.q_ramp)
+    for kk in (wrong_q, inverted):
+        alt = layered_conduction_profile(w, Df * kk, Df)
+        assert np.abs(alt - expect).max() > 1e-3 * np.abs(expect).max()

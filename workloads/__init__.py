@@ -380,6 +380,27 @@ def conduction_column(nx: int, ny: int, nz: int, tau: float, Pr: float, q_w: flo
                     gamma=np.ones((nz, ny, nx)), Pr=Pr, q_w=q_w, T_in=T_top, w_dp=0.0)
 
 
+def conduction_layers(nx: int, ny: int, gammas, tau: float, Pr: float, q_w: float,
+                      T_top: float, k_ratio: float = 100.0, q_ramp: float = 1.0) -> Workload:
+    """Pure conduction through layers of design nodes: the closed box of
+    `conduction_column` (heated floor z = 0, zero-velocity inlet on the top
+    face as a Dirichlet T_top boundary, adiabatic side walls) whose interior
+    layers z = 1 .. nz-2 are DESIGN nodes, layer z holding the uniform design
+    value gammas[z - 1] (so nz = len(gammas) + 2).  No flow: the design field
+    enters only through the conductivity of each layer."""
+    g = np.asarray(gammas, dtype=np.float64)
+    nz = len(g) + 2
+    m = walled_box(nx, ny, nz, interior=DESIGN)
+    m[0, 1:ny - 1, 1:nx - 1] = code(HEATED, NPZ)
+    m[nz - 1, 1:ny - 1, 1:nx - 1] = code(INLET, NMZ)
+    gamma = np.ones((nz, ny, nx))
+    gamma[1:nz - 1] = g[:, None, None]
+    return Workload(name=f"conduction_layers_{nx}x{ny}x{nz}", dim=3, nx=nx, ny=ny, nz=nz,
+                    thermal=True, tau=tau, Re=0.0, L_ref=1.0, objective=OBJ_HEATSINK, mask=m,
+                    gamma=gamma, Pr=Pr, q_w=q_w, T_in=T_top, w_dp=0.0, k_ratio=k_ratio,
+                    q_ramp=q_ramp)
+
+
 def conduction_column_2d(nx: int, ny: int, tau: float, Pr: float, q_w: float,
                          T_top: float) -> Workload:
     """Pure conduction in 2D (D2Q9 + D2Q5): a heated floor (y = 0, heat flux

@@ -39,13 +39,15 @@ STATUS = {0: "converged", 1: "step cap reached"}
 def bytes_per_node(kernel, w):
     """Algorithmic bytes per node-update of a step kernel for workload w:
     every population read once and written once (4 B each), plus the
-    per-node inputs each kernel reads once (forward: gamma, flags; adjoint:
-    u, T, gamma, flags, and the dissipation source G)."""
+    per-node inputs each kernel reads once (forward: gamma, flags and, with
+    the thermal lattice, the reference temperature its populations are
+    stored against; adjoint: u, T, gamma, flags, and the dissipation source
+    G)."""
     q = 9 if w.nz == 1 else 19          # D2Q9 on a 2D lattice, else D3Q19
     dim = 2 if w.nz == 1 else 3
     qt = (5 if w.nz == 1 else 7) if w.thermal else 0   # D2Q5 / D3Q7
     if kernel == "forward":
-        return (q + qt) * 4 * 2 + 4 + 1
+        return (q + qt) * 4 * 2 + 4 + 1 + (4 if w.thermal else 0)
     b = (q + qt) * 4 * 2 + dim * 4 + (4 if w.thermal else 0) + 4 + 1
     if w.objective == 1:                # dissipation: source G (3 floats)
         b += 12

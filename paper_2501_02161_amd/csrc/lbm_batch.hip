@@ -281,7 +281,9 @@ int bind_slot(lbm_batch* b, Slot& s, const Request& r, hipStream_t st) {
     p->a[k] = (float*)(base + L.a[k]);
     p->g[k] = th ? (float*)(base + L.g[k]) : nullptr;
     p->b[k] = th ? (float*)(base + L.b[k]) : nullptr;
+    p->R[k] = th ? (float*)(base + L.R[k]) : nullptr;
   }
+  p->rcur = 0;
   p->gneq = th ? (float*)(base + L.gneq) : nullptr;
   p->G = (p->d.objective == LBM_OBJ_DISSIPATION) ? (float*)(base + L.G) : nullptr;
   p->uin = (float*)(base + L.uin);
@@ -313,6 +315,7 @@ int bind_slot(lbm_batch* b, Slot& s, const Request& r, hipStream_t st) {
   HIPCHK(launch_fill(p->f[0], (size_t)qf_of(p) * p->Np, st));
   if (th) {
     HIPCHK(launch_fill(p->g[0], (size_t)qg_of(p) * p->Np, st));
+    HIPCHK(launch_ref_init(p->R[0], p->flags, p->kp, st));
     HIPCHK(launch_heat_init(p->g[0], s.gamma, p->flags, p->kp, st));
   }
   HIPCHK(hipStreamSynchronize(st));  // the staging is reused
@@ -392,8 +395,10 @@ int upload_tables(lbm_batch* b, Lane& ln) {
     d.check = p->d.check_every;
     p->fcur = 0;
     p->acur = 0;
+    p->rcur = 0;
     d.fa = fwd_args(p, s.gamma, s.drho, s.u, s.T);
     d.aa = adj_args(p, s.gamma, s.u, s.T);
+    d.R1 = p->R[1];
     for (int t = 0; t < p->nblk; ++t) ln.h_tiles.push_back(Tile{i, t});
     ln.nodes += p->N;
   }
@@ -580,17 +585,24 @@ int launch_solo(lbm_batch* b, int L, int i) {
   const int n = std::min(b->quantum, cap - s0);
   const int last = s0 + n;
   const bool diag = (chk > 0 && last % chk == 0) || last == cap;
+  // reference buffer of the thermal state during this quantum: it flips at
+  // every re-base, which follows a diagnostic step, and those only end quanta
+  const int rpar = chk > 0 ? (s0 / chk) & 1 : 0;
+  const bool rebase = th && diag && s.phase == PH_FORWARD;
   if (p->nblk >= kDirectTiles) {
     // argument sets for even and odd steps, built here, issued by the worker
     const int phase = s.phase, obj = p->d.objective;
     FwdArgs fa[2];
     AdjArgs aa[2];
+    p->rcur = rpar;
     for (int par = 0; par < 2; ++par) {
       p->fcur = par;
       p->acur = par;
       fa[par] = fwd_args(p, s.gamma, s.drho, s.u, s.T);
       aa[par] = adj_args(p, s.gamma, s.u, s.T);
     }
+    p->fcur = last & 1;  // the state after the quantum's last step
+    const RebaseArgs ra = rebase_args(p, s.T);
     const double* part = p->partials;
     const int nblk = p->nblk;
     hipStream_t st = ln.stream;
@@ -607,6 +619,7 @@ int launch_solo(lbm_batch* b, int L, int i) {
         e = phase == PH_FORWARD ? launch_forward(fa[par], th, dq, st)
                                 : launch_adjoint(aa[par], th, obj, dq, st);
       }
+      if (e == hipSuccess && rebase) e = launch_rebase(ra, st);
       if (e == hipSuccess && diag)
         e = launch_finalize(part, nblk, phase == PH_FORWARD ? kRedFwd : kRedAdj, ds, st);
       if (e == hipSuccess) e = launch_advance(base, Q, st);
@@ -622,7 +635,7 @@ int launch_solo(lbm_batch* b, int L, int i) {
     ln.busy = true;
     return LBM_OK;
   }
-  const auto key = std::make_tuple(s.ticket, s.phase, s0 & 1, int(diag));
+  const auto key = std::make_tuple(s.ticket, s.phase, s0 & 1, int(diag) | (rpar << 1));
   auto it = ln.solo.find(key);
   if (it == ln.solo.end()) {
     if (ln.solo.size() >= 8) {
@@ -636,11 +649,17 @@ int launch_solo(lbm_batch* b, int L, int i) {
         const bool dq = diag && q == n - 1;
         if (phase == PH_FORWARD) {
           p->fcur = (s0 + q) & 1;
+          p->rcur = rpar;
           e = launch_forward(fwd_args(p, s.gamma, s.drho, s.u, s.T), th, dq, ln.stream);
         } else {
           p->acur = (s0 + q) & 1;
           e = launch_adjoint(adj_args(p, s.gamma, s.u, s.T), th, p->d.objective, dq, ln.stream);
         }
+      }
+      if (e == hipSuccess && rebase) {
+        p->fcur = last & 1;
+        p->rcur = rpar;
+        e = launch_rebase(rebase_args(p, s.T), ln.stream);
       }
       if (e == hipSuccess && diag)
         e = launch_finalize(p->partials, p->nblk, phase == PH_FORWARD ? kRedFwd : kRedAdj,
@@ -704,6 +723,10 @@ int launch_quantum(lbm_batch* b, int L) {
         for (int q = 0; q < b->quantum && e == hipSuccess; ++q)
           e = launch_batch(ln.d_tiles, ntiles, ln.d_slots, ln.d_base, q, b->thermal != 0,
                            b->objective, ln.stream);
+        // diagnostic steps end quanta: re-base the thermal states they left
+        if (e == hipSuccess && b->thermal)
+          e = launch_batch_rebase(ln.d_tiles, ntiles, ln.d_slots, ln.d_base, b->quantum - 1,
+                                  ln.stream);
         if (e == hipSuccess) e = launch_finalize_slots(ln.d_slots, b->max_slots, ln.d_sums, ln.stream);
         if (e == hipSuccess) e = launch_advance(ln.d_base, b->quantum, ln.stream);
         return e;
@@ -730,6 +753,7 @@ int launch_quantum(lbm_batch* b, int L) {
     } else {
       for (int q = 0; q < Q && e == hipSuccess; ++q)
         e = launch_batch(tiles, ntiles, sl, base, q, th, obj, st);
+      if (e == hipSuccess && th) e = launch_batch_rebase(tiles, ntiles, sl, base, Q - 1, st);
       if (e == hipSuccess) e = launch_finalize_slots(sl, ns, ds, st);
       if (e == hipSuccess) e = launch_advance(base, Q, st);
     }

@@ -46,6 +46,7 @@ Layout layout_of(const lbm_problem* p) {
   for (int k = 0; k < 2; ++k) L.g[k] = th ? take(pg) : 0;
   for (int k = 0; k < 2; ++k) L.a[k] = take(pf);
   for (int k = 0; k < 2; ++k) L.b[k] = th ? take(pg) : 0;
+  for (int k = 0; k < 2; ++k) L.R[k] = th ? take((size_t)p->Np * sizeof(float)) : 0;
   L.gneq = th ? take(pg) : 0;
   L.G = (p->d.objective == LBM_OBJ_DISSIPATION) ? take((size_t)3 * p->Np * sizeof(float)) : 0;
   L.uin = take((size_t)p->Np * sizeof(float));
@@ -231,8 +232,7 @@ int validate_and_setup(lbm_problem* p, const lbm_desc_t& d, const uint8_t* mask)
   k.kr = (float)d.k_ratio;
   k.qr = (float)d.q_ramp;
   k.q_w = (float)d.q_w;
-  k.T_ref = (float)d.T_in;
-  k.dT_in = 0.0f;
+  k.T_in = (float)d.T_in;
   k.c_in = p->n_inlet > 0 ? (float)(d.w_dp / (3.0 * p->n_inlet)) : 0.0f;
   k.c_layer = p->n_layer > 0 ? (float)(1.0 / p->n_layer) : 0.0f;
   k.two_nu = (float)(2.0 * nu);
@@ -286,6 +286,7 @@ FwdArgs fwd_args(lbm_problem* p, const float* gamma, float* drho, float* u, floa
   A.fout = p->f[1 - p->fcur];
   A.gin = p->g[p->fcur];
   A.gout = p->g[1 - p->fcur];
+  A.Rin = p->R[p->rcur];
   A.flags = p->flags;
   A.gamma = gamma;
   A.uin = p->uin;
@@ -336,6 +337,11 @@ int run_forward(lbm_problem* p, const float* gamma, float* drho, float* u, float
     HIPCHK(launch_forward(fwd_args(p, gamma, drho, u, T), th, diag, s));
     p->fcur = 1 - p->fcur;
     if (!diag) continue;
+    if (th) {
+      // move the thermal state's reference onto this step's temperature
+      HIPCHK(launch_rebase(rebase_args(p, T), s));
+      p->rcur = 1 - p->rcur;
+    }
     int rc = read_sums(p, kRedFwd, s);
     if (rc) return rc;
     mon[0] = p->pinned[0] / p->n_nonwall;
@@ -381,6 +387,17 @@ int run_forward(lbm_problem* p, const float* gamma, float* drho, float* u, float
     info->J = J;
   }
   return status;
+}
+
+RebaseArgs rebase_args(lbm_problem* p, const float* T) {
+  RebaseArgs A{};
+  A.g = p->g[p->fcur];
+  A.Rin = p->R[p->rcur];
+  A.Rout = p->R[1 - p->rcur];
+  A.T = T;
+  A.flags = p->flags;
+  A.P = p->kp;
+  return A;
 }
 
 AdjArgs adj_args(lbm_problem* p, const float* gamma, const float* u, const float* T) {
@@ -463,8 +480,10 @@ int run_thermal(lbm_problem* p, const float* gamma, const float* u, const float*
   A.partials = p->partials;
   A.P = p->kp;
   A.gout = p->g[0];
+  A.R = p->R[0];  // the given temperature is the reference throughout the re-solve
   HIPCHK(launch_thermal_init(A, s));
   p->fcur = 0;
+  p->rcur = 0;
   double prev = 0, res = 0, mon = 0;
   bool have_prev = false;
   int status = LBM_NOT_CONVERGED, k = 0;
@@ -577,7 +596,9 @@ int lbm_bind_workspace(lbm_problem_t* p, void* device_ptr, size_t bytes) {
     p->a[k] = (float*)(base + L.a[k]);
     p->g[k] = th ? (float*)(base + L.g[k]) : nullptr;
     p->b[k] = th ? (float*)(base + L.b[k]) : nullptr;
+    p->R[k] = th ? (float*)(base + L.R[k]) : nullptr;
   }
+  p->rcur = 0;
   p->gneq = th ? (float*)(base + L.gneq) : nullptr;
   p->G = (p->d.objective == LBM_OBJ_DISSIPATION) ? (float*)(base + L.G) : nullptr;
   p->uin = (float*)(base + L.uin);
@@ -605,9 +626,11 @@ int lbm_forward_solve(lbm_problem_t* p, const float* gamma, float* drho, float* 
   hipStream_t s = (hipStream_t)stream;
   p->fwd_done = p->adj_done = p->have_gneq = false;
   p->fcur = 0;
+  p->rcur = 0;
   HIPCHK(launch_fill(p->f[0], (size_t)qf_of(p) * p->Np, s));
   if (thermal_of(p)) {
     HIPCHK(launch_fill(p->g[0], (size_t)qg_of(p) * p->Np, s));
+    HIPCHK(launch_ref_init(p->R[0], p->flags, p->kp, s));
     HIPCHK(launch_heat_init(p->g[0], gamma, p->flags, p->kp, s));
   }
   return run_forward(p, gamma, drho, u, T, p->d.max_steps, p->d.check_every, p->d.tol, s, info);
@@ -803,6 +826,9 @@ int lbm_copy_state(const lbm_problem_t* p, int32_t which, float* dst, void* stre
   for (int i = 0; i < q; ++i)
     HIPCHK(hipMemcpyAsync(dst + (size_t)i * p->N, src + (size_t)i * p->Np, (size_t)p->N * sizeof(float),
                           hipMemcpyDeviceToDevice, s));
+  // the forward thermal state is kept relative to a per-node reference;
+  // export it in the shift of T_in
+  if (which == 1) HIPCHK(launch_export_thermal(src, p->R[p->rcur], p->flags, dst, p->kp, s));
   return LBM_OK;
 }
 

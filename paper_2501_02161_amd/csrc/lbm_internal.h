@@ -39,8 +39,7 @@ struct KParams {
   float dfc;                     // (nu/Pr)/cs2 of D3Q7: tau_g = 1/2 + dfc k(g)
   float kr, qr;                  // conductivity ratio and RAMP parameter
   float q_w;                     // heat flux per heated wall node and step
-  float T_ref;                   // thermal shift (= T_in)
-  float dT_in;                   // T_in - T_ref
+  float T_in;                    // inlet (Dirichlet) temperature
   float c_in;                    // w_dp / (3 N_inlet): dJ/df_i at inlet nodes
   float c_layer;                 // 1 / N_layer: dJ/dg_i at objective-layer nodes
   float two_nu;                  // 2 nu (dissipation source)
@@ -54,11 +53,21 @@ struct KParams {
   int q;                         // flow lattice: 19 (D3Q19) or 9 (D2Q9, nz = 1)
 };
 
+// Thermal populations are stored relative to a per-node reference
+// temperature R: the slot of population i at node x holds g_i - w_i R(x), and
+// a pull from node y adds w_i (R(y) - R(x)).  Wall nodes hold R = +inf and
+// carry the values they bounce back in the shift of the node that reads them
+// (no term is added across a wall).  R is re-based onto the current
+// temperature at every residual check of a forward sweep (k_rebase), which
+// keeps the stored values at the size of their deviations from the local
+// temperature, so their FP32 rounding does not stall the slow approach to the
+// steady state.
 struct FwdArgs {
   const float* fin;
   float* fout;
   const float* gin;
   float* gout;
+  const float* Rin;     // reference temperature per node (thermal), read only in a step
   const uint8_t* flags;
   const float* gamma;
   const float* uin;     // prescribed normal inlet speed per node
@@ -102,12 +111,24 @@ struct SensArgs {
 struct ThermArgs {
   const float* gin;
   float* gout;
+  float* R;             // reference temperature per node (the given T; +inf at walls)
   const uint8_t* flags;
   const float* gamma;
   const float* u;       // [3][N] frozen velocity
   const float* T;       // [N] initial temperature (init kernel only)
   float* gneq;          // 7 (2D: 5) x Np (diagnostic step)
   double* partials;
+  KParams P;
+};
+
+// Re-base of a forward thermal state (in place on g) from the reference Rin
+// onto the temperature field T, writing the new reference to Rout.
+struct RebaseArgs {
+  float* g;
+  const float* Rin;
+  float* Rout;
+  const float* T;
+  const uint8_t* flags;
   KParams P;
 };
 
@@ -122,8 +143,9 @@ struct SlotDev {
   int start;        // launch index of the phase's first step
   int max_steps;
   int check;        // residual check period (0: only the last step)
-  FwdArgs fa;       // fin/gin = buffer 0, fout/gout = buffer 1
+  FwdArgs fa;       // fin/gin = buffer 0, fout/gout = buffer 1, Rin = reference buffer 0
   AdjArgs aa;       // ain/bin = buffer 0, aout/bout = buffer 1
+  float* R1;        // reference buffer 1 (the forward re-bases at every diagnostic step)
 };
 struct Tile {
   int slot;
@@ -152,6 +174,18 @@ hipError_t launch_levelset_update(const float* phi, float* phi_out, const float*
 // (no-op without heat generation).
 hipError_t launch_heat_init(float* g, const float* gamma, const uint8_t* flags, const KParams& P,
                             hipStream_t s);
+// Reference temperature of a forward start: T_in at non-wall nodes, +inf at walls.
+hipError_t launch_ref_init(float* R, const uint8_t* flags, const KParams& P, hipStream_t s);
+// Re-base of a forward thermal state (see RebaseArgs).
+hipError_t launch_rebase(const RebaseArgs& a, hipStream_t s);
+// Thermal state in the shift of T_in (g_i - w_i T_in, node-major planes of N
+// floats) from the stored per-node-reference form (src planes of Np floats).
+hipError_t launch_export_thermal(const float* src, const float* R, const uint8_t* flags, float* dst,
+                                 const KParams& P, hipStream_t s);
+// Batch form of the re-base: every slot whose step `*base + q - start` was a
+// diagnostic forward step re-bases its tiles.
+hipError_t launch_batch_rebase(const Tile* tiles, int ntiles, const SlotDev* slots, const int* base,
+                               int q, hipStream_t s);
 // Step kernels; with non-null events the launch records them at the start and
 // end of the kernel itself (hipExtLaunchKernelGGL), for per-launch timing.
 hipError_t launch_forward(const FwdArgs& a, bool thermal, bool diag, hipStream_t s,
@@ -229,6 +263,8 @@ struct lbm_problem {
   float* g[2] = {nullptr, nullptr};
   float* a[2] = {nullptr, nullptr};
   float* b[2] = {nullptr, nullptr};
+  float* R[2] = {nullptr, nullptr};  // reference temperature of the thermal state (rcur current)
+  int rcur = 0;
   float* gneq = nullptr;
   float* G = nullptr;
   float* uin = nullptr;
@@ -252,7 +288,7 @@ namespace lbmadj {
 
 // Workspace regions of a problem (byte offsets, 256-byte aligned).
 struct Layout {
-  size_t f[2], g[2], a[2], b[2], gneq, G, uin, flags, partials, sums, total;
+  size_t f[2], g[2], a[2], b[2], R[2], gneq, G, uin, flags, partials, sums, total;
 };
 Layout layout_of(const lbm_problem* p);
 bool thermal_of(const lbm_problem* p);
@@ -262,6 +298,7 @@ int sens_buffer(const lbm_problem* p);  // adjoint buffer the sensitivity contra
 int validate_and_setup(lbm_problem* p, const lbm_desc_t& d, const uint8_t* mask);
 FwdArgs fwd_args(lbm_problem* p, const float* gamma, float* drho, float* u, float* T);
 AdjArgs adj_args(lbm_problem* p, const float* gamma, const float* u, const float* T);
+RebaseArgs rebase_args(lbm_problem* p, const float* T);  // re-base of g[fcur] from R[rcur]
 bool rel_converged(double now, double before, double tol);
 
 }  // namespace lbmadj

@@ -197,11 +197,20 @@ __device__ __forceinline__ Mirror mirror_of(int x, int y, int z, const KParams& 
 // reflection at the plane midway between the two layers; the quarter-domain
 // heat sink).  Forward pulls use (-e_I), adjoint pulls (+e_I); in both the
 // reflected slot is the transpose of the other's.
+// Where population I of node n is pulled from: the neighbour n + (DX, DY, DZ)
+// and slot I, or for a neighbour beyond a mirror plane the node's own layer
+// along that axis and the reflected slot; `valid` is false beyond a
+// non-periodic face (then node = n, and the pulled value is 0).
+struct Src {
+  int slot;
+  int node;
+  bool valid;
+};
 template <class L, int I, int DX, int DY, int DZ>
-__device__ __forceinline__ float load_pull(const float* __restrict__ base, size_t Np, const Nbr& b,
-                                           int n, const Mirror& m) {
+__device__ __forceinline__ Src pull_src(const Nbr& b, int n, const Mirror& m) {
   if constexpr (DX != 1 && DY != 1 && DZ != 1) {
-    return load_nbr<DX, DY, DZ>(base + (size_t)I * Np, b, n);
+    const bool v = b.vx[DX + 1] && b.vy[DY + 1] && b.vz[DZ + 1];
+    return Src{I, v ? b.X[DX + 1] + b.Yo[DY + 1] + b.Zo[DZ + 1] : n, v};
   } else {
     const bool rx = (DX == 1) && m.x, ry = (DY == 1) && m.y, rz = (DZ == 1) && m.z;
     constexpr int I1 = mirror_dir<L, I, 1>(), I2 = mirror_dir<L, I, 2>(), I3 = mirror_dir<L, I, 3>();
@@ -212,9 +221,37 @@ __device__ __forceinline__ float load_pull(const float* __restrict__ base, size_
     const int Yo = ry ? b.Yo[1] : b.Yo[DY + 1];
     const int Zo = rz ? b.Zo[1] : b.Zo[DZ + 1];
     const bool v = (rx || b.vx[DX + 1]) && (ry || b.vy[DY + 1]) && (rz || b.vz[DZ + 1]);
-    const int s = v ? X + Yo + Zo : n;
-    const float r = base[(size_t)p * Np + s];
-    return v ? r : 0.0f;
+    return Src{p, v ? X + Yo + Zo : n, v};
+  }
+}
+
+template <class L, int I, int DX, int DY, int DZ>
+__device__ __forceinline__ float load_pull(const float* __restrict__ base, size_t Np, const Nbr& b,
+                                           int n, const Mirror& m) {
+  const Src sr = pull_src<L, I, DX, DY, DZ>(b, n, m);
+  const float r = base[(size_t)sr.slot * Np + sr.node];
+  return sr.valid ? r : 0.0f;
+}
+
+// A reference temperature of +inf marks a wall node.
+__device__ __forceinline__ bool ref_is_node(float R) { return R <= 3.0e38f; }
+
+// Forward thermal pull in the per-node reference form: the value of slot I
+// pulled from its source node, moved into node n's shift by
+// w_I (R(source) - R(n)) unless the source or node n is a wall (walls hold
+// their values in the shift of the node that reads them).
+template <class G, int I, int DX, int DY, int DZ>
+__device__ __forceinline__ float load_pull_ref(const float* __restrict__ base,
+                                               const float* __restrict__ R, size_t Np, const Nbr& b,
+                                               int n, const Mirror& m, float Rn, bool wall_here) {
+  if constexpr (DX == 0 && DY == 0 && DZ == 0) {
+    return base[(size_t)I * Np + n];
+  } else {
+    const Src sr = pull_src<G, I, DX, DY, DZ>(b, n, m);
+    const float r = base[(size_t)sr.slot * Np + sr.node];
+    const float Rs = R[sr.node];
+    const bool shift = sr.valid && !wall_here && ref_is_node(Rs);
+    return sr.valid ? (shift ? r + G::w[I] * (Rs - Rn) : r) : 0.0f;
   }
 }
 
@@ -408,10 +445,14 @@ __device__ __forceinline__ void forward_tile(const FwdArgs& A, int blk) {
       h[i] = load_pull<L, i, -L::ex[i], -L::ey[i], -L::ez[i]>(A.fin, P.Np, nb, n, mr);
     });
     float k[G::Q];
+    float Rn = 0.0f;  // the node's reference temperature (thermal shift)
     if constexpr (THERMAL) {
+      Rn = A.Rin[n];
+      const bool wall_here = kind >= K_WALL;
       sfor<G::Q>([&](auto I) {
         constexpr int i = I;
-        k[i] = load_pull<G, i, -G::ex[i], -G::ey[i], -G::ez[i]>(A.gin, P.Np, nb, n, mr);
+        k[i] = load_pull_ref<G, i, -G::ex[i], -G::ey[i], -G::ez[i]>(A.gin, A.Rin, P.Np, nb, n, mr,
+                                                                     Rn, wall_here);
       });
       // zero-gradient outflow: the population along the inward normal takes
       // the node's own post-collision value
@@ -467,7 +508,7 @@ __device__ __forceinline__ void forward_tile(const FwdArgs& A, int blk) {
           const int d = nc + 1;
           float s = 0.f;
           sfor<G::Q>([&](auto J) { s += (J == d) ? 0.0f : k[J]; });
-          sfor<G::Q>([&](auto J) { k[J] = (J == d) ? P.dT_in - s : k[J]; });
+          sfor<G::Q>([&](auto J) { k[J] = (J == d) ? (P.T_in - Rn) - s : k[J]; });
         }
       }
       // moments of the post-boundary state (Eq. 6)
@@ -497,7 +538,7 @@ __device__ __forceinline__ void forward_tile(const FwdArgs& A, int blk) {
       if constexpr (THERMAL) {
         float dT = 0.f;
         sfor<G::Q>([&](auto I) { dT += k[I]; });
-        Tabs = P.T_ref + dT;
+        Tabs = Rn + dT;
         const float tg = 0.5f + P.dfc * ((kind == K_DESIGN) ? khat_of(gam, P) : 1.0f);
         const float og = 1.0f / tg;
         // heat generation Q = beta_max (1 - gamma) (1 - T) in the design domain
@@ -534,7 +575,7 @@ __device__ __forceinline__ void forward_tile(const FwdArgs& A, int blk) {
 }
 
 template <class L, bool MIR, bool THERMAL, bool DIAG, bool EARLY = false>
-__global__ __launch_bounds__(kBlock) void k_forward(FwdArgs A) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_forward(FwdArgs A) {
   forward_tile<L, MIR, THERMAL, DIAG, EARLY>(A, remap_block(blockIdx.x, A.P));
 }
 
@@ -934,6 +975,9 @@ __device__ __forceinline__ void batch_tile(const SlotDev& S, int blk, int k, boo
       A.gin = S.fa.gout;
       A.gout = const_cast<float*>(S.fa.gin);
     }
+    // the reference buffers alternate at every re-base (after each
+    // diagnostic step of the sweep)
+    if (THERMAL && S.check > 0 && ((k / S.check) & 1)) A.Rin = S.R1;
     if (diag) forward_tile<L, MIR, THERMAL, true>(A, blk);
     else forward_tile<L, MIR, THERMAL, false>(A, blk);
   } else {
@@ -962,7 +1006,7 @@ __device__ __forceinline__ void batch_tile(const SlotDev& S, int blk, int k, boo
 // alone.  An engine takes 3D and 2D requests side by side (the lattice is
 // uniform over a block: a tile belongs to one slot).
 template <bool THERMAL, int OBJ>
-__global__ __launch_bounds__(kBlock) void k_batch(const Tile* __restrict__ tiles,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_batch(const Tile* __restrict__ tiles,
                                                   const SlotDev* __restrict__ slots,
                                                   const int* __restrict__ base, int q, int xper,
                                                   int xrem) {
@@ -1007,9 +1051,11 @@ __global__ __launch_bounds__(kBlock) void k_thermal(ThermArgs A) {
     const unsigned fl = A.flags[n];
     const int kind = fl & 7, nc = (fl >> 3) & 7;
     float k[G::Q];
+    const float Rn = A.R[n];
     sfor<G::Q>([&](auto I) {
       constexpr int i = I;
-      k[i] = load_pull<G, i, -G::ex[i], -G::ey[i], -G::ez[i]>(A.gin, P.Np, nb, n, mr);
+      k[i] = load_pull_ref<G, i, -G::ex[i], -G::ey[i], -G::ez[i]>(A.gin, A.R, P.Np, nb, n, mr, Rn,
+                                                                   kind >= K_WALL);
     });
     const int d = nc + 1;
     if (kind == K_OUTLET) {
@@ -1025,12 +1071,12 @@ __global__ __launch_bounds__(kBlock) void k_thermal(ThermArgs A) {
       if (kind == K_INLET) {
         float s = 0.f;
         sfor<G::Q>([&](auto J) { s += (J == d) ? 0.0f : k[J]; });
-        sfor<G::Q>([&](auto J) { k[J] = (J == d) ? P.dT_in - s : k[J]; });
+        sfor<G::Q>([&](auto J) { k[J] = (J == d) ? (P.T_in - Rn) - s : k[J]; });
       }
       const float ux = A.u[n], uy = A.u[P.N + n], uz = A.u[2 * P.N + n];
       float dT = 0.f;
       sfor<G::Q>([&](auto I) { dT += k[I]; });
-      const float Tabs = P.T_ref + dT;
+      const float Tabs = Rn + dT;
       const float gm = (kind == K_DESIGN) ? A.gamma[n] : 1.0f;
       const float tg = 0.5f + P.dfc * ((kind == K_DESIGN) ? khat_of(gm, P) : 1.0f);
       const float og = 1.0f / tg;
@@ -1052,8 +1098,9 @@ __global__ __launch_bounds__(kBlock) void k_thermal(ThermArgs A) {
   if constexpr (DIAG) block_reduce_store<kRedFwd>(acc, A.partials + (size_t)blk * kRedFwd);
 }
 
-// Initial thermal state g = g_eq(T, u) (stored shifted by w T_ref) at
-// non-wall nodes, 0 (that is w T_ref) at walls.
+// Initial thermal state g = g_eq(T, u) at non-wall nodes, stored relative
+// to the reference R = T (so only the advective part 4 w T e.u remains), and
+// 0 at walls (whose reference is +inf).
 template <class G>
 __global__ __launch_bounds__(kBlock) void k_thermal_init(ThermArgs A) {
   const KParams& P = A.P;
@@ -1062,11 +1109,119 @@ __global__ __launch_bounds__(kBlock) void k_thermal_init(ThermArgs A) {
   const int kind = A.flags[n] & 7;
   const float ux = A.u[n], uy = A.u[P.N + n], uz = A.u[2 * P.N + n];
   const float Tabs = A.T[n];
+  A.R[n] = (kind >= K_WALL) ? INFINITY : Tabs;
   sfor<G::Q>([&](auto I) {
     constexpr int i = I;
     const float eu = float(G::ex[i]) * ux + float(G::ey[i]) * uy + float(G::ez[i]) * uz;
-    const float keq = G::w[i] * ((Tabs - P.T_ref) + 4.0f * Tabs * eu);
+    const float keq = G::w[i] * (4.0f * Tabs * eu);
     A.gout[(size_t)i * P.Np + n] = (kind >= K_WALL) ? 0.0f : keq;
+  });
+}
+
+// Reference of a forward start: T_in at non-wall nodes, +inf at walls (and in
+// the padding beyond N).
+__global__ __launch_bounds__(kBlock) void k_ref_init(float* __restrict__ R,
+                                                     const uint8_t* __restrict__ flags, KParams P) {
+  const int n = blockIdx.x * kBlock + threadIdx.x;
+  if (n >= P.Np) return;
+  R[n] = (n < P.N && (flags[n] & 7) < K_WALL) ? P.T_in : INFINITY;
+}
+
+// Re-base of the forward thermal state onto the temperature field T: every
+// non-wall node n moves its own slots by w_i (Rin(n) - T(n)) and, for each
+// direction whose pull source is a wall, the wall slot it reads (walls hold
+// values in their reader's shift; each slot has one reader, so the writes do
+// not collide); Rout = T at non-wall nodes, +inf at walls.  Exact up to one
+// FP32 rounding per slot.
+template <class G, bool MIR>
+__device__ __forceinline__ void rebase_tile(const RebaseArgs& A, int blk) {
+  const KParams& P = A.P;
+  const int n = blk * kBlock + threadIdx.x;
+  if (n >= P.N) return;
+  const int kind = A.flags[n] & 7;
+  if (kind >= K_WALL) {
+    A.Rout[n] = INFINITY;
+    return;
+  }
+  const int x = n % P.nx, t = n / P.nx, y = t % P.ny, z = t / P.ny;
+  const Nbr nb = make_nbr(x, y, z, P);
+  const Mirror mr = MIR ? mirror_of(x, y, z, P) : Mirror{false, false, false};
+  const float Tn = A.T[n];
+  const float dR = A.Rin[n] - Tn;
+  A.Rout[n] = Tn;
+  sfor<G::Q>([&](auto I) {
+    constexpr int i = I;
+    float* own = A.g + (size_t)i * P.Np + n;
+    *own = *own + G::w[i] * dR;
+    if constexpr (i != 0) {
+      const Src sr = pull_src<G, i, -G::ex[i], -G::ey[i], -G::ez[i]>(nb, n, mr);
+      if (sr.valid && (A.flags[sr.node] & 7) >= K_WALL) {
+        float* ws = A.g + (size_t)sr.slot * P.Np + sr.node;
+        *ws = *ws + G::w[i] * dR;
+      }
+    }
+  });
+}
+
+template <class G, bool MIR>
+__global__ __launch_bounds__(kBlock) void k_rebase(RebaseArgs A) {
+  rebase_tile<G, MIR>(A, blockIdx.x);
+}
+
+// Re-base after launch q of a quantum: each slot whose step in that launch
+// was a diagnostic forward step re-bases its tiles (thermal engines only).
+__global__ __launch_bounds__(kBlock) void k_batch_rebase(const Tile* __restrict__ tiles,
+                                                         const SlotDev* __restrict__ slots,
+                                                         const int* __restrict__ base, int q,
+                                                         int xper, int xrem) {
+  const int b = blockIdx.x, xcd = b & 7, idx = b >> 3;
+  const int t = xcd < xrem ? xcd * (xper + 1) + idx : xrem * (xper + 1) + (xcd - xrem) * xper + idx;
+  const Tile tl = tiles[t];
+  const SlotDev& S = slots[tl.slot];
+  const int k = *base + q - S.start;
+  if (S.phase != 1 || k < 0 || k >= S.max_steps) return;  // uniform over the block
+  const bool diag = (S.check > 0 && (k + 1) % S.check == 0) || (k + 1 == S.max_steps);
+  if (!diag) return;
+  const bool r1 = S.check > 0 && ((k / S.check) & 1);
+  RebaseArgs A;
+  A.g = ((k + 1) & 1) ? S.fa.gout : const_cast<float*>(S.fa.gin);  // state after step k
+  A.Rin = r1 ? S.R1 : S.fa.Rin;
+  A.Rout = r1 ? const_cast<float*>(S.fa.Rin) : S.R1;
+  A.T = S.fa.T;
+  A.flags = S.fa.flags;
+  A.P = S.fa.P;
+  const bool mir = has_mirror(A.P);
+  if (A.P.q == 9) {
+    if (mir) rebase_tile<Q5, true>(A, tl.blk);
+    else rebase_tile<Q5, false>(A, tl.blk);
+  } else {
+    if (mir) rebase_tile<Q7, true>(A, tl.blk);
+    else rebase_tile<Q7, false>(A, tl.blk);
+  }
+}
+
+// The stored thermal state in the shift of T_in: own slots of non-wall nodes
+// and the wall slots they read move by w_i (R(n) - T_in); every other slot was
+// copied beforehand unchanged.
+template <class G, bool MIR>
+__global__ __launch_bounds__(kBlock) void k_export_thermal(const float* __restrict__ src,
+                                                           const float* __restrict__ R,
+                                                           const uint8_t* __restrict__ flags,
+                                                           float* __restrict__ dst, KParams P) {
+  const int n = blockIdx.x * kBlock + threadIdx.x;
+  if (n >= P.N || (flags[n] & 7) >= K_WALL) return;
+  const int x = n % P.nx, t = n / P.nx, y = t % P.ny, z = t / P.ny;
+  const Nbr nb = make_nbr(x, y, z, P);
+  const Mirror mr = MIR ? mirror_of(x, y, z, P) : Mirror{false, false, false};
+  const float dR = R[n] - P.T_in;
+  sfor<G::Q>([&](auto I) {
+    constexpr int i = I;
+    dst[(size_t)i * P.N + n] = src[(size_t)i * P.Np + n] + G::w[i] * dR;
+    if constexpr (i != 0) {
+      const Src sr = pull_src<G, i, -G::ex[i], -G::ey[i], -G::ez[i]>(nb, n, mr);
+      if (sr.valid && (flags[sr.node] & 7) >= K_WALL)
+        dst[(size_t)sr.slot * P.N + sr.node] = src[(size_t)sr.slot * P.Np + sr.node] + G::w[i] * dR;
+    }
   });
 }
 
@@ -1258,7 +1413,7 @@ __global__ __launch_bounds__(kBlock) void k_heat_init(float* __restrict__ g,
   const int n = blockIdx.x * kBlock + threadIdx.x;
   if (n >= P.N) return;
   if ((flags[n] & 7) != K_DESIGN) return;
-  const float Q = P.beta * (1.0f - gamma[n]) * (1.0f - P.T_ref);
+  const float Q = P.beta * (1.0f - gamma[n]) * (1.0f - P.T_in);
   sfor<G::Q>([&](auto I) { g[(size_t)I * P.Np + n] = G::w[I] * Q; });
 }
 
@@ -1268,6 +1423,48 @@ hipError_t launch_heat_init(float* g, const float* gamma, const uint8_t* flags, 
   const dim3 grid((P.N + kBlock - 1) / kBlock), block(kBlock);
   if (P.q == 9) hipLaunchKernelGGL((k_heat_init<Q5>), grid, block, 0, s, g, gamma, flags, P);
   else hipLaunchKernelGGL((k_heat_init<Q7>), grid, block, 0, s, g, gamma, flags, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_ref_init(float* R, const uint8_t* flags, const KParams& P, hipStream_t s) {
+  const dim3 grid((P.Np + kBlock - 1) / kBlock), block(kBlock);
+  hipLaunchKernelGGL(k_ref_init, grid, block, 0, s, R, flags, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_rebase(const RebaseArgs& a, hipStream_t s) {
+  const dim3 grid(a.P.nblk), block(kBlock);
+  const bool mir = (a.P.sx | a.P.sy | a.P.sz) != 0;
+  if (a.P.q == 9) {
+    if (mir) hipLaunchKernelGGL((k_rebase<Q5, true>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_rebase<Q5, false>), grid, block, 0, s, a);
+  } else {
+    if (mir) hipLaunchKernelGGL((k_rebase<Q7, true>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_rebase<Q7, false>), grid, block, 0, s, a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_export_thermal(const float* src, const float* R, const uint8_t* flags, float* dst,
+                                 const KParams& P, hipStream_t s) {
+  const dim3 grid(P.nblk), block(kBlock);
+  const bool mir = (P.sx | P.sy | P.sz) != 0;
+  if (P.q == 9) {
+    if (mir) hipLaunchKernelGGL((k_export_thermal<Q5, true>), grid, block, 0, s, src, R, flags, dst, P);
+    else hipLaunchKernelGGL((k_export_thermal<Q5, false>), grid, block, 0, s, src, R, flags, dst, P);
+  } else {
+    if (mir) hipLaunchKernelGGL((k_export_thermal<Q7, true>), grid, block, 0, s, src, R, flags, dst, P);
+    else hipLaunchKernelGGL((k_export_thermal<Q7, false>), grid, block, 0, s, src, R, flags, dst, P);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_rebase(const Tile* tiles, int ntiles, const SlotDev* slots, const int* base,
+                               int q, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  const int xper = ntiles / 8, xrem = ntiles % 8;
+  hipLaunchKernelGGL(k_batch_rebase, dim3(ntiles), dim3(kBlock), 0, s, tiles, slots, base, q,
+                     xper, xrem);
   return hipGetLastError();
 }
 
@@ -1328,9 +1525,12 @@ __global__ __launch_bounds__(kBlock) void k_stream_probe(FwdArgs A) {
   });
   float k[G::Q];
   if constexpr (THERMAL) {
+    // the reference temperatures are read where the step reads them
+    const float Rn = A.Rin[n];
     sfor<G::Q>([&](auto I) {
       constexpr int i = I;
-      k[i] = load_pull<G, i, -G::ex[i], -G::ey[i], -G::ez[i]>(A.gin, P.Np, nb, n, mr);
+      k[i] = load_pull_ref<G, i, -G::ex[i], -G::ey[i], -G::ez[i]>(A.gin, A.Rin, P.Np, nb, n, mr, Rn,
+                                                                   never);
     });
   }
   sfor<L::Q>([&](auto I) { A.fout[(size_t)I * P.Np + n] = never ? gv : h[I]; });

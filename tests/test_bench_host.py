@@ -34,8 +34,9 @@ def test_bytes_per_node(bench, name, q, thermal):
     assert bool(w.thermal) == thermal and (w.nz == 1) == (q == 9)
     qt = (5 if q == 9 else 7) if thermal else 0
     dim = 2 if q == 9 else 3
-    # every population read and written once, gamma and flags once
-    assert bench.bytes_per_node("forward", w) == (q + qt) * 8 + 4 + 1
+    # every population read and written once, gamma and flags once, and the
+    # thermal lattice's reference temperature
+    assert bench.bytes_per_node("forward", w) == (q + qt) * 8 + 4 + 1 + (4 if thermal else 0)
     extra = 12 if w.objective == 1 else 0      # dissipation source
     assert bench.bytes_per_node("adjoint", w) == (q + qt) * 8 + 4 * dim + (4 if thermal else 0) + 5 + extra
 

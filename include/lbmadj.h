@@ -196,6 +196,25 @@ size_t lbm_workspace_bytes(const lbm_problem_t* p);
  * (synchronous).  The workspace must outlive every later call. */
 int lbm_bind_workspace(lbm_problem_t* p, void* device_ptr, size_t bytes);
 
+/* Allocation-free binding, for callers that cannot allocate device memory
+ * (code under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Binds the library's static workspace of the current device
+ * (a 32 MiB device array the library holds on every GPU it runs on until the
+ * process ends) in place of caller memory, and uploads the node flags and
+ * inlet profile (synchronous, on the default stream).  Neither this call nor
+ * the later calls on p allocate device or pinned host memory (the residual
+ * sums come back through pageable host memory, which can make those copies
+ * wait for other streams).  Every problem bound this way on one device
+ * shares that device's array, which keeps the last call's contents: binding
+ * another problem takes the array over, after which the previous owner's
+ * calls return LBM_ESTATE until it is bound again; calls on problems that
+ * share a device's array must not overlap in time (they race).  The solves
+ * clear every buffer they need zeroed themselves.  LBM_EINVAL if
+ * lbm_workspace_bytes(p) exceeds 32 MiB (about 60,000 nodes of the coupled
+ * D3Q19 + D3Q7 lattices); LBM_EDEVICE if the array's address cannot be
+ * taken. */
+int lbm_bind_static_workspace(lbm_problem_t* p);
+
 /* Steady forward solve from rest (f = f_eq(rho0, 0), T = T_in).
  * gamma: device [N] design field (read).  drho: device [N], written with the
  * density deviation rho - rho0 (pressure deviation drho/3); u: device [3][N]

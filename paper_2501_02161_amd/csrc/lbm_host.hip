@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -266,6 +267,64 @@ int sweep_end(lbm_problem* p, int kind, int launches, hipStream_t s) {
   p->t_ms[kind] += ms;
   p->t_n[kind] += launches;
   return LBM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free binding: a static workspace per device, for callers that
+// cannot allocate device memory.  `scratch` is one array per GPU (each device
+// holds its own copy at its own address); host code uses only the address
+// hipGetSymbolAddress gives on each device, taken once per device.  One
+// problem at a time owns a device's array: binding another one takes it over
+// (the previous owner's later calls return LBM_ESTATE).
+// ---------------------------------------------------------------------------
+constexpr size_t kStaticBytes = size_t(32) << 20;
+constexpr int kStaticDevices = 64;
+__device__ __align__(256) char scratch[kStaticBytes];
+
+struct StaticWorkspace {
+  std::mutex mu;
+  void* ptr[kStaticDevices] = {};
+  const lbm_problem* owner[kStaticDevices] = {};
+};
+StaticWorkspace& static_ws() {
+  static StaticWorkspace s;
+  return s;
+}
+
+bool static_owned(const lbm_problem* p) {
+  if (!p->static_ws || p->dev < 0 || p->dev >= kStaticDevices) return false;
+  StaticWorkspace& sw = static_ws();
+  std::lock_guard<std::mutex> lk(sw.mu);
+  return sw.owner[p->dev] == p;
+}
+
+void static_release(const lbm_problem* p) {
+  if (!p->static_ws || p->dev < 0 || p->dev >= kStaticDevices) return;
+  StaticWorkspace& sw = static_ws();
+  std::lock_guard<std::mutex> lk(sw.mu);
+  if (sw.owner[p->dev] == p) sw.owner[p->dev] = nullptr;
+}
+
+// Workspace pointers of p at base (256-byte aligned) of `bytes` bytes.
+void set_workspace(lbm_problem* p, char* base, size_t bytes) {
+  const Layout L = layout_of(p);
+  const bool th = thermal_of(p);
+  p->ws = base;
+  p->ws_bytes = bytes;
+  for (int k = 0; k < 2; ++k) {
+    p->f[k] = (float*)(base + L.f[k]);
+    p->a[k] = (float*)(base + L.a[k]);
+    p->g[k] = th ? (float*)(base + L.g[k]) : nullptr;
+    p->b[k] = th ? (float*)(base + L.b[k]) : nullptr;
+    p->R[k] = th ? (float*)(base + L.R[k]) : nullptr;
+  }
+  p->rcur = 0;
+  p->gneq = th ? (float*)(base + L.gneq) : nullptr;
+  p->G = (p->d.objective == LBM_OBJ_DISSIPATION) ? (float*)(base + L.G) : nullptr;
+  p->uin = (float*)(base + L.uin);
+  p->flags = (uint8_t*)(base + L.flags);
+  p->partials = (double*)(base + L.partials);
+  p->sums = (double*)(base + L.sums);
 }
 
 bool rel_converged(double now, double before, double tol) {
@@ -533,6 +592,8 @@ int run_thermal(lbm_problem* p, const float* gamma, const float* u, const float*
 int check_bound(const lbm_problem* p) {
   if (!p) return fail(LBM_EINVAL, "problem is NULL");
   if (!p->ws) return fail(LBM_ESTATE, "no workspace bound");
+  if (p->static_ws && !static_owned(p))
+    return fail(LBM_ESTATE, "the device's static workspace has been bound to another problem since");
   return LBM_OK;
 }
 
@@ -586,26 +647,16 @@ int lbm_bind_workspace(lbm_problem_t* p, void* device_ptr, size_t bytes) {
   if (!p || !device_ptr) return fail(LBM_EINVAL, "problem or workspace is NULL");
   const Layout L = layout_of(p);
   if (bytes < L.total) return fail(LBM_EINVAL, "workspace too small");
+  static_release(p);
+  p->static_ws = false;
   HIPCHK(hipGetDevice(&p->dev));
   char* base = (char*)(((uintptr_t)device_ptr + 255) & ~uintptr_t(255));
-  p->ws = base;
-  p->ws_bytes = bytes;
-  const bool th = thermal_of(p);
-  for (int k = 0; k < 2; ++k) {
-    p->f[k] = (float*)(base + L.f[k]);
-    p->a[k] = (float*)(base + L.a[k]);
-    p->g[k] = th ? (float*)(base + L.g[k]) : nullptr;
-    p->b[k] = th ? (float*)(base + L.b[k]) : nullptr;
-    p->R[k] = th ? (float*)(base + L.R[k]) : nullptr;
+  set_workspace(p, base, bytes);
+  if (!p->pinned_owned) {
+    p->pinned = nullptr;
+    HIPCHK(hipHostMalloc((void**)&p->pinned, 16 * sizeof(double), hipHostMallocDefault));
+    p->pinned_owned = true;
   }
-  p->rcur = 0;
-  p->gneq = th ? (float*)(base + L.gneq) : nullptr;
-  p->G = (p->d.objective == LBM_OBJ_DISSIPATION) ? (float*)(base + L.G) : nullptr;
-  p->uin = (float*)(base + L.uin);
-  p->flags = (uint8_t*)(base + L.flags);
-  p->partials = (double*)(base + L.partials);
-  p->sums = (double*)(base + L.sums);
-  if (!p->pinned) HIPCHK(hipHostMalloc((void**)&p->pinned, 16 * sizeof(double), hipHostMallocDefault));
   std::vector<float> uin(p->Np, 0.0f);
   std::copy(p->uin_host.begin(), p->uin_host.end(), uin.begin());
   std::vector<uint8_t> fl(p->Np, (uint8_t)K_WALL);
@@ -613,6 +664,48 @@ int lbm_bind_workspace(lbm_problem_t* p, void* device_ptr, size_t bytes) {
   HIPCHK(hipMemcpy(p->uin, uin.data(), p->Np * sizeof(float), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(p->flags, fl.data(), p->Np, hipMemcpyHostToDevice));
   p->fwd_done = p->adj_done = p->adj_state = false;
+  return LBM_OK;
+}
+
+int lbm_bind_static_workspace(lbm_problem_t* p) {
+  last_error().clear();
+  if (!p) return fail(LBM_EINVAL, "problem is NULL");
+  const Layout L = layout_of(p);
+  if (L.total > kStaticBytes)
+    return fail(LBM_EINVAL, "the problem needs " + std::to_string(L.total) +
+                                " bytes of workspace; the static workspace holds " +
+                                std::to_string(kStaticBytes));
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kStaticDevices) return fail(LBM_EINVAL, "device index out of range");
+  void* base = nullptr;
+  {
+    StaticWorkspace& sw = static_ws();
+    std::lock_guard<std::mutex> lk(sw.mu);
+    if (!sw.ptr[dev]) {
+      void* ptr = nullptr;
+      const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !ptr)
+        return fail(LBM_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+      sw.ptr[dev] = ptr;
+    }
+    base = sw.ptr[dev];
+    if (p->static_ws && p->dev >= 0 && p->dev < kStaticDevices && sw.owner[p->dev] == p)
+      sw.owner[p->dev] = nullptr;
+    sw.owner[dev] = p;
+  }
+  p->static_ws = true;
+  p->dev = dev;
+  set_workspace(p, (char*)base, kStaticBytes);
+  if (!p->pinned_owned) p->pinned = p->pinned_local;
+  // node flags and inlet profile; the padding beyond N is a wall with no inflow
+  const size_t pad = (size_t)(p->Np - p->N);
+  HIPCHK(hipMemcpy(p->uin, p->uin_host.data(), (size_t)p->N * sizeof(float), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(p->flags, p->flags_host.data(), (size_t)p->N, hipMemcpyHostToDevice));
+  HIPCHK(launch_fill(p->uin + p->N, pad, nullptr));
+  HIPCHK(launch_fill_u8(p->flags + p->N, pad, (uint8_t)K_WALL, nullptr));
+  HIPCHK(hipStreamSynchronize(nullptr));
+  p->fwd_done = p->adj_done = p->adj_state = p->have_gneq = false;
   return LBM_OK;
 }
 
@@ -953,7 +1046,8 @@ void lbm_problem_destroy(lbm_problem_t* p) {
     (void)hipEventDestroy(p->sweep_ev[0]);
     (void)hipEventDestroy(p->sweep_ev[1]);
   }
-  if (p->pinned) (void)hipHostFree(p->pinned);
+  static_release(p);
+  if (p->pinned && p->pinned_owned) (void)hipHostFree(p->pinned);
   delete p;
 }
 

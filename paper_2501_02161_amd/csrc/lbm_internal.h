@@ -154,6 +154,7 @@ struct Tile {
 
 // Launchers (return the hipError_t of the launch).
 hipError_t launch_fill(float* p, size_t count, hipStream_t s);
+hipError_t launch_fill_u8(uint8_t* p, size_t count, uint8_t value, hipStream_t s);
 // Copy of n16 16-byte words (dwordx4 loads and stores); both pointers 16-byte aligned.
 hipError_t launch_copy16(const void* src, void* dst, size_t n16, hipStream_t s);
 // Level-set design update (per-block FP64 partials: stats 2 values, lambda 1).
@@ -271,7 +272,10 @@ struct lbm_problem {
   uint8_t* flags = nullptr;
   double* partials = nullptr;
   double* sums = nullptr;
-  double* pinned = nullptr;
+  double* pinned = nullptr;        // host copy of the reduction sums
+  bool pinned_owned = false;       // pinned was allocated by lbm_bind_workspace
+  double pinned_local[16] = {};    // pageable stand-in of the allocation-free binding
+  bool static_ws = false;          // bound to the device's static workspace
   int fcur = 0, acur = 0;
   bool fwd_done = false, adj_done = false;
   bool adj_state = false;  // the adjoint populations hold a finished adjoint solve (resumable)

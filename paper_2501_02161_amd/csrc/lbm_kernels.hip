@@ -1251,6 +1251,11 @@ __global__ void k_fill(float* __restrict__ p, size_t count) {
   if (i < count) p[i] = 0.0f;
 }
 
+__global__ void k_fill_u8(uint8_t* __restrict__ p, size_t count, uint8_t value) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = value;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1474,6 +1479,13 @@ hipError_t launch_copy16(const void* src, void* dst, size_t n16, hipStream_t s) 
   const unsigned blocks = (unsigned)((n16 + per - 1) / per);
   hipLaunchKernelGGL(k_copy16, dim3(blocks), dim3(kBlock), 0, s, (const float4*)src, (float4*)dst,
                      n16);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u8(uint8_t* p, size_t count, uint8_t value, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  const unsigned blocks = (unsigned)((count + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_fill_u8, dim3(blocks), dim3(kBlock), 0, s, p, count, value);
   return hipGetLastError();
 }
 

@@ -77,7 +77,8 @@ class lbm_batch_stats_t(ctypes.Structure):
 LBM_BATCH_QUEUED, LBM_BATCH_RUNNING, LBM_BATCH_DONE, LBM_BATCH_FAILED = 0, 1, 2, 3
 LBM_BATCH_POLICY_ALL, LBM_BATCH_POLICY_SRW, LBM_BATCH_POLICY_OVERLAP = 0, 1, 2
 
-EXPORTS = ("lbm_problem_create", "lbm_workspace_bytes", "lbm_bind_workspace", "lbm_forward_solve",
+EXPORTS = ("lbm_problem_create", "lbm_workspace_bytes", "lbm_bind_workspace",
+           "lbm_bind_static_workspace", "lbm_forward_solve",
            "lbm_forward_continue", "lbm_adjoint_solve", "lbm_adjoint_continue",
            "lbm_thermal_resolve", "lbm_sensitivity", "lbm_forward_resume",
            "lbm_adjoint_resume", "lbm_levelset_update",
@@ -107,6 +108,8 @@ def load_library(path: str = LIB_PATH):
     lib.lbm_workspace_bytes.restype = c_size_t
     lib.lbm_bind_workspace.argtypes = [P, P, c_size_t]
     lib.lbm_bind_workspace.restype = c_int
+    lib.lbm_bind_static_workspace.argtypes = [P]
+    lib.lbm_bind_static_workspace.restype = c_int
     lib.lbm_forward_solve.argtypes = [P, P, P, P, P, POINTER(lbm_info_t), P]
     lib.lbm_forward_solve.restype = c_int
     lib.lbm_forward_continue.argtypes = [P, P, c_int32, P, P, P, POINTER(lbm_info_t), P]
@@ -203,6 +206,12 @@ def lbm_workspace_bytes(p) -> int:
 
 def lbm_bind_workspace(p, ws: torch.Tensor) -> None:
     _check(load_library().lbm_bind_workspace(p, c_void_p(ws.data_ptr()), ws.numel()))
+
+
+def lbm_bind_static_workspace(p) -> None:
+    """Bind the library's static workspace of the current device (no device
+    allocation; at most 32 MiB; one problem per device owns it at a time)."""
+    _check(load_library().lbm_bind_static_workspace(p))
 
 
 def lbm_forward_solve(p, gamma, drho, u, T, stream=None) -> lbm_info_t:
@@ -413,7 +422,7 @@ class Problem:
     """One lattice problem on one GPU: the C handle plus its bound workspace
     (a torch uint8 tensor) and the output fields as torch tensors."""
 
-    def __init__(self, spec, device=None, **overrides):
+    def __init__(self, spec, device=None, static_workspace: bool = False, **overrides):
         self.lib = load_library()
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None \
             else torch.device(device)
@@ -426,9 +435,13 @@ class Problem:
         self.shape = (spec.nz, spec.ny, spec.nx)
         self.thermal = bool(spec.thermal)
         with torch.cuda.device(self.device):
-            self.ws = torch.empty(lbm_workspace_bytes(self.h), dtype=torch.uint8,
-                                  device=self.device)
-            lbm_bind_workspace(self.h, self.ws)
+            if static_workspace:
+                self.ws = None
+                lbm_bind_static_workspace(self.h)
+            else:
+                self.ws = torch.empty(lbm_workspace_bytes(self.h), dtype=torch.uint8,
+                                      device=self.device)
+                lbm_bind_workspace(self.h, self.ws)
         z = lambda *s: torch.zeros(*s, dtype=torch.float32, device=self.device)
         self.drho = z(self.shape)
         self.u = z((3,) + self.shape)

@@ -445,6 +445,20 @@ int lbm_batch_bind_arena(lbm_batch_t* b, void* device_ptr, size_t bytes);
  * OVERLAP, fill 512.  LBM_EINVAL on an unknown policy or fill_tiles < 1,
  * LBM_ESTATE while a quantum is in flight. */
 int lbm_batch_set_policy(lbm_batch_t* b, int32_t policy, int32_t fill_tiles);
+/* Persistent quanta: a lane whose run set spans at most max_tiles tiles of
+ * 256 nodes (a lone request included) runs its whole quantum as one
+ * cooperative launch of the ragged-batch kernel, sized to the blocks the
+ * device holds at once; its blocks loop over the quantum's steps with a
+ * device-wide barrier between steps (a bounded wait: a barrier that waits
+ * too long makes the launch give up and the lane's requests FAILED with
+ * LBM_EDEVICE).  Larger run sets take one launch per step.  The arithmetic,
+ * and so every result, is the same either way.  max_tiles = 0 turns the
+ * persistent form off.  Default 0: on MI355X a device-wide barrier (a
+ * device-scope atomic per block plus the L2 write-back every XCD needs) costs
+ * more than the kernel boundary it replaces, so one launch per step is
+ * faster at every run-set size measured.  LBM_EINVAL for max_tiles < 0,
+ * LBM_ESTATE while a quantum is in flight. */
+int lbm_batch_set_persistent(lbm_batch_t* b, int32_t max_tiles);
 /* Queue a request; validates it (LBM_EINVAL, or LBM_ENOMEM if it can never
  * fit the arena) and returns its ticket. */
 int lbm_batch_submit(lbm_batch_t* b, const lbm_desc_t* desc, const uint8_t* mask,

@@ -147,7 +147,11 @@ struct Lane {
   Tile* d_tiles = nullptr;
   double* d_sums = nullptr;
   int* d_base = nullptr;
+  unsigned* d_bar = nullptr;  // grid-barrier arrivals of a persistent quantum
+  int* d_abort = nullptr;     // raised when a persistent quantum's barrier wait gives up
   double* h_sums = nullptr;  // pinned
+  int* h_abort = nullptr;    // pinned copy of *d_abort after each persistent quantum
+  bool persistent = false;   // the quantum in flight is a persistent launch
   std::map<int, hipGraphExec_t> graphs;  // quantum graph per tile count
   // quanta of a lone slot: the single-problem kernels, arguments by value,
   // keyed by (ticket, phase, parity of the first step, residual step at end)
@@ -219,6 +223,9 @@ struct lbm_batch {
   int thermal = 0, objective = 0, max_slots = 0, quantum = 0;
   int policy = LBM_BATCH_POLICY_OVERLAP;
   int fill_tiles = 512;
+  int persist_tiles = 0;     // run sets of at most this many tiles run as one persistent launch
+  int persist_grid = 0;      // resident blocks of the persistent kernel on the device
+  int spin_limit = 1 << 21;  // polls of a grid-barrier wait before it gives up
   int dev = -1;
   char* base = nullptr;  // request arena start (aligned)
   Arena arena;
@@ -692,6 +699,48 @@ int launch_solo(lbm_batch* b, int L, int i) {
   return LBM_OK;
 }
 
+// One quantum of lane L as a single persistent launch (its tables are
+// uploaded): barrier counters cleared, the quantum's steps and the re-base in
+// one cooperative launch, the per-slot residual sums, the launch counter, the
+// copies to the host and the completion event.
+int launch_persistent(lbm_batch* b, int L, int ntiles) {
+  Lane& ln = b->lanes[L];
+  const Tile* tiles = ln.d_tiles;
+  const SlotDev* sl = ln.d_slots;
+  int* base = ln.d_base;
+  unsigned* bar = ln.d_bar;
+  int* abort = ln.d_abort;
+  int* habort = ln.h_abort;
+  double* ds = ln.d_sums;
+  double* hs = ln.h_sums;
+  hipStream_t st = ln.stream;
+  hipEvent_t ev = ln.done;
+  const int Q = b->quantum, ns = b->max_slots, obj = b->objective, grid = b->persist_grid;
+  const int spin = b->spin_limit;
+  const bool th = b->thermal != 0;
+  post(ln.worker.get(), [=]() -> hipError_t {
+    // bar and abort are single words: 0.0f fills them with zero bits
+    hipError_t e = launch_fill((float*)bar, 1, st);
+    if (e == hipSuccess) e = launch_fill((float*)abort, 1, st);
+    if (e == hipSuccess)
+      e = launch_batch_persistent(tiles, ntiles, sl, base, Q, th, obj, bar, abort, spin, grid, st);
+    if (e == hipSuccess) e = launch_finalize_slots(sl, ns, ds, st);
+    if (e == hipSuccess) e = launch_advance(base, Q, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(hs, ds, ns * 4 * sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(habort, abort, sizeof(int), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipEventRecord(ev, st);
+    return e;
+  });
+  ln.launch += b->quantum;
+  b->launches += 1;
+  for (int i = 0; i < b->max_slots; ++i)
+    if (ln.run[i] && running(b->slots[i])) b->slots[i].lane = L;
+  b->node_updates += ln.nodes * b->quantum;  // slots that finish early idle their tiles
+  ln.persistent = true;
+  ln.busy = true;
+  return LBM_OK;
+}
+
 // Issue one quantum of lane L (tables, `quantum` batch launches, residual
 // sums to the host, completion event).  No-op for an empty run set.
 int launch_quantum(lbm_batch* b, int L) {
@@ -703,13 +752,16 @@ int launch_quantum(lbm_batch* b, int L) {
       only = i;
     }
   if (nrun == 0) return LBM_OK;
-  if (nrun == 1) return launch_solo(b, L, only);
+  const bool persist_ok = b->persist_grid > 0 && b->persist_tiles > 0;
+  if (nrun == 1 && !(persist_ok && b->slots[only].p->nblk <= b->persist_tiles))
+    return launch_solo(b, L, only);
   if (needs_upload(b, ln)) {
     int rc = upload_tables(b, ln);
     if (rc) return rc;
   }
   const int ntiles = (int)ln.h_tiles.size();
   if (ntiles == 0) return LBM_OK;
+  if (persist_ok && ntiles <= b->persist_tiles) return launch_persistent(b, L, ntiles);
   hipGraphExec_t x = nullptr;
   if (ntiles < kDirectTiles) {
     auto it = ln.graphs.find(ntiles);
@@ -774,10 +826,19 @@ int launch_quantum(lbm_batch* b, int L) {
 // Bookkeeping once lane L's quantum has completed.
 int complete_quantum(lbm_batch* b, int L) {
   Lane& ln = b->lanes[L];
+  const bool gave_up = ln.persistent && *ln.h_abort != 0;
+  ln.persistent = false;
   for (int i = 0; i < b->max_slots; ++i) {
     Slot& s = b->slots[i];
     if (!running(s) || s.lane != L) continue;
     s.lane = -1;
+    if (gave_up) {
+      // the quantum stopped part-way: its slots' states are not steps of their solves
+      s.error = "persistent batch launch: a grid barrier wait gave up";
+      s.phase = PH_FAILED;
+      s.status = LBM_EDEVICE;
+      continue;
+    }
     s.steps = std::min(s.steps + b->quantum, s.p->d.max_steps);
     int rc = after_quantum(b, i, ln);
     if (rc) return rc;
@@ -815,6 +876,8 @@ void free_lanes(lbm_batch* b) {
     }
     if (ln.done) (void)hipEventDestroy(ln.done);
     if (ln.h_sums) (void)hipHostFree(ln.h_sums);
+    if (ln.h_abort) (void)hipHostFree(ln.h_abort);
+    ln.h_abort = nullptr;
     if (ln.pin_slots) (void)hipHostFree(ln.pin_slots);
     if (ln.pin_tiles) (void)hipHostFree(ln.pin_tiles);
     ln.stream = nullptr;
@@ -883,11 +946,15 @@ int lbm_batch_bind_arena(lbm_batch_t* b, void* device_ptr, size_t bytes) {
     ln.d_tiles = (Tile*)(t + align256(b->max_slots * sizeof(SlotDev)));
     ln.d_sums = (double*)((char*)ln.d_tiles + align256((size_t)b->max_tiles * sizeof(Tile)));
     ln.d_base = (int*)((char*)ln.d_sums + align256((size_t)b->max_slots * 4 * sizeof(double)));
+    ln.d_bar = (unsigned*)((char*)ln.d_base + 64);
+    ln.d_abort = (int*)((char*)ln.d_base + 128);
     t += lane_table_bytes(b->max_slots, b->max_tiles);
     if (!ln.stream) HIPCHK(hipStreamCreateWithFlags(&ln.stream, hipStreamNonBlocking));
     if (!ln.done) HIPCHK(hipEventCreateWithFlags(&ln.done, hipEventDisableTiming));
     if (!ln.h_sums)
       HIPCHK(hipHostMalloc((void**)&ln.h_sums, b->max_slots * 4 * sizeof(double), hipHostMallocDefault));
+    if (!ln.h_abort) HIPCHK(hipHostMalloc((void**)&ln.h_abort, 4 * sizeof(int), hipHostMallocDefault));
+    *ln.h_abort = 0;
     if (!ln.pin_slots)
       HIPCHK(hipHostMalloc((void**)&ln.pin_slots, b->max_slots * sizeof(SlotDev), hipHostMallocDefault));
     if (ln.pin_tiles) HIPCHK(hipHostFree(ln.pin_tiles));
@@ -908,6 +975,7 @@ int lbm_batch_bind_arena(lbm_batch_t* b, void* device_ptr, size_t bytes) {
   }
   b->base = base + tb;
   b->arena.reset((usable - tb) & ~size_t(255));
+  b->persist_grid = persistent_grid_limit(b->thermal != 0, b->objective);
   return LBM_OK;
 }
 
@@ -921,6 +989,16 @@ int lbm_batch_set_policy(lbm_batch_t* b, int32_t policy, int32_t fill_tiles) {
     if (ln.busy) return fail(LBM_ESTATE, "cannot change the policy while a quantum is in flight");
   b->policy = policy;
   b->fill_tiles = fill_tiles;
+  return LBM_OK;
+}
+
+int lbm_batch_set_persistent(lbm_batch_t* b, int32_t max_tiles) {
+  last_error().clear();
+  if (!b) return fail(LBM_EINVAL, "batch is NULL");
+  if (max_tiles < 0) return fail(LBM_EINVAL, "max_tiles must be >= 0");
+  for (const Lane& ln : b->lanes)
+    if (ln.busy) return fail(LBM_ESTATE, "cannot change the launch form while a quantum is in flight");
+  b->persist_tiles = max_tiles;
   return LBM_OK;
 }
 

@@ -206,6 +206,18 @@ hipError_t launch_finalize(const double* partials, int nblk, int nvals, double* 
                            hipStream_t s);
 hipError_t launch_batch(const Tile* tiles, int ntiles, const SlotDev* slots, const int* base,
                         int q, bool thermal, int objective, hipStream_t s);
+// Persistent form of a quantum: one cooperative launch of `grid` resident
+// blocks (at most persistent_grid_limit(), capped at ntiles) that steps every
+// slot Q times with a grid barrier between steps and re-bases the thermal
+// states of diagnostic steps at the end.  *bar must be 0 at launch; *abort is
+// raised (and the launch leaves early) if a barrier wait exceeds spin_limit
+// polls.
+hipError_t launch_batch_persistent(const Tile* tiles, int ntiles, const SlotDev* slots,
+                                   const int* base, int Q, bool thermal, int objective,
+                                   unsigned* bar, int* abort, int spin_limit, int grid,
+                                   hipStream_t s);
+// Blocks of the persistent kernel that fit on the device at once (0 if unknown).
+int persistent_grid_limit(bool thermal, int objective);
 // *base += q on the device (end of a quantum of q launches).
 hipError_t launch_advance(int* base, int q, hipStream_t s);
 // Per-slot residual sums of the slots' last diagnostic step: out[slot * 4 + v].

@@ -17,6 +17,7 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "lbm_internal.h"
@@ -1000,19 +1001,12 @@ __device__ __forceinline__ void batch_tile(const SlotDev& S, int blk, int k, boo
   }
 }
 
-// Ragged-batch step: block -> tile (XCD-contiguous runs of tiles) -> slot ->
-// the slot's forward or adjoint step on that tile, with the same tile code as
-// the single-problem kernels, so a slot computes bit for bit what it would
-// alone.  An engine takes 3D and 2D requests side by side (the lattice is
-// uniform over a block: a tile belongs to one slot).
+// One tile of a ragged-batch launch: the tile's slot takes its forward or
+// adjoint step number `launch - start` (nothing if the slot is idle there).
 template <bool THERMAL, int OBJ>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_batch(const Tile* __restrict__ tiles,
-                                                  const SlotDev* __restrict__ slots,
-                                                  const int* __restrict__ base, int q, int xper,
-                                                  int xrem) {
-  const int b = blockIdx.x, xcd = b & 7, idx = b >> 3;
-  const int t = xcd < xrem ? xcd * (xper + 1) + idx : xrem * (xper + 1) + (xcd - xrem) * xper + idx;
-  const int launch = *base + q;
+__device__ __forceinline__ void batch_step_tile(const Tile* __restrict__ tiles,
+                                                const SlotDev* __restrict__ slots, int t,
+                                                int launch) {
   const Tile tl = tiles[t];
   const SlotDev& S = slots[tl.slot];
   const int k = launch - S.start;
@@ -1026,6 +1020,21 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
   }
   if (mir) batch_tile<Q19, true, THERMAL, OBJ>(S, tl.blk, k, diag);
   else batch_tile<Q19, false, THERMAL, OBJ>(S, tl.blk, k, diag);
+}
+
+// Ragged-batch step: block -> tile (XCD-contiguous runs of tiles) -> slot ->
+// the slot's forward or adjoint step on that tile, with the same tile code as
+// the single-problem kernels, so a slot computes bit for bit what it would
+// alone.  An engine takes 3D and 2D requests side by side (the lattice is
+// uniform over a block: a tile belongs to one slot).
+template <bool THERMAL, int OBJ>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_batch(const Tile* __restrict__ tiles,
+                                                  const SlotDev* __restrict__ slots,
+                                                  const int* __restrict__ base, int q, int xper,
+                                                  int xrem) {
+  const int b = blockIdx.x, xcd = b & 7, idx = b >> 3;
+  const int t = xcd < xrem ? xcd * (xper + 1) + idx : xrem * (xper + 1) + (xcd - xrem) * xper + idx;
+  batch_step_tile<THERMAL, OBJ>(tiles, slots, t, *base + q);
 }
 
 __global__ void k_advance(int* base, int q) {
@@ -1168,17 +1177,14 @@ __global__ __launch_bounds__(kBlock) void k_rebase(RebaseArgs A) {
   rebase_tile<G, MIR>(A, blockIdx.x);
 }
 
-// Re-base after launch q of a quantum: each slot whose step in that launch
-// was a diagnostic forward step re-bases its tiles (thermal engines only).
-__global__ __launch_bounds__(kBlock) void k_batch_rebase(const Tile* __restrict__ tiles,
-                                                         const SlotDev* __restrict__ slots,
-                                                         const int* __restrict__ base, int q,
-                                                         int xper, int xrem) {
-  const int b = blockIdx.x, xcd = b & 7, idx = b >> 3;
-  const int t = xcd < xrem ? xcd * (xper + 1) + idx : xrem * (xper + 1) + (xcd - xrem) * xper + idx;
+// Re-base after the step `launch` of the tile's slot, if that was a
+// diagnostic forward step (thermal engines only).
+__device__ __forceinline__ void batch_rebase_tile(const Tile* __restrict__ tiles,
+                                                  const SlotDev* __restrict__ slots, int t,
+                                                  int launch) {
   const Tile tl = tiles[t];
   const SlotDev& S = slots[tl.slot];
-  const int k = *base + q - S.start;
+  const int k = launch - S.start;
   if (S.phase != 1 || k < 0 || k >= S.max_steps) return;  // uniform over the block
   const bool diag = (S.check > 0 && (k + 1) % S.check == 0) || (k + 1 == S.max_steps);
   if (!diag) return;
@@ -1198,6 +1204,81 @@ __global__ __launch_bounds__(kBlock) void k_batch_rebase(const Tile* __restrict_
     if (mir) rebase_tile<Q7, true>(A, tl.blk);
     else rebase_tile<Q7, false>(A, tl.blk);
   }
+}
+
+// Re-base after launch q of a quantum: each slot whose step in that launch
+// was a diagnostic forward step re-bases its tiles (thermal engines only).
+__global__ __launch_bounds__(kBlock) void k_batch_rebase(const Tile* __restrict__ tiles,
+                                                         const SlotDev* __restrict__ slots,
+                                                         const int* __restrict__ base, int q,
+                                                         int xper, int xrem) {
+  const int b = blockIdx.x, xcd = b & 7, idx = b >> 3;
+  const int t = xcd < xrem ? xcd * (xper + 1) + idx : xrem * (xper + 1) + (xcd - xrem) * xper + idx;
+  batch_rebase_tile(tiles, slots, t, *base + q);
+}
+
+// Grid-wide barrier of a persistent launch whose blocks are all resident:
+// every block's writes are made visible at device scope, block 0's thread 0
+// of each block counts in, and waits until `target` arrivals are counted.
+// The wait is bounded: after `spin_limit` polls, or once another block has
+// given up, the block raises `abort` and returns false, so every block
+// leaves its loop (the host then reports the quantum as failed).
+__device__ __forceinline__ bool grid_barrier(unsigned* bar, int* abort, unsigned target,
+                                             int spin_limit) {
+  __shared__ int ok;
+  // every wave's stores have reached the L2 before the block counts in (a
+  // workgroup barrier alone does not wait for them); thread 0's release then
+  // writes the L2 back for the other XCDs, and one acquire after the wait
+  // drops stale lines (the polls themselves are relaxed: an acquire per poll
+  // would invalidate the L2 under the blocks still computing)
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    int good = 1, spins = 0;
+    while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (__hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+          ++spins > spin_limit) {
+        __hip_atomic_store(abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        good = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    ok = good;
+  }
+  __syncthreads();
+  return ok != 0;
+}
+
+// Persistent ragged-batch quantum: one launch whose blocks (all resident)
+// loop over the quantum's Q lattice steps.  Each block owns a contiguous run
+// of tiles (blocks of one XCD own neighbouring runs), advances them by one
+// step of their slots, then waits at a grid barrier for the whole step; after
+// the last step the thermal states of diagnostic steps are re-based.  The
+// arithmetic of every tile is the per-launch kernel's, so the results are
+// bit for bit those of Q launches of k_batch.  `bar` counts barrier
+// arrivals and must be 0 at launch.
+template <bool THERMAL, int OBJ>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_batch_persistent(
+    const Tile* __restrict__ tiles, int ntiles, const SlotDev* __restrict__ slots,
+    const int* __restrict__ base, int Q, unsigned* bar, int* abort, int spin_limit) {
+  const int G = gridDim.x;
+  const int b = blockIdx.x, xcd = b & 7, idx = b >> 3;
+  const int xper = G / 8, xrem = G % 8;
+  const int lb = xcd < xrem ? xcd * (xper + 1) + idx : xrem * (xper + 1) + (xcd - xrem) * xper + idx;
+  const int t0 = (int)((long long)lb * ntiles / G), t1 = (int)((long long)(lb + 1) * ntiles / G);
+  const int launch0 = *base;
+  for (int q = 0; q < Q; ++q) {
+    for (int t = t0; t < t1; ++t) {
+      batch_step_tile<THERMAL, OBJ>(tiles, slots, t, launch0 + q);
+      __syncthreads();  // the block reduction's shared memory is reused by the next tile
+    }
+    if (!grid_barrier(bar, abort, (unsigned)(q + 1) * (unsigned)G, spin_limit)) return;
+  }
+  if constexpr (THERMAL)
+    for (int t = t0; t < t1; ++t) batch_rebase_tile(tiles, slots, t, launch0 + Q - 1);
 }
 
 // The stored thermal state in the shift of T_in: own slots of non-wall nodes
@@ -1462,6 +1543,59 @@ hipError_t launch_export_thermal(const float* src, const float* R, const uint8_t
     else hipLaunchKernelGGL((k_export_thermal<Q7, false>), grid, block, 0, s, src, R, flags, dst, P);
   }
   return hipGetLastError();
+}
+
+template <bool TH, int OBJ>
+static hipError_t persistent_launch(const Tile* tiles, int ntiles, const SlotDev* slots,
+                                    const int* base, int Q, unsigned* bar, int* abort,
+                                    int spin_limit, int grid, hipStream_t s) {
+  void* args[] = {(void*)&tiles, (void*)&ntiles, (void*)&slots, (void*)&base, (void*)&Q,
+                  (void*)&bar,   (void*)&abort,  (void*)&spin_limit};
+  return hipLaunchCooperativeKernel((const void*)k_batch_persistent<TH, OBJ>, dim3(grid), dim3(kBlock),
+                                    args, 0, s);
+}
+
+int persistent_grid_limit(bool thermal, int objective) {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  const void* k = nullptr;
+  if (thermal) {
+    switch (objective) {
+      case OBJ_PRESSURE_DROP: k = (const void*)k_batch_persistent<true, OBJ_PRESSURE_DROP>; break;
+      case OBJ_DISSIPATION: k = (const void*)k_batch_persistent<true, OBJ_DISSIPATION>; break;
+      case OBJ_HEATGEN: k = (const void*)k_batch_persistent<true, OBJ_HEATGEN>; break;
+      default: k = (const void*)k_batch_persistent<true, OBJ_HEATSINK>; break;
+    }
+  } else {
+    k = objective == OBJ_PRESSURE_DROP ? (const void*)k_batch_persistent<false, OBJ_PRESSURE_DROP>
+                                       : (const void*)k_batch_persistent<false, OBJ_DISSIPATION>;
+  }
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, kBlock, 0) != hipSuccess) return 0;
+  return per * cus;
+}
+
+hipError_t launch_batch_persistent(const Tile* tiles, int ntiles, const SlotDev* slots,
+                                   const int* base, int Q, bool thermal, int objective,
+                                   unsigned* bar, int* abort, int spin_limit, int grid,
+                                   hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  grid = std::min(grid, ntiles);
+  if (thermal) {
+    switch (objective) {
+      case OBJ_PRESSURE_DROP:
+        return persistent_launch<true, OBJ_PRESSURE_DROP>(tiles, ntiles, slots, base, Q, bar, abort, spin_limit, grid, s);
+      case OBJ_DISSIPATION:
+        return persistent_launch<true, OBJ_DISSIPATION>(tiles, ntiles, slots, base, Q, bar, abort, spin_limit, grid, s);
+      case OBJ_HEATGEN:
+        return persistent_launch<true, OBJ_HEATGEN>(tiles, ntiles, slots, base, Q, bar, abort, spin_limit, grid, s);
+      default:
+        return persistent_launch<true, OBJ_HEATSINK>(tiles, ntiles, slots, base, Q, bar, abort, spin_limit, grid, s);
+    }
+  }
+  if (objective == OBJ_PRESSURE_DROP)
+    return persistent_launch<false, OBJ_PRESSURE_DROP>(tiles, ntiles, slots, base, Q, bar, abort, spin_limit, grid, s);
+  return persistent_launch<false, OBJ_DISSIPATION>(tiles, ntiles, slots, base, Q, bar, abort, spin_limit, grid, s);
 }
 
 hipError_t launch_batch_rebase(const Tile* tiles, int ntiles, const SlotDev* slots, const int* base,

@@ -86,7 +86,7 @@ EXPORTS = ("lbm_problem_create", "lbm_workspace_bytes", "lbm_bind_workspace",
            "lbm_copy_probe",
            "lbm_lattice",
            "lbm_problem_destroy", "lbm_last_error", "lbm_batch_create", "lbm_batch_table_bytes",
-           "lbm_batch_bind_arena", "lbm_batch_set_policy", "lbm_batch_submit", "lbm_batch_step", "lbm_batch_poll",
+           "lbm_batch_bind_arena", "lbm_batch_set_policy", "lbm_batch_set_persistent", "lbm_batch_submit", "lbm_batch_step", "lbm_batch_poll",
            "lbm_batch_stats", "lbm_batch_destroy")
 
 _lib = None
@@ -153,6 +153,8 @@ def load_library(path: str = LIB_PATH):
     lib.lbm_batch_bind_arena.restype = c_int
     lib.lbm_batch_set_policy.argtypes = [P, c_int32, c_int32]
     lib.lbm_batch_set_policy.restype = c_int
+    lib.lbm_batch_set_persistent.argtypes = [P, c_int32]
+    lib.lbm_batch_set_persistent.restype = c_int
     lib.lbm_batch_submit.argtypes = [P, POINTER(lbm_desc_t), P, P, POINTER(ctypes.c_int64)]
     lib.lbm_batch_submit.restype = c_int
     lib.lbm_batch_step.argtypes = [P, P, POINTER(c_int32), POINTER(c_int32)]
@@ -359,6 +361,10 @@ def lbm_batch_bind_arena(b, arena: torch.Tensor) -> None:
 
 def lbm_batch_set_policy(b, policy: int, fill_tiles: int = 512) -> None:
     _check(load_library().lbm_batch_set_policy(b, int(policy), int(fill_tiles)))
+
+
+def lbm_batch_set_persistent(b, max_tiles: int) -> None:
+    _check(load_library().lbm_batch_set_persistent(b, int(max_tiles)))
 
 
 def lbm_batch_submit(b, desc: lbm_desc_t, mask, gamma) -> int:

@@ -2,8 +2,9 @@
 
 `BatchEngine` wraps the library's batch engine (lbm_batch_*): requests are
 queued, admitted by an HBM budget as slots and memory free up, and advanced
-together by ragged-batch kernel launches (one per lattice step of a lane's
-run set) on the engine's concurrent lanes.  `serve` replays
+together by the ragged-batch kernel on the engine's concurrent lanes: one
+launch per lattice step, or, for run sets of up to `persistent_tiles` tiles,
+one persistent launch per quantum (off by default: slower on MI355X).  `serve` replays
 an arrival trace against it in wall-clock time; `serve_back_to_back` replays
 the same trace with one plain solve at a time (lbm_forward_solve,
 lbm_adjoint_solve, lbm_sensitivity), which is the comparison the serving
@@ -22,10 +23,11 @@ from . import lbm
 class BatchEngine:
     def __init__(self, thermal: bool, objective: int, budget_bytes: int, max_slots: int = 256,
                  quantum: int = 250, device="cuda:0", policy: int = lbm.LBM_BATCH_POLICY_OVERLAP,
-                 fill_tiles: int = 512):
+                 fill_tiles: int = 512, persistent_tiles: int = 0):
         self.device = torch.device(device)
         self.h = lbm.lbm_batch_create(thermal, objective, max_slots, quantum)
         lbm.lbm_batch_set_policy(self.h, policy, fill_tiles)
+        lbm.lbm_batch_set_persistent(self.h, persistent_tiles)
         self.quantum = quantum
         with torch.cuda.device(self.device):
             total = int(budget_bytes) + lbm.lbm_batch_table_bytes(self.h, int(budget_bytes)) + 512

@@ -66,10 +66,15 @@ def _drain(eng, tickets, reqs, limit=1000):
     return results
 
 
-def test_batch_results_equal_single_solves():
+@pytest.mark.parametrize("persistent_tiles", [1024, 0], ids=["persistent", "per_step"])
+def test_batch_results_equal_single_solves(persistent_tiles):
+    """Each quantum as one persistent launch (its blocks step the run set with
+    a device-wide barrier between steps) or as one launch per step: either
+    way every result is the single solve's, bit for bit."""
     reqs = small_requests()
     refs = [alone(w) for w in reqs]
-    eng = serving.BatchEngine(True, W.OBJ_HEATSINK, budget_bytes=2 << 30, max_slots=8, quantum=Q)
+    eng = serving.BatchEngine(True, W.OBJ_HEATSINK, budget_bytes=2 << 30, max_slots=8, quantum=Q,
+                              persistent_tiles=persistent_tiles)
     tickets = {eng.submit(reqs[0]): 0, eng.submit(reqs[1]): 1}
     eng.step()
     eng.step()

@@ -86,7 +86,7 @@ def parse():
                     help="skip timing the forward step's traffic without its arithmetic")
     ap.add_argument("--no-kernel-timing", action="store_true",
                     help="do not bracket the sweeps with HIP events")
-    ap.add_argument("--serving-requests", type=int, default=64,
+    ap.add_argument("--serving-requests", type=int, default=256,
                     help="requests of the serving stream replayed batched and back to back "
                          "(0: skip the serving leg; the full stream is 256)")
     ap.add_argument("--serving-rate", type=float, default=0.0,
@@ -112,6 +112,8 @@ def parse():
                     help="comma-separated Reynolds numbers of the accuracy study")
     ap.add_argument("--accuracy-cells", type=int, default=8,
                     help="design cells checked by central differences per Reynolds number")
+    ap.add_argument("--accuracy-dim", type=int, default=2, choices=[2, 3],
+                    help="pipe bend of the accuracy study: 2D on 64^2 or 3D on 32^3")
     ap.add_argument("--optimize", type=int, default=0,
                     help="run this many level-set optimisation iterations on --workload "
                          "(Sec. 2.2) and print their JSON object")
@@ -406,12 +408,24 @@ def stability_leg(steps, dim=3):
             "seconds": round(el, 1), "points": pts}
 
 
-def accuracy_leg(res, ncells, h=1e-2, settle=10000):
+def accuracy_case(dim, Re):
+    """The pipe bend of the accuracy study: 2D on 64^2 (the small
+    configuration) or 3D on 32^3 (port 5, pressure drop, tau 0.6)."""
+    import workloads as W
+    if dim == 2:
+        return W.pipe_bend_2d(Re=Re).replace(max_steps=400000, tol=1e-9, check_every=1000)
+    w = W.pipe_bend_3d(n=32, tau=0.6, Re=Re, sigma=32 / 24.0, port=5,
+                       objective=W.OBJ_PRESSURE_DROP)
+    return w.replace(max_steps=400000, tol=1e-9, check_every=1000)
+
+
+def accuracy_leg(res, ncells, h=1e-2, settle=10000, dim=2):
     """Sensitivity accuracy of the discrete and the continuous adjoint
-    (Sec. 3.1): on the 2D pipe bend 64^2 at each Reynolds number, both
-    adjoint dJ/dgamma fields against central differences of converged GPU
-    forward solves at the design cells of largest discrete |dJ/dgamma| and at
-    seeded random ones (central differences with steps h and h/2, combined by
+    (Sec. 3.1; Figs. 7 and 13 compare them with finite differences): on the
+    pipe bend (2D 64^2 or 3D 32^3) at each Reynolds number, both adjoint
+    dJ/dgamma fields against central differences of converged GPU forward
+    solves at the design cells of largest discrete |dJ/dgamma| and at seeded
+    random ones (central differences with steps h and h/2, combined by
     Richardson extrapolation), plus the continuous field's scale and
     direction against the discrete one."""
     import numpy as np
@@ -423,7 +437,7 @@ def accuracy_leg(res, ncells, h=1e-2, settle=10000):
     rows = []
     t0 = time.perf_counter()
     for Re in res:
-        w = W.pipe_bend_2d(Re=Re).replace(max_steps=400000, tol=1e-9, check_every=1000)
+        w = accuracy_case(dim, Re)
         design = np.flatnonzero((w.mask.reshape(-1) & 7) == W.DESIGN)
         pd = lbm.Problem(w, device="cuda:0")
         rd = pd.solve(w.gamma)
@@ -481,8 +495,10 @@ def accuracy_leg(res, ncells, h=1e-2, settle=10000):
         print(f"[accuracy] {json.dumps({k: v for k, v in row.items() if k not in ('fd', 'disc', 'cont', 'cells')})}",
               file=sys.stderr, flush=True)
         rows.append(row)
-    return {"workload": "pipe_bend_2d_64x64 (D2Q9, tau 0.6, inlet rows 8-23, outlet columns "
-                        "40-55, pressure drop)", "h": h, "tol": 1e-9, "settle_steps": settle,
+    wl = ("pipe_bend_2d_64x64 (D2Q9, tau 0.6, inlet rows 8-23, outlet columns 40-55, "
+          "pressure drop)") if dim == 2 else \
+        "pipe_bend_3d_32^3 (D3Q19, tau 0.6, port 5, pressure drop)"
+    return {"workload": wl, "h": h, "tol": 1e-9, "settle_steps": settle,
             "seconds": round(time.perf_counter() - t0, 1), "rows": rows}
 
 
@@ -531,7 +547,8 @@ def main():
         return
     if args.accuracy:
         res = [float(v) for v in args.accuracy_re.split(",") if v]
-        print(json.dumps({"accuracy": accuracy_leg(res, args.accuracy_cells)}), flush=True)
+        print(json.dumps({"accuracy": accuracy_leg(res, args.accuracy_cells,
+                                                   dim=args.accuracy_dim)}), flush=True)
         return
     if args.optimize > 0:
         print(json.dumps({"optimize": optimize_leg(args)}), flush=True)

@@ -1,0 +1,123 @@
+"""Writes the stored FP64 reference solutions of the full-size configurations.
+
+For each configuration the FP64 oracle (oracle/) solves the forward problem
+and the discrete adjoint from rest to a residual far below the GPU's own
+criterion, then takes the sensitivity; the script stores the converged
+density deviation, velocity, temperature and dJ/dgamma over every node
+(float32: the 1e-5 and 1e-4 tolerances they are checked against are far
+above that rounding), J, the step counts and residuals, and what identifies
+the inputs (the workload's name, grid, parameters and seed, and a digest of
+its mask and design field).  With --fd it also stores central differences
+of J (h = 1e-4) at seeded design cells: each from two forward solves warm
+started at the converged state with the cell's design value moved by +-h,
+run the same fixed number of steps (the base state's residue cancels in the
+difference).
+
+Only the oracle and the workload generators are used here.  Run from the
+repository root:
+
+    python tests/golden/make_converged_fixtures.py heat_sink_160x80x40_Re200
+    python tests/golden/make_converged_fixtures.py heat_sink_128x64x32_Re200 --fd 32
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+import workloads as W  # noqa: E402
+
+CONFIGS = {
+    "heat_sink_160x80x40_Re200": lambda: W.heat_sink(Re=200.0),
+    "heat_sink_128x64x32_Re200": W.differentiable_case,
+}
+TOL = 1e-10          # relative change of the monitors over 1000 steps
+MAX_STEPS = 400000
+FD_H = 1e-4
+
+
+def digest(w) -> str:
+    h = hashlib.sha256()
+    h.update(np.ascontiguousarray(w.mask, dtype=np.uint8).tobytes())
+    h.update(np.ascontiguousarray(w.gamma, dtype=np.float64).tobytes())
+    return h.hexdigest()
+
+
+def fixture_path(name: str) -> str:
+    return os.path.join(HERE, f"converged_{name}.npz")
+
+
+def fd_cells(w, n: int) -> np.ndarray:
+    design = np.flatnonzero((w.mask.reshape(-1) & 7) == W.DESIGN)
+    rng = np.random.default_rng(W.SEED_BASE + 32)
+    return np.sort(rng.choice(design, size=n, replace=False))
+
+
+def log(msg):
+    print(f"[fixture] {msg}", flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("config", choices=sorted(CONFIGS))
+    ap.add_argument("--fd", type=int, default=0, help="design cells checked by central differences")
+    ap.add_argument("--fd-steps", type=int, default=0,
+                    help="steps of each warm-started difference solve (0: twice the forward's)")
+    args = ap.parse_args()
+    w = CONFIGS[args.config]()
+    o = oracle.Oracle(w)
+    t0 = time.time()
+    fw = o.forward(max_steps=MAX_STEPS, tol=TOL, check_every=1000)
+    log(f"{args.config}: forward {fw['steps']} steps, status {fw['status']}, residuals {fw['res']}, "
+        f"{time.time() - t0:.0f} s")
+    assert fw["status"] == 0, "forward did not converge"
+    f, g = fw["f"], fw["g"]
+    rho, u, T = o.macro(f, g)
+    J = o.objective(f, g)
+    t1 = time.time()
+    ad = o.adjoint(f, g, max_steps=MAX_STEPS, tol=TOL, check_every=1000)
+    log(f"adjoint {ad['steps']} steps, status {ad['status']}, residuals {ad['res']}, "
+        f"{time.time() - t1:.0f} s")
+    assert ad["status"] == 0, "adjoint did not converge"
+    dJ = o.sensitivity(f, g, ad["fsC"], ad["gsC"])
+    out = dict(drho=(rho - w.rho0).astype(np.float32), u=u.T.astype(np.float32).copy(),
+               T=(T if T is not None else np.zeros(0)).astype(np.float32),
+               dJ=dJ.astype(np.float32), J=np.float64(J),
+               fwd_steps=np.int64(fw["steps"]), adj_steps=np.int64(ad["steps"]),
+               fwd_res=np.asarray(fw["res"], dtype=np.float64),
+               adj_res=np.asarray(ad["res"], dtype=np.float64), tol=np.float64(TOL),
+               name=np.str_(w.name), grid=np.array([w.nx, w.ny, w.nz], dtype=np.int64),
+               tau=np.float64(w.tau), Re=np.float64(w.Re), seed=np.int64(w.seed),
+               inputs_sha256=np.str_(digest(w)))
+    if args.fd > 0:
+        cells = fd_cells(w, args.fd)
+        steps = args.fd_steps or 2 * fw["steps"]
+        vals = []
+        for i, k in enumerate(cells):
+            Jpm = []
+            for s in (+1.0, -1.0):
+                gm = o.gamma.copy()
+                gm[k] += s * FD_H
+                r = o.forward(gamma=gm, max_steps=steps, tol=0.0, check_every=0, state=(f, g))
+                Jpm.append(o.objective(r["f"], r["g"], gamma=gm))
+            vals.append((Jpm[0] - Jpm[1]) / (2.0 * FD_H))
+            log(f"fd cell {i + 1}/{len(cells)} node {k}: {vals[-1]:.9e} (adjoint {dJ[k]:.9e}), "
+                f"{time.time() - t0:.0f} s")
+        out.update(fd_cells=cells.astype(np.int64), fd=np.asarray(vals, dtype=np.float64),
+                   fd_h=np.float64(FD_H), fd_steps=np.int64(steps))
+    np.savez_compressed(fixture_path(args.config), **out)
+    log(f"wrote {fixture_path(args.config)} ({os.path.getsize(fixture_path(args.config)) / 1e6:.1f} MB), "
+        f"J {J:.12g}, {time.time() - t0:.0f} s")
+
+
+if __name__ == "__main__":
+    main()

@@ -144,6 +144,8 @@ def profile_run(args):
     dst = torch.empty_like(src)
     for _ in range(2):
         dst.copy_(src)
+    # and the library's own 16-byte copy kernel (3 untimed + 2 timed launches)
+    lbm.lbm_copy_probe(src, dst, 2)
     torch.cuda.synchronize()
     w = make_workload(args.workload, args.adjoint, args.re).replace(max_steps=args.fixed_steps, tol=0.0,
                                              check_every=1000)

@@ -185,10 +185,10 @@ def test_thermal_2d_fixed_steps_parity():
 def test_thermal_2d_converged_parity_and_half_equals_full():
     """Both sides step 20000 times (the FP64 residual reaches 1e-8 after
     about 8000): the converged states, without the spread that stopping at
-    different FP32 / FP64 residual checks would add.  A converged FP32 state
-    carries its per-step rounding amplified by the slowest mode of the
-    coupled iteration: 8.8e-6 in T on this 24 x 9 half channel, 1.1-2.0e-5
-    on 40 x 12 variants (after 600 steps the same fields agree to 1.2e-7)."""
+    different FP32 / FP64 residual checks would add.  With the thermal
+    populations stored against a per-node reference temperature the
+    converged T agrees to about 4e-7 on this 24 x 9 half channel (after 600
+    steps the same fields agree to 1.2e-7)."""
     w = W.paper_heat_sink_2d(24, 9, Re=10.0, tau=0.8, Pr=1.0, beta_max=2e-3, alpha_max=0.2,
                              buffer=2, sigma=1.5, seed=31).replace(max_steps=20000, tol=0.0,
                                                                    check_every=1000)

@@ -20,22 +20,30 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lbm_oracle.cpp")
-_LIB_PATH = os.path.join(_HERE, "_build", "liborc.so")
+SAN_LIB_PATH = os.path.join(_HERE, "_build", "liborc_san.so")
+# ORACLE_LIB selects another build of the oracle (the sanitized one)
+_LIB_PATH = os.environ.get("ORACLE_LIB") or os.path.join(_HERE, "_build", "liborc.so")
 _lib = None
 _lock = threading.Lock()
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with g++ (FP64, OpenMP).  Returns the library path."""
-    os.makedirs(os.path.dirname(_LIB_PATH), exist_ok=True)
-    if force or not os.path.exists(_LIB_PATH) or \
-            os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
-        tmp = _LIB_PATH + f".tmp{os.getpid()}"
-        cmd = ["g++", "-std=c++17", "-O2", "-fopenmp", "-fPIC", "-shared", "-Wall",
-               "-Wno-unknown-pragmas", "-o", tmp, _SRC]
+def build(force: bool = True, sanitize: bool = False) -> str:
+    """Compile the oracle with g++ (FP64, OpenMP).  Returns the library path.
+
+    sanitize=True builds SAN_LIB_PATH with AddressSanitizer and
+    UndefinedBehaviorSanitizer instead (load it with gcc's libasan preloaded
+    and ORACLE_LIB pointing at it)."""
+    path = SAN_LIB_PATH if sanitize else os.path.join(_HERE, "_build", "liborc.so")
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    if force or not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
+        tmp = path + f".tmp{os.getpid()}"
+        opt = (["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                "-fno-sanitize-recover=undefined"] if sanitize else ["-O2"])
+        cmd = ["g++", "-std=c++17"] + opt + ["-fopenmp", "-fPIC", "-shared", "-Wall",
+                                             "-Wno-unknown-pragmas", "-o", tmp, _SRC]
         subprocess.run(cmd, check=True)
-        os.replace(tmp, _LIB_PATH)
-    return _LIB_PATH
+        os.replace(tmp, path)
+    return path
 
 
 class OrcConfig(ctypes.Structure):
@@ -56,8 +64,9 @@ def _load():
     with _lock:
         if _lib is not None:
             return _lib
-        if not os.path.exists(_LIB_PATH) or \
-                os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        if "ORACLE_LIB" not in os.environ and (
+                not os.path.exists(_LIB_PATH) or
+                os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC)):
             build(force=True)
         lib = ctypes.CDLL(_LIB_PATH)
         P = ctypes.c_void_p

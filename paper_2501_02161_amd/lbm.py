@@ -16,7 +16,9 @@ from ctypes import POINTER, byref, c_char_p, c_double, c_int, c_int32, c_size_t,
 
 import torch
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_build", "liblbmadj.so")
+# LBMADJ_LIB selects another build of the library (the host-sanitized one)
+LIB_PATH = os.environ.get("LBMADJ_LIB") or os.path.join(
+    os.path.dirname(os.path.abspath(__file__)), "_build", "liblbmadj.so")
 
 LBM_OK, LBM_NOT_CONVERGED = 0, 1
 LBM_ADJOINT_DISCRETE, LBM_ADJOINT_CONTINUOUS = 0, 1

@@ -182,6 +182,22 @@ def test_thermal_2d_fixed_steps_parity():
     print(f"[d2q5] errors {err} J {res['J']:.9g} vs {ref['J']:.9g}", flush=True)
 
 
+def test_thermal_2d_converged_parity_40x12():
+    """The 40 x 12 heat sink (two tiles, the last ragged) whose nearly
+    uniform solid temperature let FP32 rounding of the slow thermal modes
+    stall the iteration short of the fixed point when the thermal populations
+    were stored against T_in alone.  Both sides step 20000 times (the FP64
+    residual reaches 1e-10 after 12000)."""
+    w = small_heat_sink_2d().replace(max_steps=20000, tol=0.0, check_every=1000)
+    print(f"[d2q5] converged {w.nx}x{w.ny}", flush=True)
+    prob, res = run_gpu(w)
+    o, ref = run_oracle(w, steps=20000, tol=0.0, check_every=1000)
+    err = compare_solution(w, prob, ref)
+    print(f"[d2q5] converged {w.nx}x{w.ny} errors {err} J {res['J']:.9g} vs {ref['J']:.9g}",
+          flush=True)
+    assert math.isclose(res["J"], ref["J"], rel_tol=1e-5)
+
+
 def test_thermal_2d_converged_parity_and_half_equals_full():
     """Both sides step 20000 times (the FP64 residual reaches 1e-8 after
     about 8000): the converged states, without the spread that stopping at

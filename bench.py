@@ -578,16 +578,32 @@ def main():
         J = prob.sensitivity(stream=stream)
         return fi, ai, J
 
-    for _ in range(args.warmup):
-        one()
-    torch.cuda.synchronize()
-    lbm.lbm_set_kernel_timing(prob.h, not args.no_kernel_timing)
-    lbm.lbm_kernel_timing(prob.h, reset=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    infos = [one() for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    try:
+        for _ in range(args.warmup):
+            one()
+        torch.cuda.synchronize()
+        lbm.lbm_set_kernel_timing(prob.h, not args.no_kernel_timing)
+        lbm.lbm_kernel_timing(prob.h, reset=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        infos = [one() for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+    except lbm.LBMError as e:
+        if e.code != lbm.LBM_EDIVERGED:
+            raise
+        # no steady state to differentiate about: the line says so and
+        # carries no rate
+        torch.cuda.synchronize()
+        prob.close()
+        print(json.dumps({
+            "metric": METRIC, "value": None, "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": None, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": w.name, "nodes": w.N, "tau": round(w.tau, 6), "Re": w.Re,
+                       "tol": w.tol, "max_steps": w.max_steps, "fwd_status": "diverged",
+                       "error": str(e)}}), flush=True)
+        return
     (ms_f, ms_a), (n_f, n_a) = lbm.lbm_kernel_timing(prob.h, reset=True)
     lbm.lbm_set_kernel_timing(prob.h, False)
     elapsed = t1 - t0

@@ -17,7 +17,13 @@ Only the oracle and the workload generators are used here.  Run from the
 repository root:
 
     python tests/golden/make_converged_fixtures.py heat_sink_160x80x40_Re200
-    python tests/golden/make_converged_fixtures.py heat_sink_128x64x32_Re200 --fd 32
+    python tests/golden/make_converged_fixtures.py heat_sink_128x64x32_Re200
+    python tests/golden/make_converged_fixtures.py heat_sink_128x64x32_Re200 --fd 32 \
+        --fd-steps 5000 --fd-only
+
+The differences settle within about 4000 steps of the warm start; beyond
+that the two FP64 iterations only exchange rounding noise (a few 1e-15 in
+J), which is what limits the differences' own accuracy at h = 1e-4.
 """
 from __future__ import annotations
 
@@ -72,6 +78,9 @@ def main():
     ap.add_argument("--fd", type=int, default=0, help="design cells checked by central differences")
     ap.add_argument("--fd-steps", type=int, default=0,
                     help="steps of each warm-started difference solve (0: twice the forward's)")
+    ap.add_argument("--fd-only", action="store_true",
+                    help="add the differences to the stored fixture (the forward is re-solved "
+                         "for the warm start, the adjoint is not)")
     args = ap.parse_args()
     w = CONFIGS[args.config]()
     o = oracle.Oracle(w)
@@ -81,23 +90,31 @@ def main():
         f"{time.time() - t0:.0f} s")
     assert fw["status"] == 0, "forward did not converge"
     f, g = fw["f"], fw["g"]
-    rho, u, T = o.macro(f, g)
     J = o.objective(f, g)
-    t1 = time.time()
-    ad = o.adjoint(f, g, max_steps=MAX_STEPS, tol=TOL, check_every=1000)
-    log(f"adjoint {ad['steps']} steps, status {ad['status']}, residuals {ad['res']}, "
-        f"{time.time() - t1:.0f} s")
-    assert ad["status"] == 0, "adjoint did not converge"
-    dJ = o.sensitivity(f, g, ad["fsC"], ad["gsC"])
-    out = dict(drho=(rho - w.rho0).astype(np.float32), u=u.T.astype(np.float32).copy(),
-               T=(T if T is not None else np.zeros(0)).astype(np.float32),
-               dJ=dJ.astype(np.float32), J=np.float64(J),
-               fwd_steps=np.int64(fw["steps"]), adj_steps=np.int64(ad["steps"]),
-               fwd_res=np.asarray(fw["res"], dtype=np.float64),
-               adj_res=np.asarray(ad["res"], dtype=np.float64), tol=np.float64(TOL),
-               name=np.str_(w.name), grid=np.array([w.nx, w.ny, w.nz], dtype=np.int64),
-               tau=np.float64(w.tau), Re=np.float64(w.Re), seed=np.int64(w.seed),
-               inputs_sha256=np.str_(digest(w)))
+    if args.fd_only:
+        ref = np.load(fixture_path(args.config))
+        assert str(ref["inputs_sha256"]) == digest(w), "stored fixture is for other inputs"
+        assert int(ref["fwd_steps"]) == fw["steps"] and float(ref["J"]) == J, \
+            "re-solved forward differs from the stored one"
+        out = {k: ref[k] for k in ref.files if not k.startswith("fd")}
+        dJ = ref["dJ"].astype(np.float64)
+    else:
+        rho, u, T = o.macro(f, g)
+        t1 = time.time()
+        ad = o.adjoint(f, g, max_steps=MAX_STEPS, tol=TOL, check_every=1000)
+        log(f"adjoint {ad['steps']} steps, status {ad['status']}, residuals {ad['res']}, "
+            f"{time.time() - t1:.0f} s")
+        assert ad["status"] == 0, "adjoint did not converge"
+        dJ = o.sensitivity(f, g, ad["fsC"], ad["gsC"])
+        out = dict(drho=(rho - w.rho0).astype(np.float32), u=u.T.astype(np.float32).copy(),
+                   T=(T if T is not None else np.zeros(0)).astype(np.float32),
+                   dJ=dJ.astype(np.float32), J=np.float64(J),
+                   fwd_steps=np.int64(fw["steps"]), adj_steps=np.int64(ad["steps"]),
+                   fwd_res=np.asarray(fw["res"], dtype=np.float64),
+                   adj_res=np.asarray(ad["res"], dtype=np.float64), tol=np.float64(TOL),
+                   name=np.str_(w.name), grid=np.array([w.nx, w.ny, w.nz], dtype=np.int64),
+                   tau=np.float64(w.tau), Re=np.float64(w.Re), seed=np.int64(w.seed),
+                   inputs_sha256=np.str_(digest(w)))
     if args.fd > 0:
         cells = fd_cells(w, args.fd)
         steps = args.fd_steps or 2 * fw["steps"]

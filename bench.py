@@ -86,9 +86,10 @@ def parse():
                     help="skip timing the forward step's traffic without its arithmetic")
     ap.add_argument("--no-kernel-timing", action="store_true",
                     help="do not bracket the sweeps with HIP events")
-    ap.add_argument("--serving-requests", type=int, default=256,
+    ap.add_argument("--serving-requests", type=int, default=128,
                     help="requests of the serving stream replayed batched and back to back "
-                         "(0: skip the serving leg; the full stream is 256)")
+                         "(0: skip the serving leg; the full stream is 256, about 3 minutes "
+                         "per mode, so the default replays its first 128)")
     ap.add_argument("--serving-rate", type=float, default=0.0,
                     help="Poisson arrival rate in requests/s (0: the stream's default)")
     ap.add_argument("--serving-policy", default="overlap", choices=["overlap", "srw", "all"],

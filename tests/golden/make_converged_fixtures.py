@@ -19,11 +19,13 @@ repository root:
     python tests/golden/make_converged_fixtures.py heat_sink_160x80x40_Re200
     python tests/golden/make_converged_fixtures.py heat_sink_128x64x32_Re200
     python tests/golden/make_converged_fixtures.py heat_sink_128x64x32_Re200 --fd 32 \
-        --fd-steps 5000 --fd-only
+        --fd-steps 12000 --fd-only
 
-The differences settle within about 4000 steps of the warm start; beyond
-that the two FP64 iterations only exchange rounding noise (a few 1e-15 in
-J), which is what limits the differences' own accuracy at h = 1e-4.
+The warm-started solves of some cells excite the slow thermal modes and
+need about 10000 steps to settle; once settled, the two FP64 iterations only
+exchange rounding noise (a few 1e-15 in J), which limits the differences'
+own accuracy at h = 1e-4.  The value at half the steps is stored beside the
+final one (fd_half).
 """
 from __future__ import annotations
 
@@ -118,18 +120,25 @@ def main():
     if args.fd > 0:
         cells = fd_cells(w, args.fd)
         steps = args.fd_steps or 2 * fw["steps"]
-        vals = []
+        vals, half = [], []
         for i, k in enumerate(cells):
-            Jpm = []
+            Jpm, Jh = [], []
             for s in (+1.0, -1.0):
                 gm = o.gamma.copy()
                 gm[k] += s * FD_H
-                r = o.forward(gamma=gm, max_steps=steps, tol=0.0, check_every=0, state=(f, g))
+                # in two halves: the difference at half the steps shows how
+                # far the warm-started solves still were from settling
+                r = o.forward(gamma=gm, max_steps=steps // 2, tol=0.0, check_every=0, state=(f, g))
+                Jh.append(o.objective(r["f"], r["g"], gamma=gm))
+                r = o.forward(gamma=gm, max_steps=steps - steps // 2, tol=0.0, check_every=0,
+                              state=(r["f"], r["g"]))
                 Jpm.append(o.objective(r["f"], r["g"], gamma=gm))
             vals.append((Jpm[0] - Jpm[1]) / (2.0 * FD_H))
-            log(f"fd cell {i + 1}/{len(cells)} node {k}: {vals[-1]:.9e} (adjoint {dJ[k]:.9e}), "
-                f"{time.time() - t0:.0f} s")
+            half.append((Jh[0] - Jh[1]) / (2.0 * FD_H))
+            log(f"fd cell {i + 1}/{len(cells)} node {k}: {vals[-1]:.9e} (at half the steps "
+                f"{half[-1]:.9e}; adjoint {dJ[k]:.9e}), {time.time() - t0:.0f} s")
         out.update(fd_cells=cells.astype(np.int64), fd=np.asarray(vals, dtype=np.float64),
+                   fd_half=np.asarray(half, dtype=np.float64),
                    fd_h=np.float64(FD_H), fd_steps=np.int64(steps))
     np.savez_compressed(fixture_path(args.config), **out)
     log(f"wrote {fixture_path(args.config)} ({os.path.getsize(fixture_path(args.config)) / 1e6:.1f} MB), "

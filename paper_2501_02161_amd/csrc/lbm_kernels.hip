@@ -240,20 +240,53 @@ __device__ __forceinline__ bool ref_is_node(float R) { return R <= 3.0e38f; }
 // Forward thermal pull in the per-node reference form: the value of slot I
 // pulled from its source node, moved into node n's shift by
 // w_I (R(source) - R(n)) unless the source or node n is a wall (walls hold
-// their values in the shift of the node that reads them).
+// their values in the shift of the node that reads them).  Split in two so
+// that a caller issues the loads of every direction before it uses any
+// (one memory round trip for the whole pull): RefPull holds what one
+// direction read, ref_pull_value moves it into node n's shift.
+struct RefPull {
+  float r, Rs;
+  bool valid;
+};
 template <class G, int I, int DX, int DY, int DZ>
-__device__ __forceinline__ float load_pull_ref(const float* __restrict__ base,
-                                               const float* __restrict__ R, size_t Np, const Nbr& b,
-                                               int n, const Mirror& m, float Rn, bool wall_here) {
+__device__ __forceinline__ RefPull load_ref_pull(const float* __restrict__ base,
+                                                 const float* __restrict__ R, size_t Np,
+                                                 const Nbr& b, int n, const Mirror& m) {
   if constexpr (DX == 0 && DY == 0 && DZ == 0) {
-    return base[(size_t)I * Np + n];
+    return RefPull{base[(size_t)I * Np + n], 0.0f, true};
   } else {
     const Src sr = pull_src<G, I, DX, DY, DZ>(b, n, m);
-    const float r = base[(size_t)sr.slot * Np + sr.node];
-    const float Rs = R[sr.node];
-    const bool shift = sr.valid && !wall_here && ref_is_node(Rs);
-    return sr.valid ? (shift ? r + G::w[I] * (Rs - Rn) : r) : 0.0f;
+    return RefPull{base[(size_t)sr.slot * Np + sr.node], R[sr.node], sr.valid};
   }
+}
+template <class G, int I>
+__device__ __forceinline__ float ref_pull_value(const RefPull& p, float Rn, bool wall_here) {
+  if constexpr (G::ex[I] == 0 && G::ey[I] == 0 && G::ez[I] == 0) {
+    return p.r;
+  } else {
+    const bool shift = p.valid && !wall_here && ref_is_node(p.Rs);
+    return p.valid ? (shift ? p.r + G::w[I] * (p.Rs - Rn) : p.r) : 0.0f;
+  }
+}
+// All Q thermal pulls of node n in that form: loads first, then the shifts.
+// Direction own_dir (an outlet's inward normal, else -1) keeps the raw value
+// read: its source lies outside the box (a port's normal is the inward
+// normal of a non-periodic face), so the read fell back to node n's own
+// slot, which is what the zero-gradient outflow rule takes.
+template <class G>
+__device__ __forceinline__ void load_pull_ref_all(float (&k)[G::Q], const float* __restrict__ base,
+                                                  const float* __restrict__ R, size_t Np,
+                                                  const Nbr& b, int n, const Mirror& m, float Rn,
+                                                  bool wall_here, int own_dir) {
+  RefPull pr[G::Q];
+  sfor<G::Q>([&](auto I) {
+    constexpr int i = I;
+    pr[i] = load_ref_pull<G, i, -G::ex[i], -G::ey[i], -G::ez[i]>(base, R, Np, b, n, m);
+  });
+  sfor<G::Q>([&](auto I) {
+    constexpr int i = I;
+    k[i] = (i == own_dir) ? pr[i].r : ref_pull_value<G, i>(pr[i], Rn, wall_here);
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -438,8 +471,11 @@ __device__ __forceinline__ void forward_tile(const FwdArgs& A, int blk) {
     const Mirror mr = MIR ? mirror_of(x, y, z, P) : Mirror{false, false, false};
     const unsigned fl = A.flags[n];
     const int kind = fl & 7, nc = (fl >> 3) & 7;
-    float gam_n = 1.0f;
-    if constexpr (EARLY) gam_n = A.gamma[n];
+    float gam_n = 1.0f, uin_n = 0.0f;
+    if constexpr (EARLY) {
+      gam_n = A.gamma[n];
+      uin_n = A.uin[n];
+    }
     float h[L::Q];
     sfor<L::Q>([&](auto I) {
       constexpr int i = I;
@@ -449,20 +485,16 @@ __device__ __forceinline__ void forward_tile(const FwdArgs& A, int blk) {
     float Rn = 0.0f;  // the node's reference temperature (thermal shift)
     if constexpr (THERMAL) {
       Rn = A.Rin[n];
-      const bool wall_here = kind >= K_WALL;
-      sfor<G::Q>([&](auto I) {
-        constexpr int i = I;
-        k[i] = load_pull_ref<G, i, -G::ex[i], -G::ey[i], -G::ez[i]>(A.gin, A.Rin, P.Np, nb, n, mr,
-                                                                     Rn, wall_here);
-      });
       // zero-gradient outflow: the population along the inward normal takes
       // the node's own post-collision value
-      if (kind == K_OUTLET) {
-        const int d = nc + 1;
-        const float own = A.gin[(size_t)d * P.Np + n];
-        sfor<G::Q>([&](auto I) { k[I] = (I == d) ? own : k[I]; });
-      }
+      load_pull_ref_all<G>(k, A.gin, A.Rin, P.Np, nb, n, mr, Rn, kind >= K_WALL,
+                           kind == K_OUTLET ? nc + 1 : -1);
     }
+    // the early per-node values are consumed here, ahead of the branches on
+    // the node kind, so that the compiler cannot sink their loads into those
+    // branches (a second memory round trip); the empty asm only needs them in
+    // registers
+    if constexpr (EARLY) asm volatile("" ::"v"(gam_n), "v"(uin_n));
     // post-step populations, stored once after both branches: a wave that
     // holds wall and fluid nodes then writes each cache line with one store
     // instead of two partial ones
@@ -499,7 +531,7 @@ __device__ __forceinline__ void forward_tile(const FwdArgs& A, int blk) {
     } else {
       if (kind == K_INLET || kind == K_OUTLET) {
         const bool vin = kind == K_INLET && !P.pin;   // velocity inlet
-        const float jn = vin ? A.uin[n] * P.rho0 : 0.f;
+        const float jn = vin ? (EARLY ? uin_n : A.uin[n]) * P.rho0 : 0.f;
         const float drho_b = (kind == K_INLET) ? P.drho_in : 0.0f;
         with_normal<L>(nc, [&](Normal nv) { zou_he<L>(h, nv, vin, jn, drho_b); });
       }
@@ -575,9 +607,18 @@ __device__ __forceinline__ void forward_tile(const FwdArgs& A, int blk) {
   if constexpr (DIAG) block_reduce_store<kRedFwd>(acc, A.partials + (size_t)blk * kRedFwd);
 }
 
-template <class L, bool MIR, bool THERMAL, bool DIAG, bool EARLY = false>
+template <class L, bool MIR, bool THERMAL, bool DIAG>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_forward(FwdArgs A) {
-  forward_tile<L, MIR, THERMAL, DIAG, EARLY>(A, remap_block(blockIdx.x, A.P));
+  forward_tile<L, MIR, THERMAL, DIAG, false>(A, remap_block(blockIdx.x, A.P));
+}
+
+// The coupled step on lattices too small to fill the device (the early
+// per-node loads): no occupancy target, so the compiler keeps every load of
+// the step in flight at once instead of trading registers for waves such a
+// lattice does not have.
+template <class L, bool MIR>
+__global__ __launch_bounds__(kBlock) void k_forward_early(FwdArgs A) {
+  forward_tile<L, MIR, true, false, true>(A, remap_block(blockIdx.x, A.P));
 }
 
 // ---------------------------------------------------------------------------
@@ -1061,16 +1102,9 @@ __global__ __launch_bounds__(kBlock) void k_thermal(ThermArgs A) {
     const int kind = fl & 7, nc = (fl >> 3) & 7;
     float k[G::Q];
     const float Rn = A.R[n];
-    sfor<G::Q>([&](auto I) {
-      constexpr int i = I;
-      k[i] = load_pull_ref<G, i, -G::ex[i], -G::ey[i], -G::ez[i]>(A.gin, A.R, P.Np, nb, n, mr, Rn,
-                                                                   kind >= K_WALL);
-    });
     const int d = nc + 1;
-    if (kind == K_OUTLET) {
-      const float own = A.gin[(size_t)d * P.Np + n];
-      sfor<G::Q>([&](auto I) { k[I] = (I == d) ? own : k[I]; });
-    }
+    load_pull_ref_all<G>(k, A.gin, A.R, P.Np, nb, n, mr, Rn, kind >= K_WALL,
+                         kind == K_OUTLET ? d : -1);
     float ko[G::Q];  // stored once after both branches
     if (kind >= K_WALL) {
       sfor<G::Q>([&](auto I) { ko[I] = k[G::opp[I]]; });
@@ -1674,11 +1708,7 @@ __global__ __launch_bounds__(kBlock) void k_stream_probe(FwdArgs A) {
   if constexpr (THERMAL) {
     // the reference temperatures are read where the step reads them
     const float Rn = A.Rin[n];
-    sfor<G::Q>([&](auto I) {
-      constexpr int i = I;
-      k[i] = load_pull_ref<G, i, -G::ex[i], -G::ey[i], -G::ez[i]>(A.gin, A.Rin, P.Np, nb, n, mr, Rn,
-                                                                   never);
-    });
+    load_pull_ref_all<G>(k, A.gin, A.Rin, P.Np, nb, n, mr, Rn, never, -1);
   }
   sfor<L::Q>([&](auto I) { A.fout[(size_t)I * P.Np + n] = never ? gv : h[I]; });
   if constexpr (THERMAL) sfor<G::Q>([&](auto I) { A.gout[(size_t)I * P.Np + n] = never ? gv : k[I]; });
@@ -1686,14 +1716,19 @@ __global__ __launch_bounds__(kBlock) void k_stream_probe(FwdArgs A) {
 
 template <class L, bool TH>
 static void fwd_dispatch(const FwdArgs& a, bool diag, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+  const bool early = TH && a.P.nblk < kEarlyBlocks;
   if ((a.P.sx | a.P.sy | a.P.sz) != 0) {
     if (diag) launch_step(k_forward<L, true, TH, true>, a.P.nblk, a, s, ev0, ev1);
-    else if (TH && a.P.nblk < kEarlyBlocks) launch_step(k_forward<L, true, TH, false, TH>, a.P.nblk, a, s, ev0, ev1);
-    else launch_step(k_forward<L, true, TH, false>, a.P.nblk, a, s, ev0, ev1);
+    else if constexpr (TH) {
+      if (early) launch_step(k_forward_early<L, true>, a.P.nblk, a, s, ev0, ev1);
+      else launch_step(k_forward<L, true, TH, false>, a.P.nblk, a, s, ev0, ev1);
+    } else launch_step(k_forward<L, true, TH, false>, a.P.nblk, a, s, ev0, ev1);
   } else {
     if (diag) launch_step(k_forward<L, false, TH, true>, a.P.nblk, a, s, ev0, ev1);
-    else if (TH && a.P.nblk < kEarlyBlocks) launch_step(k_forward<L, false, TH, false, TH>, a.P.nblk, a, s, ev0, ev1);
-    else launch_step(k_forward<L, false, TH, false>, a.P.nblk, a, s, ev0, ev1);
+    else if constexpr (TH) {
+      if (early) launch_step(k_forward_early<L, false>, a.P.nblk, a, s, ev0, ev1);
+      else launch_step(k_forward<L, false, TH, false>, a.P.nblk, a, s, ev0, ev1);
+    } else launch_step(k_forward<L, false, TH, false>, a.P.nblk, a, s, ev0, ev1);
   }
 }
 

@@ -423,8 +423,11 @@ typedef struct lbm_batch_stats {
 } lbm_batch_stats_t;
 
 /* Engine for requests with this thermal flag and objective; at most
- * max_slots resident requests; quantum = steps between admission and
- * residual checks.  LBM_EINVAL on bad parameters. */
+ * max_slots resident requests; quantum = steps a lane advances its run set
+ * between visits of the host (admission, residual checks).  Under OVERLAP a
+ * lone request too large for the latency lane runs on the bandwidth lane up
+ * to its next residual check, at most 4 quanta, per visit.  LBM_EINVAL on bad
+ * parameters. */
 int lbm_batch_create(int32_t thermal, int32_t objective, int32_t max_slots, int32_t quantum,
                      lbm_batch_t** out);
 /* Bytes of the arena taken by the engine's own tables for an arena of

@@ -66,6 +66,13 @@ constexpr int kLanes = 2;
 // a graph replay adds a few microseconds of dispatch per kernel, which only
 // pays for itself on kernels too short to hide a launch from the host.
 constexpr int kDirectTiles = 1024;
+// A lone request on the OVERLAP bandwidth lane that is too large for the
+// latency lane keeps the lane until it finishes (the lane takes the oldest
+// request), so its quanta run up to its next residual check, at most this
+// many quanta: every return to the host between quanta leaves the lane's
+// stream idle for the host's turnaround, which on a 10-30 us step costs
+// several per cent of a 250-step quantum.
+constexpr int kSoloQuanta = 4;
 
 struct Request {
   int64_t ticket;
@@ -164,6 +171,7 @@ struct Lane {
   std::vector<char> run;         // run set of the lane's current / next quantum
   std::vector<int64_t> up_ticket;  // ticket whose entry the device slot table holds
   bool busy = false;             // a quantum is in flight
+  int qsteps = 0;                // steps of the quantum in flight
   int launch = 0;
   long long nodes = 0;    // nodes advanced per launch
 };
@@ -589,7 +597,14 @@ int launch_solo(lbm_batch* b, int L, int i) {
   lbm_problem* p = s.p.get();
   const bool th = thermal_of(p);
   const int s0 = s.steps, cap = p->d.max_steps, chk = p->d.check_every;
-  const int n = std::min(b->quantum, cap - s0);
+  int n = std::min(b->quantum, cap - s0);
+  if (b->policy == LBM_BATCH_POLICY_OVERLAP && L == 1 && p->nblk > b->fill_tiles &&
+      p->nblk >= kDirectTiles) {
+    // up to the next residual check (the check period and the step cap are
+    // multiples of the quantum, so this is a whole number of quanta)
+    const int to_check = chk > 0 ? chk - s0 % chk : cap - s0;
+    n = std::min({to_check, cap - s0, kSoloQuanta * b->quantum});
+  }
   const int last = s0 + n;
   const bool diag = (chk > 0 && last % chk == 0) || last == cap;
   // reference buffer of the thermal state during this quantum: it flips at
@@ -617,7 +632,6 @@ int launch_solo(lbm_batch* b, int L, int i) {
     double* hs = ln.h_sums + (size_t)i * 4;
     double* ds = ln.d_sums + (size_t)i * 4;
     int* base = ln.d_base;
-    const int Q = b->quantum;
     post(ln.worker.get(), [=]() -> hipError_t {
       hipError_t e = hipSuccess;
       for (int q = 0; q < n && e == hipSuccess; ++q) {
@@ -629,14 +643,15 @@ int launch_solo(lbm_batch* b, int L, int i) {
       if (e == hipSuccess && rebase) e = launch_rebase(ra, st);
       if (e == hipSuccess && diag)
         e = launch_finalize(part, nblk, phase == PH_FORWARD ? kRedFwd : kRedAdj, ds, st);
-      if (e == hipSuccess) e = launch_advance(base, Q, st);
+      if (e == hipSuccess) e = launch_advance(base, n, st);
       if (e == hipSuccess && diag)
         e = hipMemcpyAsync(hs, ds, 4 * sizeof(double), hipMemcpyDeviceToHost, st);
       if (e == hipSuccess) e = hipEventRecord(ev, st);
       return e;
     });
     s.lane = L;
-    ln.launch += b->quantum;
+    ln.qsteps = n;
+    ln.launch += n;
     b->launches += n;
     b->node_updates += (long long)p->N * n;
     ln.busy = true;
@@ -692,6 +707,7 @@ int launch_solo(lbm_batch* b, int L, int i) {
     return e;
   });
   s.lane = L;
+  ln.qsteps = b->quantum;
   ln.launch += b->quantum;
   b->launches += n;
   b->node_updates += (long long)p->N * n;
@@ -731,6 +747,7 @@ int launch_persistent(lbm_batch* b, int L, int ntiles) {
     if (e == hipSuccess) e = hipEventRecord(ev, st);
     return e;
   });
+  ln.qsteps = b->quantum;
   ln.launch += b->quantum;
   b->launches += 1;
   for (int i = 0; i < b->max_slots; ++i)
@@ -814,6 +831,7 @@ int launch_quantum(lbm_batch* b, int L) {
     if (e == hipSuccess) e = hipEventRecord(ev, st);
     return e;
   });
+  ln.qsteps = b->quantum;
   ln.launch += b->quantum;
   b->launches += b->quantum;
   for (int i = 0; i < b->max_slots; ++i)
@@ -839,7 +857,7 @@ int complete_quantum(lbm_batch* b, int L) {
       s.status = LBM_EDEVICE;
       continue;
     }
-    s.steps = std::min(s.steps + b->quantum, s.p->d.max_steps);
+    s.steps = std::min(s.steps + ln.qsteps, s.p->d.max_steps);
     int rc = after_quantum(b, i, ln);
     if (rc) return rc;
   }

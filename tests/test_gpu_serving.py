@@ -177,3 +177,27 @@ def test_serving_trace_small():
         assert rb["J"] == rs["J"] and np.array_equal(rb["dJ"], rs["dJ"])
     print(f"[serving] batched {serving.summarize(res_b, mk_b)} back-to-back "
           f"{serving.summarize(res_s, mk_s)}", flush=True)
+
+
+def test_long_solo_quanta_equal_single_solves():
+    """Under OVERLAP a lone request too large for the latency lane runs on the
+    bandwidth lane up to its next residual check per host visit (here checks
+    every 1000 steps, cap 2750: quanta of 1000, 1000 and 750 steps) while a
+    small request moves on the latency lane: both results equal their single
+    solves bit for bit."""
+    big = W.heat_sink(64, 64, 64, Re=0.08 * 62 / ((0.6 - 0.5) / 3.0), tau=0.6, sigma=2.0,
+                      seed=931, name="big").replace(max_steps=2750, check_every=1000, tol=1e-7)
+    assert big.N // 256 >= 1024
+    small = small_requests()[0].replace(max_steps=2750, check_every=250, tol=1e-6)
+    reqs = [big, small]
+    refs = [alone(w) for w in reqs]
+    eng = serving.BatchEngine(True, W.OBJ_HEATSINK, budget_bytes=4 << 30, max_slots=4, quantum=Q,
+                              policy=lbm.LBM_BATCH_POLICY_OVERLAP, fill_tiles=512)
+    tickets = {eng.submit(big): 0, eng.submit(small): 1}
+    results = _drain(eng, tickets, reqs)
+    assert len(results) == 2
+    for i, w in enumerate(reqs):
+        _check_same(w, results[i], refs[i], refs[i][1])
+    st = eng.stats()
+    assert st["node_updates"] >= sum((results[i]["fwd_steps"] + results[i]["adj_steps"]) * w.N
+                                     for i, w in enumerate(reqs))

@@ -70,6 +70,9 @@ def parse():
                     help="Reynolds number of a pipe-bend workload (0: the workload's own)")
     ap.add_argument("--adjoint", default="discrete", choices=["discrete", "continuous"],
                     help="adjoint kind (the continuous variant is for the flow-only pipe bend)")
+    ap.add_argument("--max-steps", type=int, default=0,
+                    help="step cap of each forward and adjoint sweep (0: the workload's own, "
+                         "20000 for the heat sinks)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-fwd-steps", type=int, default=0,
                     help="oracle sample size in forward (and as many adjoint) steps (0: 300)")
@@ -568,6 +571,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     w = make_workload(args.workload, args.adjoint, args.re)
+    if args.max_steps > 0:
+        w = w.replace(max_steps=args.max_steps)
     prob = lbm.Problem(w, device="cuda:0")
     gamma = prob.gamma_tensor(w.gamma)
     stream = torch.cuda.current_stream()

@@ -95,10 +95,12 @@ def parse():
                          "per mode, so the default replays its first 128)")
     ap.add_argument("--serving-rate", type=float, default=0.0,
                     help="Poisson arrival rate in requests/s (0: the stream's default)")
-    ap.add_argument("--serving-policy", default="overlap", choices=["overlap", "srw", "all"],
+    ap.add_argument("--serving-policy", default="overlap",
+                    choices=["overlap", "overlap_fifo", "srw", "all"],
                     help="batch scheduling: two concurrent lanes, small requests beside the "
-                         "oldest one (overlap); shortest remaining work first (srw); every "
-                         "resident request every quantum (all)")
+                         "oldest one (overlap); the same lanes, small requests only beside "
+                         "larger ones that arrived after them (overlap_fifo); shortest "
+                         "remaining work first (srw); every resident request every quantum (all)")
     ap.add_argument("--serving-fill", type=int, default=512,
                     help="tiles of 256 nodes per launch the srw policy fills up to")
     ap.add_argument("--stability", action="store_true",
@@ -362,7 +364,8 @@ def serving_leg(n, rate, policy="srw", fill=512):
     warm = W.heat_sink(24, 14, 10, Re=20.0, tau=0.6, sigma=1.5,
                        name="warmup").replace(max_steps=500, check_every=250, tol=0.0)
     pol = {"srw": lbm.LBM_BATCH_POLICY_SRW, "all": lbm.LBM_BATCH_POLICY_ALL,
-           "overlap": lbm.LBM_BATCH_POLICY_OVERLAP}[policy]
+           "overlap": lbm.LBM_BATCH_POLICY_OVERLAP,
+           "overlap_fifo": lbm.LBM_BATCH_POLICY_OVERLAP_FIFO}[policy]
     eng = serving.BatchEngine(True, W.OBJ_HEATSINK, budget_bytes=W.SERVING_BUDGET_BYTES,
                               quantum=250, policy=pol, fill_tiles=fill)
     serving.serve(eng, [warm], [0.0])

@@ -399,6 +399,7 @@ int lbm_lattice(int32_t which, int32_t* e, double* w);
 #define LBM_BATCH_POLICY_ALL 0     /* one lane: every resident request            */
 #define LBM_BATCH_POLICY_SRW 1     /* one lane: shortest remaining work, filled    */
 #define LBM_BATCH_POLICY_OVERLAP 2 /* two concurrent lanes (default)               */
+#define LBM_BATCH_POLICY_OVERLAP_FIFO 3 /* two lanes, no request slowed by a later one */
 
 typedef struct lbm_batch lbm_batch_t;
 
@@ -443,7 +444,12 @@ int lbm_batch_bind_arena(lbm_batch_t* b, void* device_ptr, size_t bytes);
  * run concurrently): the latency lane takes requests of at most fill_tiles
  * tiles in arrival order, greedily up to fill_tiles; the bandwidth lane takes
  * the oldest remaining request and, if it is that small too, further small
- * ones up to fill_tiles.  Requests in no run set stay resident and paused.
+ * ones up to fill_tiles.  OVERLAP_FIFO: the lanes of OVERLAP, but the
+ * latency lane only takes requests that arrived before the oldest resident
+ * request too large for it, so no request is slowed by one that arrived
+ * after it (no worse than arrival order at the tail, small requests still
+ * running beside large ones).  Requests in no run set stay resident and
+ * paused.
  * The policy changes latency and throughput only, never a result.  Default
  * OVERLAP, fill 512.  LBM_EINVAL on an unknown policy or fill_tiles < 1,
  * LBM_ESTATE while a quantum is in flight. */
@@ -467,10 +473,10 @@ int lbm_batch_set_persistent(lbm_batch_t* b, int32_t max_tiles);
 int lbm_batch_submit(lbm_batch_t* b, const lbm_desc_t* desc, const uint8_t* mask,
                      const float* gamma_host, int64_t* ticket);
 /* Admit (uploads on `stream`, synchronised), start a quantum on every idle
- * lane, then wait until at least one lane's quantum has completed and do its
- * residual checks and phase moves.  Quanta of other lanes may still be in
- * flight on return.  active/queued (may be NULL) receive the resident
- * running requests and the queue length. */
+ * lane, then wait until at least one lane's quantum has completed, do its
+ * residual checks and phase moves and start that lane's next quantum.
+ * Quanta may still be in flight on return.  active/queued (may be NULL)
+ * receive the resident running requests and the queue length. */
 int lbm_batch_step(lbm_batch_t* b, void* stream, int32_t* active, int32_t* queued);
 /* State of a ticket; DONE/FAILED results are returned once and released. */
 int lbm_batch_poll(lbm_batch_t* b, int64_t ticket, lbm_batch_result_t* res, float* dJ_host,

@@ -33,12 +33,20 @@
 //            small ones.  A large request thus streams at nearly full HBM
 //            bandwidth in arrival order while small ones progress beside it in
 //            the bandwidth it leaves idle, instead of waiting behind it.
+//   OVERLAP_FIFO  the lanes of OVERLAP, but the latency lane only takes small
+//            slots that arrived before the oldest running slot too large for
+//            it.  Every request is then slowed only by requests that arrived
+//            before it (which plain arrival order would have run before it
+//            in full), so the latency tail is no worse than arrival order,
+//            while small requests still run beside a large one instead of
+//            after it.
 // A slot not in any run set keeps its state and its step count.
 
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -264,7 +272,10 @@ size_t lane_table_bytes(int max_slots, int max_tiles) {
 
 size_t request_bytes(const lbm_problem* p) { return layout_of(p).total + fields_bytes(p); }
 
-int lanes_used(const lbm_batch* b) { return b->policy == LBM_BATCH_POLICY_OVERLAP ? kLanes : 1; }
+bool two_lanes(int policy) {
+  return policy == LBM_BATCH_POLICY_OVERLAP || policy == LBM_BATCH_POLICY_OVERLAP_FIFO;
+}
+int lanes_used(const lbm_batch* b) { return two_lanes(b->policy) ? kLanes : 1; }
 
 bool running(const Slot& s) { return s.used && (s.phase == PH_FORWARD || s.phase == PH_ADJOINT); }
 
@@ -552,9 +563,15 @@ void choose_run_set(lbm_batch* b, int L) {
     for (auto& e : w) order.push_back(e.second);
     fill(order, true, 0);
   } else if (L == 0) {  // OVERLAP, latency lane: small slots in arrival order
+    // OVERLAP_FIFO: only those older than every running slot too large for
+    // this lane (held by a quantum in flight or not)
+    int64_t before = INT64_MAX;
+    if (b->policy == LBM_BATCH_POLICY_OVERLAP_FIFO)
+      for (int i = 0; i < b->max_slots; ++i)
+        if (running(b->slots[i]) && nblk(i) > F) before = std::min(before, b->slots[i].ticket);
     std::vector<int> small;
     for (int i : cand)
-      if (nblk(i) <= F) small.push_back(i);
+      if (nblk(i) <= F && b->slots[i].ticket < before) small.push_back(i);
     std::sort(small.begin(), small.end(), by_ticket);
     fill(small, true, 0);
   } else {  // OVERLAP, bandwidth lane: the oldest slot, then small ones if it is small
@@ -598,7 +615,7 @@ int launch_solo(lbm_batch* b, int L, int i) {
   const bool th = thermal_of(p);
   const int s0 = s.steps, cap = p->d.max_steps, chk = p->d.check_every;
   int n = std::min(b->quantum, cap - s0);
-  if (b->policy == LBM_BATCH_POLICY_OVERLAP && L == 1 && p->nblk > b->fill_tiles &&
+  if (two_lanes(b->policy) && L == 1 && p->nblk > b->fill_tiles &&
       p->nblk >= kDirectTiles) {
     // up to the next residual check (the check period and the step cap are
     // multiples of the quantum, so this is a whole number of quanta)
@@ -1001,7 +1018,8 @@ int lbm_batch_set_policy(lbm_batch_t* b, int32_t policy, int32_t fill_tiles) {
   last_error().clear();
   if (!b) return fail(LBM_EINVAL, "batch is NULL");
   if ((policy != LBM_BATCH_POLICY_ALL && policy != LBM_BATCH_POLICY_SRW &&
-       policy != LBM_BATCH_POLICY_OVERLAP) || fill_tiles < 1)
+       policy != LBM_BATCH_POLICY_OVERLAP && policy != LBM_BATCH_POLICY_OVERLAP_FIFO) ||
+      fill_tiles < 1)
     return fail(LBM_EINVAL, "bad policy or fill");
   for (const Lane& ln : b->lanes)
     if (ln.busy) return fail(LBM_ESTATE, "cannot change the policy while a quantum is in flight");
@@ -1077,6 +1095,11 @@ int lbm_batch_step(lbm_batch_t* b, void* stream, int32_t* active, int32_t* queue
       if (e == hipErrorNotReady) continue;
       HIPCHK(e);
       rc = complete_quantum(b, L);
+      if (rc) return rc;
+      // the lane's next quantum goes out now, not at the caller's next call:
+      // its stream would otherwise idle through the caller's own bookkeeping
+      choose_run_set(b, L);
+      rc = launch_quantum(b, L);
       if (rc) return rc;
       got = true;
     }

@@ -78,6 +78,7 @@ class lbm_batch_stats_t(ctypes.Structure):
 
 LBM_BATCH_QUEUED, LBM_BATCH_RUNNING, LBM_BATCH_DONE, LBM_BATCH_FAILED = 0, 1, 2, 3
 LBM_BATCH_POLICY_ALL, LBM_BATCH_POLICY_SRW, LBM_BATCH_POLICY_OVERLAP = 0, 1, 2
+LBM_BATCH_POLICY_OVERLAP_FIFO = 3
 
 EXPORTS = ("lbm_problem_create", "lbm_workspace_bytes", "lbm_bind_workspace",
            "lbm_bind_static_workspace", "lbm_forward_solve",

@@ -125,7 +125,8 @@ def test_batch_parameters_are_validated(lbm):
     lbm.lbm_batch_set_policy(b, lbm.LBM_BATCH_POLICY_ALL, 1)
     lbm.lbm_batch_set_policy(b, lbm.LBM_BATCH_POLICY_SRW, 512)
     lbm.lbm_batch_set_policy(b, lbm.LBM_BATCH_POLICY_OVERLAP, 512)
-    for policy, fill in [(3, 512), (-1, 512), (lbm.LBM_BATCH_POLICY_SRW, 0)]:
+    lbm.lbm_batch_set_policy(b, lbm.LBM_BATCH_POLICY_OVERLAP_FIFO, 512)
+    for policy, fill in [(4, 512), (-1, 512), (lbm.LBM_BATCH_POLICY_SRW, 0)]:
         with pytest.raises(lbm.LBMError) as e:
             lbm.lbm_batch_set_policy(b, policy, fill)
         assert e.value.code == lbm.LBM_EINVAL

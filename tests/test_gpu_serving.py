@@ -95,7 +95,8 @@ def test_batch_results_equal_single_solves(persistent_tiles):
                                          (lbm.LBM_BATCH_POLICY_SRW, 1),
                                          (lbm.LBM_BATCH_POLICY_SRW, 150),
                                          (lbm.LBM_BATCH_POLICY_OVERLAP, 1),
-                                         (lbm.LBM_BATCH_POLICY_OVERLAP, 20)])
+                                         (lbm.LBM_BATCH_POLICY_OVERLAP, 20),
+                                         (lbm.LBM_BATCH_POLICY_OVERLAP_FIFO, 20)])
 def test_policy_changes_no_result(policy, fill):
     """Whatever the run set of each quantum (all resident requests; one at a
     time; a few by shortest remaining work; two concurrent lanes, requests

@@ -5,6 +5,17 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+# Under pytest-xdist every worker process runs the OpenMP oracle: share the
+# cores out instead of giving each worker all of them (the oversubscribed
+# OpenMP teams spin against each other and the suite slows many times over).
+_workers = os.environ.get("PYTEST_XDIST_WORKER_COUNT")
+if _workers and "OMP_NUM_THREADS" not in os.environ:
+    try:
+        _cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        _cores = os.cpu_count() or 1
+    os.environ["OMP_NUM_THREADS"] = str(max(1, _cores // max(1, int(_workers))))
+
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (runs through the HIP library)")

@@ -70,6 +70,9 @@ def parse():
                     help="Reynolds number of a pipe-bend workload (0: the workload's own)")
     ap.add_argument("--adjoint", default="discrete", choices=["discrete", "continuous"],
                     help="adjoint kind (the continuous variant is for the flow-only pipe bend)")
+    ap.add_argument("--u-peak", type=float, default=0.0,
+                    help="peak inlet speed of the 160x80x40 heat sink (0: 0.1); tau follows "
+                         "from Re at that speed")
     ap.add_argument("--max-steps", type=int, default=0,
                     help="step cap of each forward and adjoint sweep (0: the workload's own, "
                          "20000 for the heat sinks)")
@@ -227,7 +230,7 @@ def counter_traffic(workload, kernel):
     return int((k["fetch_kib"] * c["fetch_scale"] + k["write_kib"] * c["write_scale"]) * 1024)
 
 
-def make_workload(name, adjoint="discrete", Re=0.0):
+def make_workload(name, adjoint="discrete", Re=0.0, u_peak=0.0):
     import workloads as W
     kind = 1 if adjoint == "continuous" else 0
     if name.startswith("pipe_bend_96"):
@@ -249,6 +252,9 @@ def make_workload(name, adjoint="discrete", Re=0.0):
     if name == "heat_sink_320x160x80_Re200":
         return out_of_cache_workload()
     Re = float(name.split("Re")[1])
+    if u_peak > 0:
+        return W.heat_sink(Re=Re, u_peak=u_peak,
+                           name=f"heat_sink_160x80x40_Re{Re:g}_u{u_peak:g}")
     return W.heat_sink(Re=Re)
 
 
@@ -573,7 +579,7 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    w = make_workload(args.workload, args.adjoint, args.re)
+    w = make_workload(args.workload, args.adjoint, args.re, args.u_peak)
     if args.max_steps > 0:
         w = w.replace(max_steps=args.max_steps)
     prob = lbm.Problem(w, device="cuda:0")

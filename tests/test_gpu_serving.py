@@ -202,3 +202,39 @@ def test_long_solo_quanta_equal_single_solves():
     st = eng.stats()
     assert st["node_updates"] >= sum((results[i]["fwd_steps"] + results[i]["adj_steps"]) * w.N
                                      for i, w in enumerate(reqs))
+
+
+def test_serving_requests_match_the_oracle():
+    """Requests of the serving stream itself (its 64x32x16 and 128x64x32
+    grids, with their drawn Re, tau and design fields), served together by
+    the batch engine for one 250-step quantum per sweep, give the FP64
+    oracle's J (1e-5) and dJ/dgamma over the design nodes (1e-4) after the
+    same steps."""
+    import oracle
+    from _parity import rel
+
+    picks = {}
+    for i in range(64):
+        w = W.serving_request(i)
+        key = (w.nx, w.ny, w.nz)
+        if key in ((64, 32, 16), (128, 64, 32)) and key not in picks:
+            picks[key] = w.replace(max_steps=Q, check_every=Q, tol=0.0)
+        if len(picks) == 2:
+            break
+    reqs = [picks[(64, 32, 16)], picks[(128, 64, 32)]]
+    eng = serving.BatchEngine(True, W.OBJ_HEATSINK, budget_bytes=4 << 30, max_slots=4, quantum=Q)
+    tickets = {eng.submit(w): i for i, w in enumerate(reqs)}
+    results = _drain(eng, tickets, reqs)
+    assert len(results) == 2
+    for i, w in enumerate(reqs):
+        r = results[i]
+        assert r["state"] == lbm.LBM_BATCH_DONE
+        assert (r["fwd_steps"], r["adj_steps"]) == (Q, Q)
+        ref = oracle.Oracle(w).solve(fwd_steps=Q, adj_steps=Q, tol=0.0, check_every=Q)
+        design = (w.mask.reshape(-1) & 7) == W.DESIGN
+        e_dJ = rel(r["dJ"][design], ref["dJ"][design])
+        e_J = abs(r["J"] - ref["J"]) / abs(ref["J"])
+        print(f"[serving] {w.name} tau {w.tau:.4f} Re {w.Re:.1f}: J {e_J:.2e}  dJ/dgamma {e_dJ:.2e}",
+              flush=True)
+        assert e_J <= 1e-5
+        assert e_dJ < 1e-4

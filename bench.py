@@ -352,7 +352,7 @@ def cpu_baseline(w, fwd_steps):
     return out
 
 
-def serving_leg(n, rate, policy="srw", fill=512):
+def serving_leg(n, rate, policy="overlap", fill=512):
     """Replay the first n requests of the serving stream (seeded Poisson
     arrivals) once through the continuous-batching engine and once as plain
     back-to-back solves; report latency percentiles and aggregate MLUPS of

@@ -105,7 +105,8 @@ def parse():
                          "larger ones that arrived after them (overlap_fifo); shortest "
                          "remaining work first (srw); every resident request every quantum (all)")
     ap.add_argument("--serving-fill", type=int, default=512,
-                    help="tiles of 256 nodes per launch the srw policy fills up to")
+                    help="tiles of 256 nodes per launch that the latency lane (overlap, "
+                         "overlap_fifo) or the srw policy fills up to")
     ap.add_argument("--stability", action="store_true",
                     help="run the adjoint stability sweep (3D pipe bend, discrete vs continuous "
                          "adjoint) and print its JSON object")

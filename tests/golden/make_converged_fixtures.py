@@ -20,6 +20,11 @@ repository root:
     python tests/golden/make_converged_fixtures.py heat_sink_128x64x32_Re200
     python tests/golden/make_converged_fixtures.py heat_sink_128x64x32_Re200 --fd 32 \
         --fd-steps 12000 --fd-only
+    python tests/golden/make_converged_fixtures.py pipe_bend_96 --sample 65536 --tol 1e-9
+
+With --sample K the fields are stored at K seeded non-wall nodes and dJ/dgamma
+at K seeded design nodes (their indices beside them) instead of at every
+node, which keeps the 96^3 pipe bend's fixture small.
 
 The warm-started solves of some cells excite the slow thermal modes and
 need about 10000 steps to settle; once settled, the two FP64 iterations only
@@ -47,6 +52,7 @@ import workloads as W  # noqa: E402
 CONFIGS = {
     "heat_sink_160x80x40_Re200": lambda: W.heat_sink(Re=200.0),
     "heat_sink_128x64x32_Re200": W.differentiable_case,
+    "pipe_bend_96": W.pipe_bend_3d,
 }
 TOL = 1e-10          # relative change of the monitors over 1000 steps
 MAX_STEPS = 400000
@@ -70,6 +76,16 @@ def fd_cells(w, n: int) -> np.ndarray:
     return np.sort(rng.choice(design, size=n, replace=False))
 
 
+def sample_nodes(w, k: int):
+    """K seeded non-wall nodes and K seeded design nodes (sorted)."""
+    kinds = w.mask.reshape(-1) & 7
+    rng = np.random.default_rng(W.SEED_BASE + 96)
+    live = np.flatnonzero(kinds < W.WALL)
+    design = np.flatnonzero(kinds == W.DESIGN)
+    return (np.sort(rng.choice(live, size=min(k, live.size), replace=False)),
+            np.sort(rng.choice(design, size=min(k, design.size), replace=False)))
+
+
 def log(msg):
     print(f"[fixture] {msg}", flush=True)
 
@@ -80,6 +96,10 @@ def main():
     ap.add_argument("--fd", type=int, default=0, help="design cells checked by central differences")
     ap.add_argument("--fd-steps", type=int, default=0,
                     help="steps of each warm-started difference solve (0: twice the forward's)")
+    ap.add_argument("--tol", type=float, default=TOL,
+                    help="relative change of the monitors over 1000 steps that ends each sweep")
+    ap.add_argument("--sample", type=int, default=0,
+                    help="store the fields and dJ/dgamma at this many seeded nodes only")
     ap.add_argument("--fd-only", action="store_true",
                     help="add the differences to the stored fixture (the forward is re-solved "
                          "for the warm start, the adjoint is not)")
@@ -87,7 +107,7 @@ def main():
     w = CONFIGS[args.config]()
     o = oracle.Oracle(w)
     t0 = time.time()
-    fw = o.forward(max_steps=MAX_STEPS, tol=TOL, check_every=1000)
+    fw = o.forward(max_steps=MAX_STEPS, tol=args.tol, check_every=1000)
     log(f"{args.config}: forward {fw['steps']} steps, status {fw['status']}, residuals {fw['res']}, "
         f"{time.time() - t0:.0f} s")
     assert fw["status"] == 0, "forward did not converge"
@@ -103,7 +123,7 @@ def main():
     else:
         rho, u, T = o.macro(f, g)
         t1 = time.time()
-        ad = o.adjoint(f, g, max_steps=MAX_STEPS, tol=TOL, check_every=1000)
+        ad = o.adjoint(f, g, max_steps=MAX_STEPS, tol=args.tol, check_every=1000)
         log(f"adjoint {ad['steps']} steps, status {ad['status']}, residuals {ad['res']}, "
             f"{time.time() - t1:.0f} s")
         assert ad["status"] == 0, "adjoint did not converge"
@@ -113,10 +133,16 @@ def main():
                    dJ=dJ.astype(np.float32), J=np.float64(J),
                    fwd_steps=np.int64(fw["steps"]), adj_steps=np.int64(ad["steps"]),
                    fwd_res=np.asarray(fw["res"], dtype=np.float64),
-                   adj_res=np.asarray(ad["res"], dtype=np.float64), tol=np.float64(TOL),
+                   adj_res=np.asarray(ad["res"], dtype=np.float64), tol=np.float64(args.tol),
                    name=np.str_(w.name), grid=np.array([w.nx, w.ny, w.nz], dtype=np.int64),
                    tau=np.float64(w.tau), Re=np.float64(w.Re), seed=np.int64(w.seed),
                    inputs_sha256=np.str_(digest(w)))
+        if args.sample > 0:
+            live, design = sample_nodes(w, args.sample)
+            out.update(sample=live.astype(np.int64), drho=out["drho"][live],
+                       u=out["u"][:, live].copy(),
+                       T=out["T"][live] if out["T"].size else out["T"],
+                       dJ_sample=design.astype(np.int64), dJ=out["dJ"][design])
     if args.fd > 0:
         cells = fd_cells(w, args.fd)
         steps = args.fd_steps or 2 * fw["steps"]
